@@ -1,0 +1,480 @@
+"""Pins of the FP64 reference against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a closed form,
+an exact identity, a library routine, a different algorithm, or brute force.
+They are CPU-only.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_14634_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _body_scene(off, centre=(0.0, 0.0, 0.0), velocity=(0.0, 0.0, 0.0), mass=1.0, radius=0.05, **kw):
+    return scenes.single_body(off, centre=centre, velocity=velocity, mass=mass, radius=radius, **kw)
+
+
+def _run(orc, sc, n_substeps=1, accel=None, **pkw):
+    p = orc.params_for(sc, **pkw)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v, mx = orc.substep(p, rest, sc.x, sc.v, accel=accel, n_substeps=n_substeps)
+    return x, v, mx, p, rest
+
+
+# --------------------------------------------------------------------------
+# integration step (Alg. 1, first loop): discrete free fall closed form
+# --------------------------------------------------------------------------
+
+def test_free_fall_matches_symplectic_euler_closed_form(orc):
+    g = np.array([0.3, -0.2, -9.81])
+    v0 = np.array([0.5, 0.1, 2.0])
+    sc = _body_scene(scenes.lattice_box(4, 3, 5, 0.1), centre=(0.1, -0.2, 3.0), velocity=v0,
+                     gravity=tuple(g), planes=())
+    n = 37
+    v0 = sc.v[:, 0].astype(np.float64)        # the state is stored in FP32
+    x, v, mx, p, _ = _run(orc, sc, n_substeps=n)
+    h = p.h
+    # v_n = v0 + n h g ; x_n = x0 + n h v0 + h^2 g n(n+1)/2
+    v_ref = v0 + n * h * g
+    x_ref = sc.x.astype(np.float64) + (n * h * v0 + h * h * g * n * (n + 1) / 2.0)[:, None]
+    assert mx == 0
+    np.testing.assert_allclose(v, np.repeat(v_ref[:, None], sc.n, axis=1), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(x, x_ref, rtol=1e-12, atol=1e-12)
+
+
+def test_constant_velocity_without_gravity(orc):
+    v0 = np.array([-1.5, 0.25, 0.75])
+    sc = _body_scene(scenes.lattice_box(3, 3, 3, 0.1), centre=(0.0, 0.0, 1.0), velocity=v0,
+                     gravity=(0.0, 0.0, 0.0), planes=())
+    v0 = sc.v[:, 0].astype(np.float64)
+    x, v, _, p, _ = _run(orc, sc, n_substeps=25)
+    np.testing.assert_allclose(x, sc.x + (25 * p.h * v0)[:, None], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(v, np.repeat(v0[:, None], sc.n, axis=1), rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# ground contact and friction (constraint (1)) on a single particle
+# --------------------------------------------------------------------------
+
+def _particle(z, vt=(0.0, 0.0), r=0.05, mu=0.0, iterations=1):
+    return _body_scene(np.zeros((3, 1)), centre=(0.0, 0.0, z), velocity=(vt[0], vt[1], 0.0),
+                       radius=r, gravity=(0.0, 0.0, 0.0), mu=mu, iterations=iterations)
+
+
+def test_ground_pushes_out_exactly_the_penetration(orc):
+    r = 0.05
+    sc = _particle(r - 1e-3)
+    pen = r - float(sc.x[2, 0])           # penetration of the FP32-stored start
+    x, v, _, p, _ = _run(orc, sc)
+    assert x[2, 0] == pytest.approx(r, abs=1e-15)
+    assert v[2, 0] == pytest.approx(pen / p.h, rel=1e-12)
+    assert x[0, 0] == 0.0 and x[1, 0] == 0.0
+
+
+@pytest.mark.parametrize("speed_scale", [0.5, 3.0])
+def test_ground_friction_static_and_kinetic(orc, speed_scale):
+    r, mu = 0.05, 0.4
+    sc0 = _particle(r - 1e-3, mu=mu)
+    pen = r - float(sc0.x[2, 0])
+    h = sc0.dt_frame / sc0.substeps
+    ut = speed_scale * mu * pen          # tangential displacement over the substep
+    sc = _particle(r - 1e-3, vt=(ut / h * 0.6, ut / h * 0.8), mu=mu)
+    x, v, _, p, _ = _run(orc, sc)
+    u = h * sc.v[:2, 0].astype(np.float64)
+    ut = float(np.linalg.norm(u))
+    moved = x[:2, 0] - sc.x[:2, 0].astype(np.float64)
+    if ut <= mu * pen:       # static: the whole tangential displacement is removed
+        np.testing.assert_allclose(moved, 0.0, atol=1e-15)
+    else:                    # kinetic: it shrinks by mu * pen
+        np.testing.assert_allclose(moved, u * (1.0 - mu * pen / ut), rtol=1e-12, atol=1e-16)
+    assert x[2, 0] == pytest.approx(r, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# particle-particle contact (constraint (2)): mass split and momentum
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m1,m2", [(1.0, 1.0), (1.0, 3.0)])
+def test_pair_contact_splits_penetration_by_inverse_mass(orc, m1, m2):
+    r, pen = 0.05, 2e-3
+    d = 2 * r - pen
+    sc = scenes.from_bodies([np.array([[-d / 2], [0.0], [0.0]]), np.array([[d / 2], [0.0], [0.0]])],
+                            [np.zeros(3), np.zeros(3)], [m1, m2], radius=r,
+                            gravity=(0.0, 0.0, 0.0), planes=(), iterations=1)
+    x, v, mx, _, _ = _run(orc, sc)
+    assert mx == 1
+    pen = 2 * r - (float(sc.x[0, 1]) - float(sc.x[0, 0]))
+    w1, w2 = 1.0 / m1, 1.0 / m2
+    assert x[0, 0] - sc.x[0, 0] == pytest.approx(-pen * w1 / (w1 + w2), rel=1e-9)
+    assert x[0, 1] - sc.x[0, 1] == pytest.approx(pen * w2 / (w1 + w2), rel=1e-9)
+    assert m1 * v[0, 0] + m2 * v[0, 1] == pytest.approx(0.0, abs=1e-12)
+
+
+def test_symmetric_averaging_conserves_total_momentum(orc):
+    rng = np.random.default_rng(7)
+    r = 0.05
+    off = scenes.lattice_box(3, 3, 3, 2 * r)
+    parts, vels, masses = [], [], []
+    for k in range(6):
+        parts.append(scenes.random_rotation(rng) @ off + rng.uniform(-0.25, 0.25, size=(3, 1)))
+        vels.append(rng.normal(0, 1.0, size=3))
+        masses.append(rng.uniform(0.5, 2.0))
+    for mu in (0.0, 0.4):
+        sc = scenes.from_bodies(parts, vels, masses, radius=r, gravity=(0.0, 0.0, 0.0), planes=(), mu=mu)
+        x, v, mx, _, rest = _run(orc, sc, n_substeps=20)
+        assert mx >= 2
+        P0 = (sc.v.astype(np.float64) * rest.mass).sum(axis=1)
+        P1 = (v * rest.mass).sum(axis=1)
+        np.testing.assert_allclose(P1, P0, rtol=0, atol=1e-12 * np.abs(P0).max())
+
+
+# --------------------------------------------------------------------------
+# shape matching: polar decomposition (Mueller et al. 2005)
+# --------------------------------------------------------------------------
+
+def _higham_polar(A):
+    """Newton iteration X <- (X + X^-T)/2 (Higham 1986); orthogonal polar factor."""
+    X = A.copy()
+    for _ in range(100):
+        Xn = 0.5 * (X + np.linalg.inv(X).T)
+        if np.abs(Xn - X).max() < 1e-15:
+            return Xn
+        X = Xn
+    return X
+
+
+def _kabsch(A):
+    U, s, Vt = np.linalg.svd(A)
+    d = np.sign(np.linalg.det(U @ Vt))
+    return U @ np.diag([1.0, 1.0, d]) @ Vt
+
+
+def test_polar_recovers_the_rotation_of_a_rigid_motion(orc):
+    rng = np.random.default_rng(3)
+    q = scenes.lattice_box(4, 3, 2, 0.1)
+    m = rng.uniform(0.5, 2.0, size=q.shape[1])
+    q = q - (q * m).sum(axis=1, keepdims=True) / m.sum()
+    for _ in range(20):
+        R0 = scenes.random_rotation(rng)
+        x = R0 @ q + rng.normal(size=(3, 1))
+        c = (x * m).sum(axis=1) / m.sum()
+        A = ((x - c[:, None]) * m) @ q.T
+        np.testing.assert_allclose(orc.polar(A), R0, atol=1e-13)
+
+
+def test_polar_matches_newton_polar_and_library_svd(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(200):
+        A = rng.normal(size=(3, 3))
+        R = orc.polar(A)
+        np.testing.assert_allclose(R.T @ R, np.eye(3), atol=1e-13)
+        assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-13)
+        np.testing.assert_allclose(R, _kabsch(A), atol=1e-10)
+        if np.linalg.det(A) > 0:
+            np.testing.assert_allclose(R, _higham_polar(A), atol=1e-10)
+        S = R.T @ A                          # symmetric at the optimum
+        np.testing.assert_allclose(S, S.T, atol=1e-12)
+
+
+def test_polar_maximises_trace_over_rotations(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        A = rng.normal(size=(3, 3))
+        if np.linalg.det(A) > 0:
+            A[:, 0] *= -1.0                  # reflections: optimum is not the polar factor
+        R = orc.polar(A)
+        best = np.trace(R.T @ A)
+        for _ in range(200):
+            Q = scenes.random_rotation(rng)
+            assert np.trace(Q.T @ A) <= best + 1e-12
+
+
+def test_polar_degenerate_ranks(orc):
+    assert np.allclose(orc.polar(np.zeros((3, 3))), np.eye(3))
+    rng = np.random.default_rng(6)
+    a, b = rng.normal(size=3), rng.normal(size=3)
+    A2 = np.outer(a, rng.normal(size=3)) + np.outer(b, rng.normal(size=3))   # rank 2: unique
+    np.testing.assert_allclose(orc.polar(A2), _kabsch(A2), atol=1e-10)
+    A1 = np.outer(a, b)                                                      # rank 1: R b ∥ a
+    R1 = orc.polar(A1)
+    np.testing.assert_allclose(R1.T @ R1, np.eye(3), atol=1e-13)
+    np.testing.assert_allclose(R1 @ b / np.linalg.norm(b), a / np.linalg.norm(a), atol=1e-12)
+
+
+def test_pinv_sym3_matches_library(orc):
+    rng = np.random.default_rng(8)
+    for rank in (3, 2, 1, 0):
+        for _ in range(10):
+            B = rng.normal(size=(3, rank))
+            S = B @ B.T
+            np.testing.assert_allclose(orc.pinv_sym3(S), np.linalg.pinv(S, rcond=1e-10, hermitian=True),
+                                       atol=1e-9 * max(1.0, np.abs(np.linalg.pinv(S)).max()))
+
+
+def test_rigid_body_at_its_goal_does_not_move(orc):
+    rng = np.random.default_rng(9)
+    off = scenes.lattice_box(4, 2, 3, 0.1)
+    sc = _body_scene(off, centre=(0.0, 0.0, 1.0), gravity=(0.0, 0.0, 0.0), planes=())
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    R0 = scenes.random_rotation(rng)
+    x0 = R0 @ rest.q + np.array([[0.3], [-0.1], [0.7]])
+    p = orc.params_for(sc)
+    x, v, _ = orc.substep(p, rest, x0, np.zeros_like(x0))
+    np.testing.assert_allclose(x, x0, atol=1e-14)
+    np.testing.assert_allclose(v, 0.0, atol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# momentum conservation constraint (Eqs. (4)-(5)) on arbitrary states
+# --------------------------------------------------------------------------
+
+def _mom(m, x, v):
+    c = (m[:, None] * x).sum(axis=0) / m.sum()
+    P = (m[:, None] * v).sum(axis=0)
+    L = (m[:, None] * np.cross(x - c, v)).sum(axis=0)
+    return c, P, L
+
+
+@pytest.mark.parametrize("flags", [0, 2, 4])
+def test_momentum_constraint_restores_pre_shape_matching_momentum(orc, flags):
+    rng = np.random.default_rng(10 + flags)
+    n, h = 17, 1e-3
+    m = rng.uniform(0.2, 2.0, size=n)
+    xb, vb = rng.normal(size=(n, 3)), rng.normal(size=(n, 3))
+    xa, va = xb + 0.1 * rng.normal(size=(n, 3)), vb + rng.normal(size=(n, 3))
+    x, v = orc.enforce_momentum(m, xb, vb, xa, va, h, flags)
+    _, Pb, Lb = _mom(m, xb, vb)
+    ca, Pa, La = _mom(m, xa, va)
+    P = (m[:, None] * v).sum(axis=0)
+    L = (m[:, None] * np.cross(xa - ca, v)).sum(axis=0)   # about the corrected state's r
+    np.testing.assert_allclose(P, Pa if flags & 2 else Pb, atol=1e-12)
+    np.testing.assert_allclose(L, La if flags & 4 else Lb, atol=1e-12)
+    # the correction is one rigid velocity field dv - w x r, applied to x times dt
+    dv = v - va
+    np.testing.assert_allclose(x - xa, h * dv, atol=1e-15)
+    r = xa - ca
+    Amat = np.zeros((3 * n, 6))
+    for i in range(n):
+        Amat[3 * i:3 * i + 3, :3] = np.eye(3)
+        rx, ry, rz = r[i]
+        Amat[3 * i:3 * i + 3, 3:] = np.array([[0, rz, -ry], [-rz, 0, rx], [ry, -rx, 0]])  # -w x r
+    sol, res, *_ = np.linalg.lstsq(Amat, dv.ravel(), rcond=None)
+    np.testing.assert_allclose(Amat @ sol, dv.ravel(), atol=1e-12)
+
+
+def test_free_spin_keeps_angular_momentum_only_with_the_constraint(orc):
+    r = 0.05
+    off = scenes.lattice_box(4, 4, 4, 2 * r)
+    w0 = np.array([1.0, 2.0, -3.0])
+    v = np.cross(w0, off.T).T + np.array([[0.3], [0.0], [0.1]])
+    res = {}
+    for flags in (0, orc.NO_ANG_MOM):
+        sc = _body_scene(off, centre=(0.1, 0.2, 0.3), mass=0.5, radius=r, gravity=(0.0, 0.0, 0.0), planes=())
+        sc.v[:] = v
+        x0, v0 = sc.x.astype(np.float64), sc.v.astype(np.float64)
+        x1, v1, _, p, rest = _run(orc, sc, flags=flags)
+        _, P0, L0 = _mom(rest.mass, x0.T, v0.T)
+        _, P1, L1 = _mom(rest.mass, x1.T, v1.T)
+        res[flags] = np.abs(L1 - L0).max() / np.abs(L0).max()
+        np.testing.assert_allclose(P1, P0, atol=1e-13)
+        d0 = np.linalg.norm(x0[:, :, None] - x0[:, None, :], axis=0)
+        d1 = np.linalg.norm(x1[:, :, None] - x1[:, None, :], axis=0)
+        np.testing.assert_allclose(d1, d0, atol=1e-9)      # rigid: pairwise distances kept
+    # with the constraint the residual is far below the drift it removes
+    assert res[0] < 1e-9
+    assert res[orc.NO_ANG_MOM] > 1e-6
+
+
+# --------------------------------------------------------------------------
+# velocity update (Sec. III-B): V_i = (X_i - X_init)/dt holds as an invariant
+# --------------------------------------------------------------------------
+
+def test_incremental_velocity_equals_position_difference(orc):
+    sc = scenes.drop_cubes(seed=1)
+    p = orc.params_for(sc)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v, _ = orc.substep(p, rest, sc.x, sc.v, n_substeps=4 * 150)   # first cubes have landed
+    assert (x[2] < sc.radius).any()
+    x1, v1, _ = orc.substep(p, rest, x, v)
+    np.testing.assert_allclose(v1 * p.h, x1 - x, rtol=0, atol=1e-9 * p.h * np.abs(v1).max())
+
+
+def test_resting_cube_stays_at_rest(orc):
+    r = 0.05
+    sc = _body_scene(scenes.lattice_box(4, 4, 4, 2 * r), centre=(0.0, 0.0, 0.15 + r), radius=r)
+    p = orc.params_for(sc)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    zs = []
+    for _ in range(20):
+        x, v, _ = orc.substep(p, rest, x, v, n_substeps=200)
+        zs.append(x[2].mean())
+    assert max(zs) - min(zs) < 1e-9                 # no secular drift
+    assert abs(zs[-1] - (0.15 + r)) < 0.01 * r      # penetration well below r
+    assert np.abs(v).max() <= p.h * 9.81
+
+
+# --------------------------------------------------------------------------
+# neighbour search: brute force over all pairs, and the index structure
+# --------------------------------------------------------------------------
+
+def _brute_force_lists(xt32, body, rs):
+    n = xt32.shape[1]
+    r2 = np.float32(rs * rs)
+    out = []
+    for i in range(n):
+        d = xt32 - xt32[:, i:i + 1]                       # float32 subtraction
+        s = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]     # float32, no fused ops
+        ok = (s < r2) & (body != body[i])
+        ok[i] = False
+        out.append(np.nonzero(ok)[0].astype(np.uint32))
+    return out
+
+
+def _random_cloud(rng, n, n_bodies, extent):
+    x = rng.uniform(-extent, extent, size=(3, n)).astype(np.float32)
+    body = np.sort(rng.integers(0, n_bodies, size=n)).astype(np.int32)
+    return x, body
+
+
+@pytest.mark.parametrize("case", ["cloud", "lattice", "pile"])
+def test_neighbour_lists_equal_brute_force(orc, case):
+    rng = np.random.default_rng(11)
+    r = 0.01
+    if case == "cloud":
+        xt, body = _random_cloud(rng, 1500, 40, 0.12)
+    elif case == "lattice":   # exact lattice spacing 2r: touching pairs sit on the predicate edge
+        off = scenes.lattice_box(6, 6, 6, 2 * r)
+        x = np.concatenate([off, off + np.array([[12 * r], [0.0], [0.0]]),
+                            off + np.array([[6 * r], [11 * r], [1e-3]])], axis=1)
+        xt = x.astype(np.float32)
+        body = np.repeat(np.arange(3, dtype=np.int32), off.shape[1])
+    else:
+        sc = scenes.dense_pile(seed=2, n_bodies=40, half_width=0.3, gap_frac=-4.0)
+        xt, body = sc.x, sc.body_of_particle()
+    for bits in (10, 14):
+        p = orc.make_params(1e-3, 1, r, hash_bits=bits, nbr_cap=64)
+        idx = orc.index(p, body, xt)
+        ref = _brute_force_lists(xt, body, 2 * r)
+        assert idx["max_count"] == max(len(a) for a in ref)
+        assert idx["max_count"] <= 64
+        for i in range(xt.shape[1]):
+            c = int(idx["nbr_count"][i])
+            np.testing.assert_array_equal(idx["nbr"][i, :c], ref[i])
+    assert sum(len(a) for a in ref) > 0
+
+
+def test_sorted_order_and_cell_tables(orc):
+    rng = np.random.default_rng(12)
+    xt, body = _random_cloud(rng, 3000, 50, 0.3)
+    p = orc.make_params(1e-3, 1, 0.01, hash_bits=11)
+    idx = orc.index(p, body, xt)
+    key = idx["key"]
+    assert key.max() < (1 << 11)
+    order = np.lexsort((np.arange(xt.shape[1]), key))      # by key, ties by id
+    np.testing.assert_array_equal(idx["sorted_id"], order)
+    cnt = np.bincount(key, minlength=1 << 11).astype(np.uint32)
+    np.testing.assert_array_equal(idx["cell_count"], cnt)
+    np.testing.assert_array_equal(idx["cell_start"], (np.cumsum(cnt) - cnt).astype(np.uint32))
+
+
+def test_cell_keys_hand_computed(orc):
+    # cell edge 1 (inverse exact), origin 0: the cell of (a+0.5, b+0.5, c+0.5) is (a, b, c)
+    p = orc.make_params(1e-3, 1, 0.25, cell_size=1.0, hash_bits=10)
+    pts = np.array([
+        [0.5, 0.5, 0.5],      # (0,0,0) -> 0
+        [1.5, 0.5, 0.5],      # (1,0,0) -> bit 0
+        [0.5, 1.5, 0.5],      # (0,1,0) -> bit 1
+        [0.5, 0.5, 1.5],      # (0,0,1) -> bit 2
+        [2.5, 0.5, 0.5],      # (2,0,0) -> bit 3
+        [3.5, 2.5, 1.5],      # (3,2,1) -> bits 0,3 | 4 | 2 = 29
+        [-0.5, 0.5, 0.5],     # (-1,0,0) wraps to 1023: x bits at 0,3,6,9 -> 585 (low 10 bits)
+        [1024.5, 0.5, 0.5],   # 1024 wraps to 0 -> 0
+        [1e30, 0.5, 0.5],     # clamped to 2^24, a multiple of 1024 -> 0
+    ], dtype=np.float32).T
+    np.testing.assert_array_equal(orc.cell_keys(p, pts), [0, 1, 2, 4, 8, 29, 585, 0, 0])
+
+
+def test_predict32_is_the_fp32_recipe(orc):
+    rng = np.random.default_rng(13)
+    x = rng.uniform(-3, 3, size=(3, 1000)).astype(np.float32)
+    v = rng.normal(size=(3, 1000)).astype(np.float32)
+    a = rng.normal(size=(3, 1000)).astype(np.float32)
+    p = orc.make_params(1.0 / 960.0, 1, 0.01, gravity=(0.1, -0.2, -9.81))
+    xt = orc.predict32(p, x, v, a)
+    h = np.float32(1.0 / 960.0)
+    g = np.array([0.1, -0.2, -9.81], dtype=np.float32)[:, None]
+    vt = v + h * (g + a)                       # float32 ops, each rounded
+    np.testing.assert_array_equal(xt, x + h * vt)
+    # the FP32 prediction is within FP32 rounding of the FP64 one
+    x64 = x.astype(np.float64) + (1.0 / 960.0) * (v + (1.0 / 960.0) * (g.astype(np.float64) + a))
+    assert np.abs(xt - x64).max() < 4 * np.finfo(np.float32).eps * 4
+
+
+# --------------------------------------------------------------------------
+# paper Tests 1-3 (Table I closed forms, Table II parameters)
+# --------------------------------------------------------------------------
+
+def _paper_box(golden, mu, gravity):
+    r = golden["not_in_paper"]["sphere_radius_m"]
+    n = golden["spheres_per_axis"]
+    off = scenes.lattice_box(n, n, n, 2 * r)
+    half = (n - 1) * r
+    return _body_scene(off, centre=(0.0, 0.0, half + r), mass=golden["box_mass_kg"] / n ** 3, radius=r,
+                       dt_frame=1.0 / golden["frame_rate_hz"], substeps=golden["substeps"],
+                       iterations=golden["iterations"], mu=mu, gravity=gravity)
+
+
+def _load_golden():
+    with open(os.path.join(GOLDEN, "paper_tests_1_3.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("test_id", [1, 2, 3])
+def test_paper_closed_forms_tests_1_to_3(orc, test_id):
+    gd = _load_golden()
+    g = gd["not_in_paper"]["g_m_per_s2"]
+    M = gd["box_mass_kg"]
+    t_end = 2.0
+    frames = int(round(t_end * gd["frame_rate_hz"]))
+    if test_id == 3:
+        th = gd["slope_angle_test_3_rad"]
+        sc = _paper_box(gd, gd["mu_tests_1_3"], (g * math.sin(th), 0.0, -g * math.cos(th)))
+    else:
+        mu = gd["mu_tests_1_3"] if test_id == 1 else gd["mu_test_2"]
+        sc = _paper_box(gd, mu, (0.0, 0.0, -g))
+    p = orc.params_for(sc)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    lam = (rest.mass * (rest.q[0] ** 2 + rest.q[1] ** 2)).sum()     # discrete I_zz
+    for _ in range(frames):
+        acc = np.zeros_like(x)
+        if test_id == 1:
+            acc[0] = gd["force_test_1_N"] / M                          # force at the centre of mass
+        elif test_id == 2:
+            c = (x * rest.mass).sum(axis=1) / M
+            alpha = gd["torque_test_2_Nm"] / lam                       # a_p = alpha z x r_p
+            acc[0] = -alpha * (x[1] - c[1])
+            acc[1] = alpha * (x[0] - c[0])
+        x, v, _ = orc.substep(p, rest, x, v, accel=acc, n_substeps=sc.substeps)
+    c = (x * rest.mass).sum(axis=1) / M
+    if test_id == 1:
+        ref = 0.5 * (gd["force_test_1_N"] - gd["mu_tests_1_3"] * M * g) / M * t_end ** 2
+        assert c[0] == pytest.approx(ref, rel=0.03)
+    elif test_id == 3:
+        th = gd["slope_angle_test_3_rad"]
+        ref = 0.5 * (g * math.sin(th) - gd["mu_tests_1_3"] * g * math.cos(th)) * t_end ** 2
+        assert c[0] == pytest.approx(ref, rel=0.05)
+    else:
+        A = ((x - c[:, None]) * rest.mass) @ rest.q.T
+        R = orc.polar(A)
+        theta = math.atan2(R[1, 0], R[0, 0])
+        ref = 0.5 * gd["torque_test_2_Nm"] / lam * t_end ** 2
+        assert theta == pytest.approx(ref, rel=0.03)
+        assert abs(c[0]) < 1e-6 and abs(c[1]) < 1e-6
