@@ -1,0 +1,225 @@
+/*
+ * pbdr.h -- C ABI of the MI355X (gfx950) PBD-R rigid-body solver.
+ *
+ * PBD-R is the position-based dynamics formulation of "Physically Accurate
+ * Rigid-Body Dynamics in Particle-Based Simulation" (arXiv 2603.14634): rigid
+ * bodies are groups of equal-radius spheres ("object groups", Sec. III-A);
+ * each substep predicts positions, then runs K Jacobi iterations of ground
+ * contact, particle-particle contact between different groups, and shape
+ * matching (Alg. 1), with the paper's incremental velocity update (Sec. III-B,
+ * Eqs. (1)-(3)) and momentum conservation constraint (Sec. III-C, Eqs. (4)-(5)).
+ *
+ * Conventions
+ *  - Units are SI.  Particle arrays are structure-of-arrays FP32: a "[3][N]"
+ *    array holds all x components, then all y, then all z.
+ *  - Particles are grouped by body: body b owns particles
+ *    body_start[b] .. body_start[b+1]-1 (bodies contiguous and non-empty).
+ *  - Device memory is owned by the caller.  A scene lives entirely inside one
+ *    device workspace of pbdr_scene_bytes() bytes handed to pbdr_scene_create;
+ *    the library never allocates or frees device memory.  The library owns only
+ *    the opaque host-side pbdr_scene, freed by pbdr_scene_destroy (which does
+ *    not touch the workspace).
+ *  - All device work is enqueued on the hipStream_t given at creation (NULL
+ *    means the null stream).  Calls that return results to the host
+ *    synchronise that stream.
+ *  - Every call returns a pbdr_status.  Invalid arguments are rejected before
+ *    any device work is enqueued.  Conditions found on the device (a neighbour
+ *    list over capacity, a non-finite state) are latched in the workspace and
+ *    reported by the next call that synchronises (pbdr_scene_read_*,
+ *    pbdr_scene_check).  pbdr_last_error() gives a message for the calling
+ *    thread's last failure.
+ *  - A scene is not thread-safe; distinct scenes may be used from distinct
+ *    threads.
+ */
+#ifndef PBDR_H
+#define PBDR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PBDR_ABI_VERSION 1
+#define PBDR_MAX_PLANES 8
+#define PBDR_MAX_BODY_PARTICLES 1024
+
+typedef enum {
+    PBDR_OK = 0,
+    PBDR_ERR_INVALID_ARG = -1, /* bad pointer, size, body partition or parameter   */
+    PBDR_ERR_WORKSPACE = -2,   /* workspace too small or misaligned (256 B)         */
+    PBDR_ERR_DEVICE = -3,      /* a HIP runtime call failed                          */
+    PBDR_ERR_CAPACITY = -4,    /* a neighbour list exceeded nbr_cap (lists truncated)*/
+    PBDR_ERR_NONFINITE = -5,   /* a position or velocity became NaN/Inf              */
+    PBDR_ERR_STATE = -6        /* call not valid in the scene's current state        */
+} pbdr_status;
+
+/* pbdr_params.flags */
+#define PBDR_FLAG_STD_VELOCITY 0x1u  /* standard PBD velocity (X_{i+1}-X_init)/dt, Sec. III-A */
+#define PBDR_FLAG_NO_LIN_MOM 0x2u    /* drop the linear momentum correction, Eq. (4)   */
+#define PBDR_FLAG_NO_ANG_MOM 0x4u    /* drop the angular momentum correction, Eq. (5)  */
+#define PBDR_FLAG_NO_GRAPH 0x10u     /* enqueue kernels directly instead of replaying a
+                                        captured HIP graph per frame                    */
+#define PBDR_PP_AVG_MAX (0u << 8)    /* pair correction / max(n_p, n_q)  (default)      */
+#define PBDR_PP_AVG_OWN (1u << 8)    /* pair correction / n_p                           */
+#define PBDR_PP_AVG_NONE (2u << 8)   /* pair corrections summed                         */
+#define PBDR_PP_AVG_MASK (3u << 8)
+
+/*
+ * Solver parameters.  Zero in a field marked "0 = default" selects the default.
+ *  dt_frame, substeps  the substep length of Alg. 1 is h = dt_frame / substeps
+ *                      (Sec. IV-B runs 100 Hz frames with 10 substeps).
+ *  iterations          solver iterations K per substep (Alg. 1 while loop).
+ *  gravity             uniform acceleration, part of f_ext (Alg. 1, first loop).
+ *  friction_mu         Coulomb coefficient, static = kinetic (Tables I, II).
+ *  radius              common particle radius r; spheres touch at 2r.
+ *  search_radius       neighbour predicate radius R_s, 0 = 2r.
+ *  cell_size           hash-grid cell edge a >= R_s, 0 = R_s * (1 + 2^-10).
+ *  grid_origin         hash-grid origin o.
+ *  hash_bits           key bits k in [6, 28], 0 = max(10, ceil(log2(2N))).
+ *  planes              half-spaces n.x >= d + r, rows (nx, ny, nz, d), |n| = 1.
+ *  nbr_cap             neighbour-list capacity per particle, 0 = 32, max 64.
+ */
+typedef struct {
+    double dt_frame;
+    int32_t substeps;
+    int32_t iterations;
+    double gravity[3];
+    double friction_mu;
+    double radius;
+    double search_radius;
+    double cell_size;
+    double grid_origin[3];
+    int32_t hash_bits;
+    int32_t n_planes;
+    double planes[PBDR_MAX_PLANES][4];
+    uint32_t flags;
+    int32_t nbr_cap;
+} pbdr_params;
+
+/*
+ * Initial scene, in HOST memory; copied during pbdr_scene_create, so the
+ * caller may free it on return.
+ *  x, v        [3][N] positions (m) and velocities (m/s).
+ *  mass        [N] particle masses (kg), finite and > 0.
+ *  body_start  [B+1] body partition, body_start[0] = 0, body_start[B] = N,
+ *              strictly increasing; at most PBDR_MAX_BODY_PARTICLES per body.
+ *  rest_q      optional [3][N] rest offsets q_p of shape matching (to resume a
+ *              saved scene); NULL derives them from x as x - (mass-weighted
+ *              body centre), in FP64 (Sec. III-C).
+ */
+typedef struct {
+    int32_t n_particles;
+    int32_t n_bodies;
+    const float* x;
+    const float* v;
+    const float* mass;
+    const int32_t* body_start;
+    const float* rest_q;
+} pbdr_scene_desc;
+
+/* Values the scene derived from its parameters (defaults resolved). */
+typedef struct {
+    int32_t n_particles;
+    int32_t n_bodies;
+    int32_t hash_bits;
+    int32_t nbr_cap;
+    double substep_h;
+    double search_radius;
+    double cell_size;
+    int32_t particles_per_thread; /* iteration-kernel register tiling */
+    int32_t max_body_particles;
+    size_t workspace_bytes;
+} pbdr_scene_info;
+
+typedef struct pbdr_scene pbdr_scene;
+
+/* ABI version this library implements (PBDR_ABI_VERSION). */
+int32_t pbdr_abi_version(void);
+
+/* Message describing the calling thread's last failed call ("" if none). */
+const char* pbdr_last_error(void);
+
+/* Device workspace bytes a scene of this size needs; 0 if the parameters are
+ * invalid (see pbdr_last_error). */
+size_t pbdr_scene_bytes(const pbdr_params* params, int32_t n_particles, int32_t n_bodies);
+
+/* Creates a scene in dev_workspace (device pointer, 256-byte aligned,
+ * ws_bytes >= pbdr_scene_bytes).  Copies desc into the workspace on
+ * hip_stream (a hipStream_t, or NULL) and synchronises it.  On success *out
+ * receives the handle. */
+pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* desc,
+                              void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                              pbdr_scene** out);
+
+/* Per-particle external acceleration a_p = w_p f_ext,p (Alg. 1, first loop),
+ * added to gravity: a DEVICE pointer to [3][N] floats that the scene reads at
+ * every substep until replaced, or NULL for none.  The caller keeps it alive. */
+pbdr_status pbdr_scene_set_accel(pbdr_scene* scene, const float* accel_dev);
+
+/* Advances n_frames frames of `substeps` substeps each (asynchronous). */
+pbdr_status pbdr_scene_step(pbdr_scene* scene, int32_t n_frames);
+
+/* Advances n_substeps substeps (asynchronous); for substep-level checks. */
+pbdr_status pbdr_scene_substep(pbdr_scene* scene, int32_t n_substeps);
+
+/* Replaces positions and velocities ([3][N] each; host pointers if
+ * on_device == 0, device pointers otherwise).  Bodies and rest pose are kept. */
+pbdr_status pbdr_scene_set_state(pbdr_scene* scene, const float* x, const float* v, int32_t on_device);
+
+/* Copies positions and velocities out ([3][N] each, either may be NULL) and
+ * synchronises; returns any latched device condition. */
+pbdr_status pbdr_scene_read_state(pbdr_scene* scene, float* x, float* v, int32_t on_device);
+
+/* Rest offsets q [3][N] (host), for checkpoints: a scene created from a saved
+ * state with these offsets continues identically. */
+pbdr_status pbdr_scene_read_rest(pbdr_scene* scene, float* rest_q);
+
+/* Synchronises and returns any latched device condition; *max_neighbours (if
+ * not NULL) receives the largest neighbour count seen since creation. */
+pbdr_status pbdr_scene_check(pbdr_scene* scene, int32_t* max_neighbours);
+
+/* Neighbour-list statistics since creation (or the last set_state):
+ * largest length and mean length over all particle-substeps (synchronises). */
+pbdr_status pbdr_scene_neighbour_stats(pbdr_scene* scene, int32_t* max_neighbours, double* mean_neighbours);
+
+/* Debug buffers of the last substep, copied to HOST memory (synchronises):
+ *  PBDR_DEBUG_XT          float [3][N] FP32 predicted positions (index input)
+ *  PBDR_DEBUG_KEYS        uint32 [N]   cell key of each particle
+ *  PBDR_DEBUG_SORTED      uint32 [N]   particle ids sorted by (key, id)
+ *  PBDR_DEBUG_CELL_START  uint32 [2^k] first sorted slot of each key
+ *  PBDR_DEBUG_CELL_COUNT  uint32 [2^k] particles per key
+ *  PBDR_DEBUG_NBR_COUNT   uint32 [N]   neighbour-list lengths
+ *  PBDR_DEBUG_NBR         uint32 [nbr_cap][N] lists, slot-major, ascending
+ *  PBDR_DEBUG_DELTA       float [3][N] X_K - X_init of the last substep, before
+ *                                      the final FP32 rounding of the positions */
+enum {
+    PBDR_DEBUG_XT = 1,
+    PBDR_DEBUG_KEYS = 2,
+    PBDR_DEBUG_SORTED = 3,
+    PBDR_DEBUG_CELL_START = 4,
+    PBDR_DEBUG_CELL_COUNT = 5,
+    PBDR_DEBUG_NBR_COUNT = 6,
+    PBDR_DEBUG_NBR = 7,
+    PBDR_DEBUG_DELTA = 8
+};
+pbdr_status pbdr_scene_read_debug(pbdr_scene* scene, int32_t what, void* dst_host);
+
+/* Measurement aid: enqueues n_launches back-to-back launches of the solver
+ * iteration kernel (one Jacobi iteration of Alg. 1 over all bodies) on the
+ * buffers of the last substep, as the substep itself does K times.  The state
+ * (x, v) is unchanged; the next substep overwrites the iteration buffers.
+ * Requires at least one completed substep (else PBDR_ERR_STATE). */
+pbdr_status pbdr_scene_launch_iterations(pbdr_scene* scene, int32_t n_launches);
+
+/* Resolved parameters and sizes. */
+pbdr_status pbdr_scene_info_get(const pbdr_scene* scene, pbdr_scene_info* out);
+
+/* Frees the host handle (and any captured graph).  The workspace is untouched. */
+void pbdr_scene_destroy(pbdr_scene* scene);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBDR_H */

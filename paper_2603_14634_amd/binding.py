@@ -1,0 +1,301 @@
+"""ctypes binding of libpbdr (include/pbdr.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts numpy /
+torch arguments to the C ABI and back.  Device memory comes from torch (one
+uint8 workspace tensor per scene) and work is enqueued on torch's current HIP
+stream.  Importing works without a GPU; creating a ``Solver`` needs the built
+library and a GPU, and raises if either is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpbdr.so")
+
+OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_DEVICE, ERR_CAPACITY, ERR_NONFINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+FLAG_STD_VELOCITY, FLAG_NO_LIN_MOM, FLAG_NO_ANG_MOM, FLAG_NO_GRAPH = 0x1, 0x2, 0x4, 0x10
+PP_AVG_MAX, PP_AVG_OWN, PP_AVG_NONE = 0, 1 << 8, 2 << 8
+DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3, 4, 5
+DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8
+MAX_PLANES = 8
+
+EXPORTED = [
+    "pbdr_abi_version", "pbdr_last_error", "pbdr_scene_bytes", "pbdr_scene_create",
+    "pbdr_scene_set_accel", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
+    "pbdr_scene_read_state", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
+    "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations", "pbdr_scene_destroy",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dt_frame", ctypes.c_double),
+        ("substeps", ctypes.c_int32),
+        ("iterations", ctypes.c_int32),
+        ("gravity", ctypes.c_double * 3),
+        ("friction_mu", ctypes.c_double),
+        ("radius", ctypes.c_double),
+        ("search_radius", ctypes.c_double),
+        ("cell_size", ctypes.c_double),
+        ("grid_origin", ctypes.c_double * 3),
+        ("hash_bits", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("planes", (ctypes.c_double * 4) * MAX_PLANES),
+        ("flags", ctypes.c_uint32),
+        ("nbr_cap", ctypes.c_int32),
+    ]
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int32),
+        ("n_bodies", ctypes.c_int32),
+        ("x", ctypes.c_void_p),
+        ("v", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("body_start", ctypes.c_void_p),
+        ("rest_q", ctypes.c_void_p),
+    ]
+
+
+class SceneInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int32),
+        ("n_bodies", ctypes.c_int32),
+        ("hash_bits", ctypes.c_int32),
+        ("nbr_cap", ctypes.c_int32),
+        ("substep_h", ctypes.c_double),
+        ("search_radius", ctypes.c_double),
+        ("cell_size", ctypes.c_double),
+        ("particles_per_thread", ctypes.c_int32),
+        ("max_body_particles", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+class PbdrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("pbdr status %d: %s" % (status, message))
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libpbdr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libpbdr.so is not built (expected at %s); run "
+                           "`python -m paper_2603_14634_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    lib.pbdr_abi_version.restype = i32
+    lib.pbdr_last_error.restype = ctypes.c_char_p
+    lib.pbdr_scene_bytes.restype = sz
+    lib.pbdr_scene_bytes.argtypes = [ctypes.POINTER(Params), i32, i32]
+    lib.pbdr_scene_create.restype = i32
+    lib.pbdr_scene_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(SceneDesc), vp, sz, vp,
+                                      ctypes.POINTER(vp)]
+    for name, args in [("pbdr_scene_set_accel", [vp, vp]), ("pbdr_scene_step", [vp, i32]),
+                       ("pbdr_scene_substep", [vp, i32]), ("pbdr_scene_set_state", [vp, vp, vp, i32]),
+                       ("pbdr_scene_read_state", [vp, vp, vp, i32]), ("pbdr_scene_read_rest", [vp, vp]),
+                       ("pbdr_scene_check", [vp, ctypes.POINTER(i32)]),
+                       ("pbdr_scene_neighbour_stats", [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
+                       ("pbdr_scene_read_debug", [vp, i32, vp]),
+                       ("pbdr_scene_launch_iterations", [vp, i32]),
+                       ("pbdr_scene_info_get", [vp, ctypes.POINTER(SceneInfo)])]:
+        fn = getattr(lib, name)
+        fn.restype = i32
+        fn.argtypes = args
+    lib.pbdr_scene_destroy.restype = None
+    lib.pbdr_scene_destroy.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load_library().pbdr_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise PbdrError(status, last_error())
+
+
+def make_params(dt_frame: float, substeps: int, iterations: int, radius: float,
+                gravity: Sequence[float] = (0.0, 0.0, -9.81), mu: float = 0.4,
+                planes: Sequence[Sequence[float]] = ((0.0, 0.0, 1.0, 0.0),),
+                search_radius: float = 0.0, cell_size: float = 0.0, grid_origin=(0.0, 0.0, 0.0),
+                hash_bits: int = 0, nbr_cap: int = 0, flags: int = 0) -> Params:
+    p = Params()
+    p.dt_frame = dt_frame
+    p.substeps = substeps
+    p.iterations = iterations
+    p.gravity[:] = [float(g) for g in gravity]
+    p.friction_mu = mu
+    p.radius = radius
+    p.search_radius = search_radius
+    p.cell_size = cell_size
+    p.grid_origin[:] = [float(o) for o in grid_origin]
+    p.hash_bits = hash_bits
+    if len(planes) > MAX_PLANES:
+        raise ValueError("at most %d planes" % MAX_PLANES)
+    p.n_planes = len(planes)
+    for j, pl in enumerate(planes):
+        p.planes[j][:] = [float(c) for c in pl]
+    p.flags = flags
+    p.nbr_cap = nbr_cap
+    return p
+
+
+def params_for(scene, **kw) -> Params:
+    """Parameters of a ``scenes.Scene``; keyword arguments override."""
+    args = dict(gravity=scene.gravity, mu=scene.mu, planes=scene.planes)
+    args.update(kw)
+    return make_params(scene.dt_frame, scene.substeps, scene.iterations, scene.radius, **args)
+
+
+def scene_bytes(params: Params, n_particles: int, n_bodies: int) -> int:
+    return int(load_library().pbdr_scene_bytes(ctypes.byref(params), n_particles, n_bodies))
+
+
+def _host_f32(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+class Solver:
+    """One scene resident in GPU memory (a torch uint8 workspace)."""
+
+    def __init__(self, params: Params, x, v, mass, body_start, rest_q=None, device: str = "cuda:0",
+                 stream=None):
+        import torch
+
+        self._lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP GPU is required")
+        self.device = torch.device(device)
+        self.params = params
+        self._x = _host_f32(x, (3, np.asarray(x).shape[1]))
+        n = self._x.shape[1]
+        self._v = _host_f32(v, (3, n))
+        self._m = _host_f32(mass, (n,))
+        self._bs = np.ascontiguousarray(body_start, dtype=np.int32)
+        self._q = None if rest_q is None else _host_f32(rest_q, (3, n))
+        self.n, self.n_bodies = n, int(self._bs.shape[0] - 1)
+        nbytes = self._lib.pbdr_scene_bytes(ctypes.byref(params), n, self.n_bodies)
+        if nbytes == 0:
+            raise PbdrError(ERR_INVALID_ARG, last_error())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        desc = SceneDesc(n, self.n_bodies, self._x.ctypes.data, self._v.ctypes.data, self._m.ctypes.data,
+                         self._bs.ctypes.data, None if self._q is None else self._q.ctypes.data)
+        handle = ctypes.c_void_p()
+        _check(self._lib.pbdr_scene_create(ctypes.byref(params), ctypes.byref(desc),
+                                           self.workspace.data_ptr(), int(nbytes),
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
+        self._h = handle
+        self._accel = None
+
+    @classmethod
+    def from_scene(cls, scene, device: str = "cuda:0", **param_overrides) -> "Solver":
+        return cls(params_for(scene, **param_overrides), scene.x, scene.v, scene.mass, scene.body_start,
+                   device=device)
+
+    # -- stepping ---------------------------------------------------------
+    def step(self, n_frames: int = 1):
+        _check(self._lib.pbdr_scene_step(self._h, n_frames))
+
+    def substep(self, n_substeps: int = 1):
+        _check(self._lib.pbdr_scene_substep(self._h, n_substeps))
+
+    def set_accel(self, accel):
+        """accel: torch float32 device tensor [3, N] (kept alive here) or None."""
+        if accel is None:
+            self._accel = None
+            _check(self._lib.pbdr_scene_set_accel(self._h, None))
+            return
+        if tuple(accel.shape) != (3, self.n) or accel.dtype.__str__() != "torch.float32" or not accel.is_cuda:
+            raise ValueError("accel must be a float32 CUDA tensor of shape (3, N)")
+        self._accel = accel.contiguous()
+        _check(self._lib.pbdr_scene_set_accel(self._h, ctypes.c_void_p(self._accel.data_ptr())))
+
+    # -- state ------------------------------------------------------------
+    def set_state(self, x, v):
+        if hasattr(x, "is_cuda") and x.is_cuda:
+            _check(self._lib.pbdr_scene_set_state(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                  ctypes.c_void_p(v.data_ptr()), 1))
+        else:
+            xx, vv = _host_f32(x, (3, self.n)), _host_f32(v, (3, self.n))
+            _check(self._lib.pbdr_scene_set_state(self._h, xx.ctypes.data, vv.ctypes.data, 0))
+
+    def read_state(self):
+        x = np.empty((3, self.n), dtype=np.float32)
+        v = np.empty((3, self.n), dtype=np.float32)
+        _check(self._lib.pbdr_scene_read_state(self._h, x.ctypes.data, v.ctypes.data, 0))
+        return x, v
+
+    def read_state_device(self, x, v):
+        _check(self._lib.pbdr_scene_read_state(self._h, ctypes.c_void_p(x.data_ptr()),
+                                               ctypes.c_void_p(v.data_ptr()), 1))
+
+    def read_rest(self):
+        q = np.empty((3, self.n), dtype=np.float32)
+        _check(self._lib.pbdr_scene_read_rest(self._h, q.ctypes.data))
+        return q
+
+    def check(self) -> int:
+        mx = ctypes.c_int32()
+        _check(self._lib.pbdr_scene_check(self._h, ctypes.byref(mx)))
+        return int(mx.value)
+
+    def status(self) -> int:
+        mx = ctypes.c_int32()
+        return int(self._lib.pbdr_scene_check(self._h, ctypes.byref(mx)))
+
+    def neighbour_stats(self):
+        mx, mean = ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.pbdr_scene_neighbour_stats(self._h, ctypes.byref(mx), ctypes.byref(mean)))
+        return int(mx.value), float(mean.value)
+
+    def launch_iterations(self, n_launches: int):
+        """Measurement aid: n back-to-back launches of the iteration kernel alone."""
+        _check(self._lib.pbdr_scene_launch_iterations(self._h, n_launches))
+
+    def info(self) -> SceneInfo:
+        out = SceneInfo()
+        _check(self._lib.pbdr_scene_info_get(self._h, ctypes.byref(out)))
+        return out
+
+    def read_debug(self, what: int) -> np.ndarray:
+        info = self.info()
+        n, T, cap = self.n, 1 << info.hash_bits, info.nbr_cap
+        shapes = {DEBUG_XT: ((3, n), np.float32), DEBUG_KEYS: ((n,), np.uint32),
+                  DEBUG_SORTED: ((n,), np.uint32), DEBUG_CELL_START: ((T,), np.uint32),
+                  DEBUG_CELL_COUNT: ((T,), np.uint32), DEBUG_NBR_COUNT: ((n,), np.uint32),
+                  DEBUG_NBR: ((cap, n), np.uint32), DEBUG_DELTA: ((3, n), np.float32)}
+        shape, dt = shapes[what]
+        out = np.empty(shape, dtype=dt)
+        _check(self._lib.pbdr_scene_read_debug(self._h, what, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pbdr_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

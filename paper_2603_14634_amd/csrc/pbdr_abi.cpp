@@ -1,0 +1,542 @@
+// Host side of libpbdr: argument validation, workspace layout, scene
+// creation, stepping (direct launches or a captured per-frame HIP graph),
+// and result / debug read-back.  See include/pbdr.h for the contract.
+#include "pbdr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "pbdr_device.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+pbdr_status fail(pbdr_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return fail(PBDR_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr uint32_t kKnownFlags = PBDR_FLAG_STD_VELOCITY | PBDR_FLAG_NO_LIN_MOM | PBDR_FLAG_NO_ANG_MOM |
+                                 PBDR_FLAG_NO_GRAPH | PBDR_PP_AVG_MASK;
+constexpr int32_t kMaxParticles = 1 << 28;
+constexpr int kMinHashBits = 6, kMaxHashBits = 28;
+
+struct Resolved {
+    pbdr_params p;
+    double h, rs, a;
+    int k, cap;
+};
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
+{
+    if (!in) return fail(PBDR_ERR_INVALID_ARG, "params is NULL");
+    const pbdr_params& p = *in;
+    if (!(std::isfinite(p.dt_frame) && p.dt_frame > 0.0)) return fail(PBDR_ERR_INVALID_ARG, "dt_frame must be finite and > 0");
+    if (p.substeps < 1 || p.substeps > 100000) return fail(PBDR_ERR_INVALID_ARG, "substeps must be in [1, 100000]");
+    if (p.iterations < 0 || p.iterations > 100000) return fail(PBDR_ERR_INVALID_ARG, "iterations must be in [0, 100000]");
+    if (!finite3(p.gravity)) return fail(PBDR_ERR_INVALID_ARG, "gravity must be finite");
+    if (!(std::isfinite(p.friction_mu) && p.friction_mu >= 0.0)) return fail(PBDR_ERR_INVALID_ARG, "friction_mu must be finite and >= 0");
+    if (!(std::isfinite(p.radius) && p.radius > 0.0)) return fail(PBDR_ERR_INVALID_ARG, "radius must be finite and > 0");
+    if (!(std::isfinite(p.search_radius) && p.search_radius >= 0.0)) return fail(PBDR_ERR_INVALID_ARG, "search_radius must be finite and >= 0");
+    if (!(std::isfinite(p.cell_size) && p.cell_size >= 0.0)) return fail(PBDR_ERR_INVALID_ARG, "cell_size must be finite and >= 0");
+    if (!finite3(p.grid_origin)) return fail(PBDR_ERR_INVALID_ARG, "grid_origin must be finite");
+    if (p.n_planes < 0 || p.n_planes > PBDR_MAX_PLANES) return fail(PBDR_ERR_INVALID_ARG, "n_planes must be in [0, %d]", PBDR_MAX_PLANES);
+    for (int j = 0; j < p.n_planes; ++j) {
+        const double* pl = p.planes[j];
+        if (!(finite3(pl) && std::isfinite(pl[3]))) return fail(PBDR_ERR_INVALID_ARG, "plane %d is not finite", j);
+        const double len = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        if (std::fabs(len - 1.0) > 1e-6) return fail(PBDR_ERR_INVALID_ARG, "plane %d normal is not unit length", j);
+    }
+    if (p.flags & ~kKnownFlags) return fail(PBDR_ERR_INVALID_ARG, "unknown flag bits 0x%x", p.flags & ~kKnownFlags);
+    if ((p.flags & PBDR_PP_AVG_MASK) == (3u << 8)) return fail(PBDR_ERR_INVALID_ARG, "invalid pair averaging mode");
+    if (p.nbr_cap < 0 || p.nbr_cap > pbdr::kMaxCap) return fail(PBDR_ERR_INVALID_ARG, "nbr_cap must be in [0, %d]", pbdr::kMaxCap);
+    if (p.hash_bits != 0 && (p.hash_bits < kMinHashBits || p.hash_bits > kMaxHashBits))
+        return fail(PBDR_ERR_INVALID_ARG, "hash_bits must be 0 or in [%d, %d]", kMinHashBits, kMaxHashBits);
+    if (n < 0 || n > kMaxParticles) return fail(PBDR_ERR_INVALID_ARG, "particle count %d out of range", n);
+    Resolved r;
+    r.p = p;
+    r.h = p.dt_frame / (double)p.substeps;
+    r.rs = p.search_radius > 0.0 ? p.search_radius : 2.0 * p.radius;
+    r.a = p.cell_size > 0.0 ? p.cell_size : r.rs * (1.0 + 1.0 / 1024.0);
+    if (r.a < r.rs) return fail(PBDR_ERR_INVALID_ARG, "cell_size %g is below the search radius %g", r.a, r.rs);
+    if (p.hash_bits) {
+        r.k = p.hash_bits;
+    } else {
+        int k = 10;
+        while (k < kMaxHashBits && (1ll << k) < 2ll * (long long)n) ++k;
+        r.k = k;
+    }
+    r.cap = p.nbr_cap ? p.nbr_cap : 32;
+    *out = r;
+    return PBDR_OK;
+}
+
+struct Layout {
+    size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt, sbody, key, rank,
+        sorted_raw, sorted, nbr_n, nbr, cell_count, cell_start, tile_sums, body_rot, counters, total;
+};
+
+Layout make_layout(int32_t n, int32_t nb, int k, int cap)
+{
+    const size_t N = (size_t)n, B = (size_t)nb, T = (size_t)1 << k;
+    const size_t tiles = (T + pbdr::kScanTile - 1) / pbdr::kScanTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255u) & ~(size_t)255u;
+        return o;
+    };
+    Layout L;
+    L.x = take(12 * N);
+    L.v = take(12 * N);
+    L.mass = take(4 * N);
+    L.body = take(4 * N);
+    L.q = take(12 * N);
+    L.body_start = take(4 * (B + 1));
+    L.body_mass = take(4 * B);
+    L.dl0 = take(12 * N);
+    L.dl1 = take(12 * N);
+    L.vel0 = take(12 * N);
+    L.vel1 = take(12 * N);
+    L.xt = take(12 * N);
+    L.sxt = take(12 * N);
+    L.sbody = take(4 * N);
+    L.key = take(4 * N);
+    L.rank = take(4 * N);
+    L.sorted_raw = take(4 * N);
+    L.sorted = take(4 * N);
+    L.nbr_n = take(4 * N);
+    L.nbr = take(4 * N * (size_t)cap);
+    L.cell_count = take(4 * T);
+    L.cell_start = take(4 * T);
+    L.tile_sums = take(4 * tiles);
+    L.body_rot = take(36 * B);
+    L.counters = take(sizeof(pbdr::Counters));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct pbdr_scene {
+    Resolved res;
+    Layout lay;
+    pbdr::Scene dev;
+    pbdr::StepConsts consts;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    int ppt = 1;
+    int max_body = 0;
+    bool stepped = false;
+};
+
+namespace {
+
+void drop_graph(pbdr_scene* s)
+{
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+}
+
+pbdr_status read_counters(pbdr_scene* s, pbdr::Counters* c)
+{
+    HIP_TRY(hipMemcpyAsync(c, s->ws + s->lay.counters, sizeof(*c), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PBDR_OK;
+}
+
+pbdr_status latched(pbdr_scene* s)
+{
+    pbdr::Counters c;
+    pbdr_status st = read_counters(s, &c);
+    if (st != PBDR_OK) return st;
+    if (c.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity became non-finite");
+    if (c.err & pbdr::kErrCapacity)
+        return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", c.max_nbr, s->res.cap);
+    return PBDR_OK;
+}
+
+void fill_consts(pbdr_scene* s)
+{
+    const Resolved& r = s->res;
+    pbdr::StepConsts& c = s->consts;
+    std::memset(&c, 0, sizeof(c));
+    c.h = (float)r.h;
+    c.inv_h = (float)(1.0 / r.h);
+    for (int k = 0; k < 3; ++k) {
+        c.g[k] = (float)r.p.gravity[k];
+        c.origin[k] = (float)r.p.grid_origin[k];
+    }
+    c.mu = (float)r.p.friction_mu;
+    c.radius = (float)r.p.radius;
+    c.two_r = (float)(2.0 * r.p.radius);
+    c.search_r2 = (float)(r.rs * r.rs);
+    c.inv_cell = (float)(1.0 / r.a);
+    c.key_mask = (uint32_t)((1ull << r.k) - 1ull);
+    c.nbr_cap = r.cap;
+    c.flags = r.p.flags;
+    c.n_planes = r.p.n_planes;
+    for (int j = 0; j < r.p.n_planes; ++j) {
+        for (int k = 0; k < 3; ++k) c.plane_n[j][k] = (float)r.p.planes[j][k];
+        c.plane_d[j] = (float)r.p.planes[j][3];
+    }
+}
+
+void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
+{
+    char* w = s->ws;
+    const Layout& L = s->lay;
+    pbdr::Scene& d = s->dev;
+    d.n = n;
+    d.nb = nb;
+    d.T = (uint32_t)(1ull << s->res.k);
+    d.n_scan_tiles = (uint32_t)(((size_t)d.T + pbdr::kScanTile - 1) / pbdr::kScanTile);
+    d.x = (float*)(w + L.x);
+    d.v = (float*)(w + L.v);
+    d.mass = (const float*)(w + L.mass);
+    d.body = (const int32_t*)(w + L.body);
+    d.q = (const float*)(w + L.q);
+    d.body_start = (const int32_t*)(w + L.body_start);
+    d.body_mass = (const float*)(w + L.body_mass);
+    d.dl[0] = (float*)(w + L.dl0);
+    d.dl[1] = (float*)(w + L.dl1);
+    d.vel[0] = (float*)(w + L.vel0);
+    d.vel[1] = (float*)(w + L.vel1);
+    d.xt = (float*)(w + L.xt);
+    d.sxt = (float*)(w + L.sxt);
+    d.sbody = (int32_t*)(w + L.sbody);
+    d.key = (uint32_t*)(w + L.key);
+    d.rank = (uint32_t*)(w + L.rank);
+    d.sorted_raw = (uint32_t*)(w + L.sorted_raw);
+    d.sorted = (uint32_t*)(w + L.sorted);
+    d.nbr_n = (uint32_t*)(w + L.nbr_n);
+    d.nbr = (uint32_t*)(w + L.nbr);
+    d.cell_count = (uint32_t*)(w + L.cell_count);
+    d.cell_start = (uint32_t*)(w + L.cell_start);
+    d.tile_sums = (uint32_t*)(w + L.tile_sums);
+    d.body_rot = (float*)(w + L.body_rot);
+    d.counters = (pbdr::Counters*)(w + L.counters);
+    d.accel = nullptr;
+}
+
+pbdr_status check_host_finite(const float* a, size_t count, const char* what)
+{
+    for (size_t i = 0; i < count; ++i)
+        if (!std::isfinite(a[i])) return fail(PBDR_ERR_INVALID_ARG, "%s[%zu] is not finite", what, i);
+    return PBDR_OK;
+}
+
+pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
+{
+    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->ppt, substeps_total, s->stream);
+    if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    s->stepped = true;
+    return PBDR_OK;
+}
+
+pbdr_status ensure_graph(pbdr_scene* s)
+{
+    if (s->exec) return PBDR_OK;
+    if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->ppt, s->res.p.substeps,
+                                          s->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(PBDR_ERR_DEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    s->graph = g;
+    HIP_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    return PBDR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pbdr_abi_version(void) { return PBDR_ABI_VERSION; }
+
+const char* pbdr_last_error(void) { return g_err; }
+
+size_t pbdr_scene_bytes(const pbdr_params* params, int32_t n_particles, int32_t n_bodies)
+{
+    Resolved r;
+    if (resolve(params, n_particles, &r) != PBDR_OK) return 0;
+    if (n_bodies < 0 || (n_particles > 0 && n_bodies < 1) || n_bodies > n_particles) {
+        fail(PBDR_ERR_INVALID_ARG, "body count %d invalid for %d particles", n_bodies, n_particles);
+        return 0;
+    }
+    return make_layout(n_particles, n_bodies, r.k, r.cap).total;
+}
+
+pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* desc, void* dev_workspace,
+                              size_t ws_bytes, void* hip_stream, pbdr_scene** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(PBDR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!desc) return fail(PBDR_ERR_INVALID_ARG, "desc is NULL");
+    const int32_t n = desc->n_particles, nb = desc->n_bodies;
+    Resolved r;
+    pbdr_status st = resolve(params, n, &r);
+    if (st != PBDR_OK) return st;
+    if (nb < 0 || nb > n || (n > 0 && nb < 1)) return fail(PBDR_ERR_INVALID_ARG, "body count %d invalid for %d particles", nb, n);
+    if (n > 0 && (!desc->x || !desc->v || !desc->mass || !desc->body_start))
+        return fail(PBDR_ERR_INVALID_ARG, "desc arrays must not be NULL");
+    int max_body = 0;
+    if (n > 0) {
+        if (desc->body_start[0] != 0 || desc->body_start[nb] != n)
+            return fail(PBDR_ERR_INVALID_ARG, "body_start must begin at 0 and end at n_particles");
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t len = desc->body_start[b + 1] - desc->body_start[b];
+            if (len < 1) return fail(PBDR_ERR_INVALID_ARG, "body %d is empty or body_start decreases", b);
+            if (len > PBDR_MAX_BODY_PARTICLES)
+                return fail(PBDR_ERR_INVALID_ARG, "body %d has %d particles (max %d)", b, len, PBDR_MAX_BODY_PARTICLES);
+            if (len > max_body) max_body = len;
+        }
+        for (int32_t i = 0; i < n; ++i)
+            if (!(std::isfinite(desc->mass[i]) && desc->mass[i] > 0.0f))
+                return fail(PBDR_ERR_INVALID_ARG, "mass[%d] must be finite and > 0", i);
+        if ((st = check_host_finite(desc->x, 3 * (size_t)n, "x")) != PBDR_OK) return st;
+        if ((st = check_host_finite(desc->v, 3 * (size_t)n, "v")) != PBDR_OK) return st;
+        if (desc->rest_q && (st = check_host_finite(desc->rest_q, 3 * (size_t)n, "rest_q")) != PBDR_OK) return st;
+    }
+    const Layout lay = make_layout(n, nb, r.k, r.cap);
+    if (!dev_workspace) return fail(PBDR_ERR_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)dev_workspace & 255u) != 0) return fail(PBDR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < lay.total) return fail(PBDR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+
+    pbdr_scene* s = new (std::nothrow) pbdr_scene();
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "out of host memory");
+    s->res = r;
+    s->lay = lay;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (char*)dev_workspace;
+    s->ws_bytes = ws_bytes;
+    s->max_body = max_body;
+    s->ppt = max_body <= pbdr::kBlock ? 1 : (max_body <= 2 * pbdr::kBlock ? 2 : 4);
+    fill_device(s, n, nb);
+    fill_consts(s);
+
+    // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
+    std::vector<int32_t> body((size_t)n);
+    std::vector<float> bmass((size_t)nb), q(3 * (size_t)n);
+    for (int32_t b = 0; b < nb; ++b) {
+        double M = 0.0, cm[3] = {0.0, 0.0, 0.0};
+        for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i) {
+            body[(size_t)i] = b;
+            const double m = desc->mass[i];
+            M += m;
+            for (int k = 0; k < 3; ++k) cm[k] += m * (double)desc->x[(size_t)k * n + i];
+        }
+        bmass[(size_t)b] = (float)M;
+        for (int k = 0; k < 3; ++k) cm[k] /= M;
+        for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i)
+            for (int k = 0; k < 3; ++k) {
+                const size_t j = (size_t)k * n + i;
+                q[j] = desc->rest_q ? desc->rest_q[j] : (float)((double)desc->x[j] - cm[k]);
+            }
+    }
+    auto h2d = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(s->ws + off, src, bytes, hipMemcpyHostToDevice, s->stream);
+    };
+    hipError_t e = hipSuccess;
+    if (n > 0) {
+        if (e == hipSuccess) e = h2d(lay.x, desc->x, 12 * (size_t)n);
+        if (e == hipSuccess) e = h2d(lay.v, desc->v, 12 * (size_t)n);
+        if (e == hipSuccess) e = h2d(lay.mass, desc->mass, 4 * (size_t)n);
+        if (e == hipSuccess) e = h2d(lay.body, body.data(), 4 * (size_t)n);
+        if (e == hipSuccess) e = h2d(lay.q, q.data(), 12 * (size_t)n);
+        if (e == hipSuccess) e = h2d(lay.body_start, desc->body_start, 4 * ((size_t)nb + 1));
+        if (e == hipSuccess) e = h2d(lay.body_mass, bmass.data(), 4 * (size_t)nb);
+    }
+    if (e == hipSuccess) e = pbdr::enqueue_clear_counters(s->dev, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return fail(PBDR_ERR_DEVICE, "scene upload failed: %s", hipGetErrorString(e));
+    }
+    *out = s;
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_set_accel(pbdr_scene* s, const float* accel_dev)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    if (s->dev.accel != accel_dev) drop_graph(s);
+    s->dev.accel = accel_dev;
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_step(pbdr_scene* s, int32_t n_frames)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    if (n_frames < 0) return fail(PBDR_ERR_INVALID_ARG, "n_frames must be >= 0");
+    if (n_frames == 0 || s->dev.n == 0) return PBDR_OK;
+    if (s->res.p.flags & PBDR_FLAG_NO_GRAPH) {
+        const long long total = (long long)n_frames * s->res.p.substeps;
+        if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
+        return enqueue(s, (int32_t)total);
+    }
+    pbdr_status st = ensure_graph(s);
+    if (st != PBDR_OK) return st;
+    for (int32_t f = 0; f < n_frames; ++f) HIP_TRY(hipGraphLaunch(s->exec, s->stream));
+    s->stepped = true;
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
+    if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
+    hipError_t e = pbdr::enqueue_iterations(s->dev, s->consts, s->ppt, n_launches, s->stream);
+    if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_substep(pbdr_scene* s, int32_t n_substeps)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    if (n_substeps < 0) return fail(PBDR_ERR_INVALID_ARG, "n_substeps must be >= 0");
+    if (n_substeps == 0 || s->dev.n == 0) return PBDR_OK;
+    return enqueue(s, n_substeps);
+}
+
+pbdr_status pbdr_scene_set_state(pbdr_scene* s, const float* x, const float* v, int32_t on_device)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    const size_t bytes = 12 * (size_t)s->dev.n;
+    if (bytes == 0) return PBDR_OK;
+    if (!x || !v) return fail(PBDR_ERR_INVALID_ARG, "x and v must not be NULL");
+    if (!on_device) {
+        pbdr_status st = check_host_finite(x, 3 * (size_t)s->dev.n, "x");
+        if (st == PBDR_OK) st = check_host_finite(v, 3 * (size_t)s->dev.n, "v");
+        if (st != PBDR_OK) return st;
+    }
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(s->ws + s->lay.x, x, bytes, kind, s->stream));
+    HIP_TRY(hipMemcpyAsync(s->ws + s->lay.v, v, bytes, kind, s->stream));
+    HIP_TRY(pbdr::enqueue_clear_counters(s->dev, s->stream));
+    if (!on_device) HIP_TRY(hipStreamSynchronize(s->stream));
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_read_state(pbdr_scene* s, float* x, float* v, int32_t on_device)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    const size_t bytes = 12 * (size_t)s->dev.n;
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (bytes && x) HIP_TRY(hipMemcpyAsync(x, s->ws + s->lay.x, bytes, kind, s->stream));
+    if (bytes && v) HIP_TRY(hipMemcpyAsync(v, s->ws + s->lay.v, bytes, kind, s->stream));
+    return latched(s);
+}
+
+pbdr_status pbdr_scene_read_rest(pbdr_scene* s, float* rest_q)
+{
+    if (!s || !rest_q) return fail(PBDR_ERR_INVALID_ARG, "scene and rest_q must not be NULL");
+    const size_t bytes = 12 * (size_t)s->dev.n;
+    if (bytes) HIP_TRY(hipMemcpyAsync(rest_q, s->ws + s->lay.q, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_check(pbdr_scene* s, int32_t* max_neighbours)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    pbdr::Counters c;
+    pbdr_status st = read_counters(s, &c);
+    if (st != PBDR_OK) return st;
+    if (max_neighbours) *max_neighbours = (int32_t)c.max_nbr;
+    return latched(s);
+}
+
+pbdr_status pbdr_scene_neighbour_stats(pbdr_scene* s, int32_t* max_neighbours, double* mean_neighbours)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    pbdr::Counters c;
+    pbdr_status st = read_counters(s, &c);
+    if (st != PBDR_OK) return st;
+    if (max_neighbours) *max_neighbours = (int32_t)c.max_nbr;
+    if (mean_neighbours) *mean_neighbours = c.nbr_rows ? (double)c.nbr_sum / (double)c.nbr_rows : 0.0;
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_read_debug(pbdr_scene* s, int32_t what, void* dst)
+{
+    if (!s || !dst) return fail(PBDR_ERR_INVALID_ARG, "scene and dst must not be NULL");
+    const size_t N = (size_t)s->dev.n, T = (size_t)s->dev.T;
+    size_t off = 0, bytes = 0;
+    switch (what) {
+    case PBDR_DEBUG_XT: off = s->lay.xt; bytes = 12 * N; break;
+    case PBDR_DEBUG_KEYS: off = s->lay.key; bytes = 4 * N; break;
+    case PBDR_DEBUG_SORTED: off = s->lay.sorted; bytes = 4 * N; break;
+    case PBDR_DEBUG_CELL_START: off = s->lay.cell_start; bytes = 4 * T; break;
+    case PBDR_DEBUG_CELL_COUNT: off = s->lay.cell_count; bytes = 4 * T; break;
+    case PBDR_DEBUG_NBR_COUNT: off = s->lay.nbr_n; bytes = 4 * N; break;
+    case PBDR_DEBUG_NBR: off = s->lay.nbr; bytes = 4 * N * (size_t)s->res.cap; break;
+    case PBDR_DEBUG_DELTA:
+        off = (s->res.p.iterations % 2 == 0) ? s->lay.dl0 : s->lay.dl1;
+        bytes = 12 * N;
+        break;
+    default: return fail(PBDR_ERR_INVALID_ARG, "unknown debug buffer %d", what);
+    }
+    if (bytes) HIP_TRY(hipMemcpyAsync(dst, s->ws + off, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return PBDR_OK;
+}
+
+pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
+{
+    if (!s || !out) return fail(PBDR_ERR_INVALID_ARG, "scene and out must not be NULL");
+    out->n_particles = s->dev.n;
+    out->n_bodies = s->dev.nb;
+    out->hash_bits = s->res.k;
+    out->nbr_cap = s->res.cap;
+    out->substep_h = s->res.h;
+    out->search_radius = s->res.rs;
+    out->cell_size = s->res.a;
+    out->particles_per_thread = s->ppt;
+    out->max_body_particles = s->max_body;
+    out->workspace_bytes = s->lay.total;
+    return PBDR_OK;
+}
+
+void pbdr_scene_destroy(pbdr_scene* s)
+{
+    if (!s) return;
+    drop_graph(s);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+}
+
+}  // extern "C"

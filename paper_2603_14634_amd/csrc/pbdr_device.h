@@ -1,0 +1,90 @@
+// Internal device-side layout shared by the PBD-R kernels and the C-ABI host
+// code of libpbdr.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pbdr {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kMaxPlanes = 8;
+constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
+constexpr int kScanItems = 8;    // cell-table scan: counts per thread
+constexpr int kScanTile = kBlock * kScanItems;
+
+enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u };
+
+enum : uint32_t {
+    kFlagStdVelocity = 0x1u,
+    kFlagNoLinMom = 0x2u,
+    kFlagNoAngMom = 0x4u,
+    kAvgShift = 8u,
+};
+
+// Device-side counters, latched across substeps until read by the host.
+struct Counters {
+    uint32_t err;                  // kErr* bits
+    uint32_t max_nbr;              // largest neighbour-list length seen
+    unsigned long long nbr_sum;    // sum of list lengths (for the mean)
+    unsigned long long nbr_rows;   // particles counted in nbr_sum
+};
+
+// FP32 constants of one substep.
+struct StepConsts {
+    float h, inv_h;
+    float g[3];
+    float mu, radius, two_r;
+    float search_r2;      // fl32(R_s^2)
+    float inv_cell;       // fl32(1 / a)
+    float origin[3];
+    uint32_t key_mask;    // 2^k - 1
+    int32_t nbr_cap;
+    uint32_t flags;
+    int32_t n_planes;
+    float plane_n[kMaxPlanes][3];
+    float plane_d[kMaxPlanes];
+};
+
+// Device pointers into a scene's workspace.
+struct Scene {
+    int32_t n, nb;
+    uint32_t T;               // 2^k cells
+    uint32_t n_scan_tiles;    // ceil(T / kScanTile)
+    float* x;                 // [3][N] state positions (X_init during a substep)
+    float* v;                 // [3][N] state velocities
+    const float* mass;        // [N]
+    const int32_t* body;      // [N] body of each particle
+    const float* q;           // [3][N] rest offsets
+    const int32_t* body_start;// [B+1]
+    const float* body_mass;   // [B]
+    float* dl[2];             // [3][N] X_i - X_init, double buffered
+    float* vel[2];            // [3][N] V_i, double buffered
+    float* xt;                // [3][N] FP32 predicted positions
+    float* sxt;               // [3][N] predicted positions in raw sorted order
+    int32_t* sbody;           // [N] body ids in raw sorted order
+    uint32_t* key;            // [N]
+    uint32_t* rank;           // [N] slot within the key from the counting pass
+    uint32_t* sorted_raw;     // [N] ids grouped by key, arbitrary order within a key
+    uint32_t* sorted;         // [N] ids sorted by (key, id)
+    uint32_t* nbr_n;          // [N] neighbour-list length
+    uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
+    uint32_t* cell_count;     // [T]
+    uint32_t* cell_start;     // [T]
+    uint32_t* tile_sums;      // [n_scan_tiles]
+    float* body_rot;          // [B][9] last rotation of shape matching
+    Counters* counters;
+    const float* accel;       // [3][N] external acceleration or nullptr
+};
+
+// Enqueues `count` substeps.  iterations = K; ppt = particles per thread of
+// the iteration kernel (1, 2 or 4).
+hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int ppt,
+                            int count, hipStream_t stream);
+
+// Enqueues `count` launches of the iteration kernel alone (measurement).
+hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int ppt, int count, hipStream_t stream);
+
+// Clears the latched counters.
+hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream);
+
+}  // namespace pbdr

@@ -1,0 +1,140 @@
+"""C-ABI checks that need no GPU: exports, header, struct layout, validation."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2603_14634_amd import binding as B
+from paper_2603_14634_amd import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pbdr.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pbdr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = B.load_library()
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(B.EXPORTED) == declared
+    assert lib.pbdr_abi_version() == 1
+
+
+def test_header_compiles_as_c_and_struct_layout_matches_binding(tmp_path):
+    prog = tmp_path / "layout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pbdr.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pbdr_params), offsetof(pbdr_params, planes),
+         offsetof(pbdr_params, flags), sizeof(pbdr_scene_desc), sizeof(pbdr_scene_info),
+         offsetof(pbdr_scene_info, workspace_bytes));
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(prog),
+                    "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
+    got = [int(t) for t in out]
+    want = [ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
+            ctypes.sizeof(B.SceneInfo), B.SceneInfo.workspace_bytes.offset]
+    assert got == want
+
+
+def _params(**kw):
+    sc = scenes.drop_cubes(0)
+    return sc, B.params_for(sc, **kw)
+
+
+def test_scene_bytes_and_parameter_validation():
+    sc, p = _params()
+    nbytes = B.scene_bytes(p, sc.n, sc.n_bodies)
+    assert nbytes > 0 and nbytes % 256 == 0
+    bad = [
+        dict(substeps=0), dict(iterations=-1), dict(radius=0.0), dict(dt_frame=float("nan")),
+        dict(mu=-0.1), dict(nbr_cap=65), dict(hash_bits=5), dict(hash_bits=29), dict(flags=0x8),
+        dict(flags=3 << 8), dict(cell_size=0.05), dict(planes=[(0.0, 0.0, 2.0, 0.0)]),
+    ]
+    for kw in bad:
+        sc2 = scenes.drop_cubes(0)
+        args = dict(gravity=sc2.gravity, mu=sc2.mu, planes=sc2.planes)
+        base = dict(dt_frame=sc2.dt_frame, substeps=sc2.substeps, iterations=sc2.iterations, radius=sc2.radius)
+        base.update({k: v for k, v in kw.items() if k in base})
+        args.update({k: v for k, v in kw.items() if k not in base})
+        pp = B.make_params(**base, **args)
+        assert B.scene_bytes(pp, sc.n, sc.n_bodies) == 0, kw
+        assert B.last_error() != ""
+    assert B.scene_bytes(p, sc.n, 0) == 0          # particles without bodies
+    assert B.scene_bytes(p, 0, 0) > 0              # an empty scene is valid
+
+
+def _create(p, x, v, m, bs, ws=None, ws_bytes=1 << 20):
+    lib = B.load_library()
+    desc = B.SceneDesc(x.shape[1], bs.shape[0] - 1, x.ctypes.data, v.ctypes.data, m.ctypes.data,
+                       bs.ctypes.data, None)
+    h = ctypes.c_void_p()
+    st = lib.pbdr_scene_create(ctypes.byref(p), ctypes.byref(desc), ws, ws_bytes, None, ctypes.byref(h))
+    return st, h
+
+
+def test_create_rejects_bad_scenes_before_any_device_call():
+    sc, p = _params()
+    x, v, m, bs = sc.x, sc.v, sc.mass, sc.body_start.copy()
+    # every failure below is detected on the host; no workspace or GPU is needed
+    st, h = _create(p, x, v, m, bs, ws=None)
+    assert st == B.ERR_WORKSPACE and not h.value
+    st, _ = _create(p, x, v, m, bs, ws=ctypes.c_void_p(0x1001))
+    assert st == B.ERR_WORKSPACE and "aligned" in B.last_error()
+    st, _ = _create(p, x, v, m, bs, ws=ctypes.c_void_p(0x1000), ws_bytes=16)
+    assert st == B.ERR_WORKSPACE
+    bad_bs = bs.copy()
+    bad_bs[3] = bad_bs[2]
+    st, _ = _create(p, x, v, m, bad_bs, ws=ctypes.c_void_p(0x1000))
+    assert st == B.ERR_INVALID_ARG and "empty" in B.last_error()
+    bad_bs = bs.copy()
+    bad_bs[-1] += 1
+    st, _ = _create(p, x, v, m, bad_bs, ws=ctypes.c_void_p(0x1000))
+    assert st == B.ERR_INVALID_ARG
+    bad_m = m.copy()
+    bad_m[5] = -1.0
+    st, _ = _create(p, x, v, bad_m, bs, ws=ctypes.c_void_p(0x1000))
+    assert st == B.ERR_INVALID_ARG and "mass" in B.last_error()
+    bad_x = x.copy()
+    bad_x[1, 7] = np.inf
+    st, _ = _create(p, bad_x, v, m, bs, ws=ctypes.c_void_p(0x1000))
+    assert st == B.ERR_INVALID_ARG and "not finite" in B.last_error()
+    big = scenes.single_body(scenes.lattice_box(11, 10, 10, 0.02), radius=0.01)
+    pb = B.params_for(big)
+    st, _ = _create(pb, big.x, big.v, big.mass, big.body_start, ws=ctypes.c_void_p(0x1000))
+    assert st == B.ERR_INVALID_ARG and "max 1024" in B.last_error()
+
+
+def test_null_handles_are_rejected():
+    lib = B.load_library()
+    assert lib.pbdr_scene_step(None, 1) == B.ERR_INVALID_ARG
+    assert lib.pbdr_scene_substep(None, 1) == B.ERR_INVALID_ARG
+    assert lib.pbdr_scene_read_state(None, None, None, 0) == B.ERR_INVALID_ARG
+    assert lib.pbdr_scene_launch_iterations(None, 1) == B.ERR_INVALID_ARG
+    lib.pbdr_scene_destroy(None)
+
+
+def test_solver_refuses_to_run_without_gpu_or_library(monkeypatch):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    sc = scenes.drop_cubes(0)
+    with pytest.raises(RuntimeError):
+        B.Solver.from_scene(sc)

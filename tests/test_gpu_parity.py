@@ -1,0 +1,292 @@
+"""GPU parity: the HIP solver (through the C ABI) against the FP64 reference.
+
+Every start state is either produced by the scene generator or by the
+reference itself (rounded to FP32); nothing the GPU computes is fed to the
+reference.  Per substep the checks are:
+
+* bit-exact: FP32 predicted positions, cell keys, (key, id) order, cell tables,
+  neighbour counts and lists;
+* displacement X_K - X_init within 1e-5 * r of the reference (before the final
+  FP32 rounding of the positions);
+* positions within 1e-5 * r + ulp32(|x|) and velocities within
+  1e-5 * r / h + 2 ulp32(|v|).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_14634_amd import binding as B
+from paper_2603_14634_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load_library()      # raises if libpbdr.so is missing
+
+
+def _hash_bits(n):
+    return int(min(28, max(10, math.ceil(math.log2(max(2 * n, 2))))))
+
+
+def _orc_params(orc, sc, flags=0, cap=32, bits=None, threads=THREADS):
+    return orc.params_for(sc, hash_bits=_hash_bits(sc.n) if bits is None else bits, nbr_cap=cap,
+                          flags=flags, threads=threads)
+
+
+def _gpu_solver(sc, flags=0, cap=32, bits=None):
+    p = B.params_for(sc, hash_bits=_hash_bits(sc.n) if bits is None else bits, nbr_cap=cap,
+                     flags=flags | B.FLAG_NO_GRAPH)
+    return B.Solver(p, sc.x, sc.v, sc.mass, sc.body_start)
+
+
+def _ulp32(a):
+    a = np.abs(np.asarray(a, dtype=np.float32))
+    return (np.spacing(a)).astype(np.float64)
+
+
+def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=None, label=""):
+    """One substep from the FP32 state (x, v) on both sides; asserts parity."""
+    import torch
+
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    print("[parity] %s n=%d bodies=%d flags=%#x" % (label or sc.name, sc.n, sc.n_bodies, flags), flush=True)
+    s = solver or _gpu_solver(sc, flags=flags, cap=cap, bits=bits)
+    s.set_state(x, v)
+    acc_t = None
+    if accel is not None:
+        acc_t = torch.tensor(np.ascontiguousarray(accel, dtype=np.float32), device="cuda")
+        s.set_accel(acc_t)
+    s.substep(1)
+    xg, vg = s.read_state()
+    dg = s.read_debug(B.DEBUG_DELTA).astype(np.float64)
+    p = _orc_params(orc, sc, flags=flags, cap=cap, bits=bits)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    # indexing: bit-exact on the reference's own FP32 prediction
+    xt_o = orc.predict32(p, x, v, accel)
+    np.testing.assert_array_equal(s.read_debug(B.DEBUG_XT), xt_o)
+    idx = orc.index(p, rest.body_of_particle(), xt_o)
+    np.testing.assert_array_equal(s.read_debug(B.DEBUG_KEYS), idx["key"])
+    np.testing.assert_array_equal(s.read_debug(B.DEBUG_SORTED), idx["sorted_id"])
+    np.testing.assert_array_equal(s.read_debug(B.DEBUG_CELL_COUNT), idx["cell_count"])
+    np.testing.assert_array_equal(s.read_debug(B.DEBUG_CELL_START), idx["cell_start"])
+    cnt = s.read_debug(B.DEBUG_NBR_COUNT)
+    np.testing.assert_array_equal(cnt, idx["nbr_count"])
+    nbr = s.read_debug(B.DEBUG_NBR)
+    stored = np.minimum(cnt, cap)
+    for slot in range(int(stored.max()) if sc.n else 0):
+        rows = np.nonzero(stored > slot)[0]
+        np.testing.assert_array_equal(nbr[slot, rows], idx["nbr"][rows, slot])
+    # physics: one substep in FP64
+    xo, vo, _ = orc.substep(p, rest, x, v, accel=None if accel is None else accel.astype(np.float64))
+    r = sc.radius
+    h = sc.dt_frame / sc.substeps
+    d_err = np.abs(dg - (xo - x.astype(np.float64)))
+    x_err = np.abs(xg.astype(np.float64) - xo)
+    v_err = np.abs(vg.astype(np.float64) - vo)
+    tol_d = 1e-5 * r
+    tol_x = 1e-5 * r + _ulp32(xo)
+    tol_v = 1e-5 * r / h + 2 * _ulp32(vo)
+    print("[parity]   max |d err| %.3g (tol %.3g)  max |v err| %.3g  contacts max %d"
+          % (d_err.max() if sc.n else 0, tol_d, v_err.max() if sc.n else 0, int(cnt.max()) if sc.n else 0),
+          flush=True)
+    assert np.all(d_err <= tol_d), "displacement error %.3g > %.3g" % (d_err.max(), tol_d)
+    assert np.all(x_err <= tol_x)
+    assert np.all(v_err <= tol_v), "velocity error %.3g" % v_err.max()
+    return s, xg, vg, int(cnt.max()) if sc.n else 0
+
+
+def _oracle_states(orc, sc, frames, threads=THREADS):
+    """FP32-rounded reference states of the scene after each number of frames."""
+    p = _orc_params(orc, sc, threads=threads)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    out, done = {}, 0
+    for f in sorted(frames):
+        if f > done:
+            x, v, _ = orc.substep(p, rest, x, v, n_substeps=(f - done) * sc.substeps)
+            done = f
+        out[f] = (x.astype(np.float32), v.astype(np.float32))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 8 lattice cubes (512 particles): along the reference trajectory
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_drop_cubes_along_reference_trajectory(orc, seed):
+    sc = scenes.drop_cubes(seed)
+    states = _oracle_states(orc, sc, [0, 60, 110, 150, 200])
+    contacts = 0
+    for f, (x, v) in states.items():
+        _, _, _, c = check_substep(orc, sc, x, v, label="drop_cubes seed %d frame %d" % (seed, f))
+        contacts = max(contacts, c)
+    lowest = min(float(xs[2].min()) for xs, _ in states.values())
+    assert lowest < sc.radius          # ground contact was exercised
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+def test_cuboid_rain_full_size(orc):
+    sc = scenes.cuboid_rain(0)
+    states = _oracle_states(orc, sc, [0, 12])
+    for f, (x, v) in states.items():
+        check_substep(orc, sc, x, v, label="cuboid_rain frame %d" % f)
+
+
+def test_dense_pile_full_size(orc):
+    sc = scenes.dense_pile(0, gap_frac=-0.05)
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, label="dense_pile 20k")
+    assert c >= 1
+
+
+# ---------------------------------------------------------------------------
+# ragged sizes and edge cases
+# ---------------------------------------------------------------------------
+
+def _touching_bodies(sizes, r=0.01, seed=0, speed=0.3, **kw):
+    """Bodies of the given particle counts (lattice balls) spawned overlapping."""
+    rng = np.random.default_rng(seed)
+    parts, vels, masses = [], [], []
+    x0 = 0.0
+    for k, n in enumerate(sizes):
+        if n == 1:
+            off = np.zeros((3, 1))
+        else:
+            a = int(math.ceil(n ** (1.0 / 3.0)))
+            off = scenes.lattice_box(a, a, a, 2 * r)[:, :n]
+            off = off - off.mean(axis=1, keepdims=True)
+        off = scenes.random_rotation(rng) @ off
+        ext = np.abs(off[0]).max() + r
+        parts.append(off + np.array([[x0 + ext], [0.0], [0.05 + np.abs(off[2]).max()]]))
+        x0 += 2 * ext - 0.6 * r
+        vels.append(rng.normal(0, speed, size=3))
+        masses.append(rng.uniform(0.01, 0.03))
+    return scenes.from_bodies(parts, vels, masses, radius=r, **kw)
+
+
+@pytest.mark.parametrize("sizes", [
+    [1],
+    [1, 1, 1],
+    [255, 256, 257],
+    [511, 513, 64, 1, 7],
+    [1024, 1000, 3],
+])
+def test_ragged_body_sizes(orc, sizes):
+    sc = _touching_bodies(sizes)
+    check_substep(orc, sc, sc.x, sc.v, label="ragged %s" % sizes)
+
+
+def test_empty_scene():
+    p = B.make_params(1.0 / 240, 4, 10, 0.01)
+    s = B.Solver(p, np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros(0, np.float32),
+                 np.zeros(1, np.int32))
+    s.step(3)
+    x, v = s.read_state()
+    assert x.shape == (3, 0)
+
+
+@pytest.mark.parametrize("flags", [B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN, B.PP_AVG_NONE])
+def test_flags_match_reference(orc, flags):
+    sc = _touching_bodies([27, 64, 8, 125], seed=3)
+    check_substep(orc, sc, sc.x, sc.v, flags=flags, label="flags %#x" % flags)
+
+
+def test_walls_friction_and_external_acceleration(orc):
+    sc = scenes.dense_pile(1, n_bodies=300, half_width=0.35, gap_frac=-0.1, speed=1.0)
+    rng = np.random.default_rng(5)
+    acc = rng.normal(0, 3.0, size=(3, sc.n)).astype(np.float32)
+    check_substep(orc, sc, sc.x, sc.v, accel=acc, label="walls + accel")
+    sc.mu = 0.0
+    check_substep(orc, sc, sc.x, sc.v, label="walls, mu = 0")
+
+
+def test_heavy_hash_aliasing(orc):
+    sc = scenes.dense_pile(2, n_bodies=400, half_width=0.5, gap_frac=-0.05)
+    check_substep(orc, sc, sc.x, sc.v, bits=10, label="k = 10 (aliased)")
+
+
+def test_capacity_overflow_is_reported(orc):
+    sc = _touching_bodies([64, 64, 64], seed=4)
+    s = _gpu_solver(sc, cap=1)
+    s.substep(1)
+    with pytest.raises(B.PbdrError) as e:
+        s.read_state()
+    assert e.value.status == B.ERR_CAPACITY
+    assert s.neighbour_stats()[0] > 1
+
+
+def test_non_finite_state_is_reported():
+    import torch
+
+    sc = _touching_bodies([8, 8])
+    s = _gpu_solver(sc)
+    x = torch.tensor(sc.x, device="cuda")
+    v = torch.tensor(sc.v, device="cuda")
+    v[0, 3] = float("nan")
+    s.set_state(x, v)               # device pointers bypass the host-side finite check
+    s.substep(1)
+    with pytest.raises(B.PbdrError) as e:
+        s.read_state()
+    assert e.value.status == B.ERR_NONFINITE
+
+
+def test_invalid_arguments_rejected_before_device_work():
+    sc = _touching_bodies([8, 8])
+    bad = B.params_for(sc)
+    bad.substeps = 0
+    with pytest.raises(B.PbdrError) as e:
+        B.Solver(bad, sc.x, sc.v, sc.mass, sc.body_start)
+    assert e.value.status == B.ERR_INVALID_ARG
+    bs = sc.body_start.copy()
+    bs[1] = bs[0]
+    with pytest.raises(B.PbdrError):
+        B.Solver(B.params_for(sc), sc.x, sc.v, sc.mass, bs)
+    m = sc.mass.copy()
+    m[0] = 0.0
+    with pytest.raises(B.PbdrError):
+        B.Solver(B.params_for(sc), sc.x, sc.v, m, sc.body_start)
+
+
+# ---------------------------------------------------------------------------
+# determinism, graph replay, checkpoint / resume
+# ---------------------------------------------------------------------------
+
+def test_bitwise_deterministic_and_graph_equals_direct_launches():
+    sc = scenes.drop_cubes(0)
+    runs = []
+    for flags in (B.FLAG_NO_GRAPH, 0, 0):
+        s = B.Solver(B.params_for(sc, flags=flags), sc.x, sc.v, sc.mass, sc.body_start)
+        s.step(150)
+        runs.append(s.read_state())
+    for x, v in runs[1:]:
+        np.testing.assert_array_equal(x, runs[0][0])
+        np.testing.assert_array_equal(v, runs[0][1])
+
+
+def test_checkpoint_resume_is_bit_identical():
+    sc = scenes.drop_cubes(2)
+    a = B.Solver(B.params_for(sc), sc.x, sc.v, sc.mass, sc.body_start)
+    a.step(100)
+    x, v = a.read_state()
+    q = a.read_rest()
+    a.step(60)
+    xa, va = a.read_state()
+    b = B.Solver(B.params_for(sc), x, v, sc.mass, sc.body_start, rest_q=q)
+    b.step(60)
+    xb, vb = b.read_state()
+    np.testing.assert_array_equal(xa, xb)
+    np.testing.assert_array_equal(va, vb)
