@@ -192,21 +192,24 @@ def polar(A: np.ndarray) -> np.ndarray:
     return r
 
 
-def pinv_sym3(S: np.ndarray, rel_tol: float = 1e-12) -> np.ndarray:
+def pinv_sym3(S: np.ndarray, cutoff: Optional[float] = None) -> np.ndarray:
+    """Pseudo-inverse dropping eigenvalues <= cutoff (default 1e-12 * trace)."""
     lib = load()
     s = _f64(S).reshape(3, 3).copy()
+    if cutoff is None:
+        cutoff = 1e-12 * float(np.trace(s))
     out = np.zeros((3, 3))
-    lib.orc_pinv_sym3(_p(s), ctypes.c_double(rel_tol), _p(out))
+    lib.orc_pinv_sym3(_p(s), ctypes.c_double(cutoff), _p(out))
     return out
 
 
-def enforce_momentum(mass, xb, vb, xa, va, h: float, flags: int = 0):
+def enforce_momentum(mass, xb, vb, xa, va, h: float, flags: int = 0, radius: float = 0.0):
     """Eqs. (4)-(5) on one body; positions/velocities are AoS [n, 3]."""
     lib = load()
     n = len(mass)
     xo = np.zeros((n, 3))
     vo = np.zeros((n, 3))
     lib.orc_enforce_momentum(ctypes.c_int32(n), _p(_f64(mass)), _p(_f64(xb)), _p(_f64(vb)),
-                             _p(_f64(xa)), _p(_f64(va)), ctypes.c_double(h), ctypes.c_uint32(flags),
-                             _p(xo), _p(vo))
+                             _p(_f64(xa)), _p(_f64(va)), ctypes.c_double(h), ctypes.c_double(radius),
+                             ctypes.c_uint32(flags), _p(xo), _p(vo))
     return xo, vo

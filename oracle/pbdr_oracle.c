@@ -333,9 +333,11 @@ void orc_polar(const double* A, double* R)
 /* Used for omega = I^-1 dL (Sec. III-C, angular momentum correction).       */
 /* Reading: a body whose inertia tensor is singular (one particle, or all    */
 /* particles on a line) gets the pseudo-inverse: eigenvalues at or below     */
-/* rel_tol * trace(I) are dropped.                                           */
+/* `cutoff` are dropped.  The caller takes the cutoff relative to the body's */
+/* own scale (see momentum_body), because the inertia tensor of a            */
+/* one-particle body is rounding noise, not zero.                            */
 /* ------------------------------------------------------------------------ */
-void orc_pinv_sym3(const double* S, double rel_tol, double* out)
+void orc_pinv_sym3(const double* S, double cutoff, double* out)
 {
     double a[3][3], Q[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
     for (int r = 0; r < 3; ++r)
@@ -381,7 +383,7 @@ void orc_pinv_sym3(const double* S, double rel_tol, double* out)
     }
     for (int k = 0; k < 3; ++k) {
         const double lam = a[k][k];
-        if (!(lam > rel_tol * tr)) continue;
+        if (!(lam > cutoff)) continue;
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) out[3 * r + c] += Q[r][k] * Q[c][k] / lam;
     }
@@ -398,7 +400,7 @@ void orc_pinv_sym3(const double* S, double rel_tol, double* out)
 /* ------------------------------------------------------------------------ */
 static void momentum_body(int32_t s, int32_t e, int32_t stride, const double* mass,
                           const double* xb, const double* vb, const double* xa, const double* va,
-                          double h, uint32_t flags, double* xo, double* vo)
+                          double h, double radius, uint32_t flags, double* xo, double* vo)
 {
     const size_t n = (size_t)stride;
     double M = 0.0, cb[3] = {0, 0, 0}, ca[3] = {0, 0, 0}, Pb[3] = {0, 0, 0}, Pa[3] = {0, 0, 0};
@@ -435,9 +437,12 @@ static void momentum_body(int32_t s, int32_t e, int32_t stride, const double* ma
     if (!(flags & ORC_NO_LIN_MOM))
         for (int k = 0; k < 3; ++k) dv[k] = (Pb[k] - Pa[k]) / M;
     if (!(flags & ORC_NO_ANG_MOM)) {
+        /* pseudo-inverse cutoff: 1e-12 of max(trace I, M (2r)^2), so that a
+           one-particle body (inertia = rounding noise) gets no angular step */
         double Ip[9], dL[3];
         for (int k = 0; k < 3; ++k) dL[k] = La[k] - Lb[k];
-        orc_pinv_sym3(I, 1e-12, Ip);
+        const double scale = fmax(I[0] + I[4] + I[8], M * 4.0 * radius * radius);
+        orc_pinv_sym3(I, 1e-12 * scale, Ip);
         for (int r = 0; r < 3; ++r) w[r] = Ip[3 * r] * dL[0] + Ip[3 * r + 1] * dL[1] + Ip[3 * r + 2] * dL[2];
     }
     for (int32_t i = s; i < e; ++i) {
@@ -453,7 +458,7 @@ static void momentum_body(int32_t s, int32_t e, int32_t stride, const double* ma
 }
 
 void orc_enforce_momentum(int32_t n, const double* mass, const double* xb, const double* vb,
-                          const double* xa, const double* va, double h, uint32_t flags,
+                          const double* xa, const double* va, double h, double radius, uint32_t flags,
                           double* x_out, double* v_out)
 {
     if (n <= 0) return;
@@ -469,7 +474,7 @@ void orc_enforce_momentum(int32_t n, const double* mass, const double* xb, const
             sxa[(size_t)k * n + i] = xa[3 * i + k];
             sva[(size_t)k * n + i] = va[3 * i + k];
         }
-    momentum_body(0, n, n, mass, sxb, svb, sxa, sva, h, flags, sxo, svo);
+    momentum_body(0, n, n, mass, sxb, svb, sxa, sva, h, radius, flags, sxo, svo);
     for (int32_t i = 0; i < n; ++i)
         for (int k = 0; k < 3; ++k) {
             x_out[3 * i + k] = sxo[(size_t)k * n + i];
@@ -662,7 +667,7 @@ int32_t orc_substep(const orc_params* p, int32_t n, int32_t nb, const int32_t* b
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthr)
             for (int32_t b = 0; b < nb; ++b)
                 momentum_body(body_start[b], body_start[b + 1], n, mass, Xb, Vb, Xa, Va, h,
-                              p->flags, X, V);
+                              p->radius, p->flags, X, V);
         }
     }
     memcpy(x, X, n3 * sizeof(double));

@@ -68,13 +68,13 @@ int32_t orc_index(int32_t n, const orc_params* p, const int32_t* body, const flo
 /* Rotation part of A (row-major 3x3): the proper rotation maximising tr(R^T A). */
 void orc_polar(const double* A, double* R);
 
-/* Symmetric 3x3 pseudo-inverse with eigenvalue cutoff rel_tol * trace. */
-void orc_pinv_sym3(const double* S, double rel_tol, double* out);
+/* Symmetric 3x3 pseudo-inverse dropping eigenvalues <= cutoff. */
+void orc_pinv_sym3(const double* S, double cutoff, double* out);
 
 /* Momentum conservation constraint, Eqs. (4)-(5), for one body of n particles
- * (AoS [n][3] arrays).  Writes the corrected positions and velocities. */
+ * (AoS [n][3] arrays) of radius r.  Writes the corrected positions and velocities. */
 void orc_enforce_momentum(int32_t n, const double* mass, const double* xb, const double* vb,
-                          const double* xa, const double* va, double h, uint32_t flags,
+                          const double* xa, const double* va, double h, double radius, uint32_t flags,
                           double* x_out, double* v_out);
 
 /* One substep (Alg. 1) on the state x, v (SoA [3][n], updated in place).

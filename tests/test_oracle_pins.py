@@ -116,6 +116,30 @@ def test_pair_contact_splits_penetration_by_inverse_mass(orc, m1, m2):
     assert m1 * v[0, 0] + m2 * v[0, 1] == pytest.approx(0.0, abs=1e-12)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_one_particle_bodies_move_only_by_contact(orc, seed):
+    # three one-particle bodies on the x axis, overlapping by pen: a one-particle
+    # body has no shape-matching goal offset and no rotational inertia, so only
+    # the pair corrections act, along x; the middle one has two neighbours.
+    rng = np.random.default_rng(seed)
+    r, pen = 0.01, 0.006
+    m = rng.uniform(0.005, 0.05, size=3)
+    xs = np.array([0.0, 2 * r - pen, 2 * (2 * r - pen)]) + rng.uniform(-1, 1)
+    sc = scenes.from_bodies([np.array([[x], [0.25], [0.5]]) for x in xs], [np.zeros(3)] * 3, list(m),
+                            radius=r, gravity=(0.0, 0.0, 0.0), planes=(), mu=0.0, iterations=1)
+    x, v, mx, _, _ = _run(orc, sc)
+    assert mx == 2
+    m = sc.mass.astype(np.float64)                        # stored in FP32
+    x0 = sc.x.astype(np.float64)
+    np.testing.assert_array_equal(x[1:], x0[1:])          # nothing moves in y or z
+    gaps = np.diff(x0[0])
+    corr = [m[1] / (m[0] + m[1]) * (2 * r - gaps[0]) / 2, m[2] / (m[1] + m[2]) * (2 * r - gaps[1]) / 2]
+    expect = x0[0] + np.array([-corr[0],
+                               m[0] / (m[0] + m[1]) * (2 * r - gaps[0]) / 2 - corr[1],
+                               m[1] / (m[1] + m[2]) * (2 * r - gaps[1]) / 2])
+    np.testing.assert_allclose(x[0], expect, rtol=0, atol=1e-15)
+
+
 def test_symmetric_averaging_conserves_total_momentum(orc):
     rng = np.random.default_rng(7)
     r = 0.05
@@ -248,7 +272,7 @@ def test_momentum_constraint_restores_pre_shape_matching_momentum(orc, flags):
     m = rng.uniform(0.2, 2.0, size=n)
     xb, vb = rng.normal(size=(n, 3)), rng.normal(size=(n, 3))
     xa, va = xb + 0.1 * rng.normal(size=(n, 3)), vb + rng.normal(size=(n, 3))
-    x, v = orc.enforce_momentum(m, xb, vb, xa, va, h, flags)
+    x, v = orc.enforce_momentum(m, xb, vb, xa, va, h, flags, radius=0.01)
     _, Pb, Lb = _mom(m, xb, vb)
     ca, Pa, La = _mom(m, xa, va)
     P = (m[:, None] * v).sum(axis=0)
