@@ -436,19 +436,20 @@ __device__ void polar_rotation(const float* A, float* R)
 }
 
 // omega = I^+ L for a symmetric positive semi-definite inertia tensor
-// (xx, yy, zz, xy, xz, yz): the closed-form inverse when I is well
-// conditioned, otherwise an eigen-decomposition dropping eigenvalues at or
-// below 1e-6 of the trace (one particle, or particles on a line).
-__device__ void solve_inertia(const float* I6, const float* L, float* w)
+// (xx, yy, zz, xy, xz, yz).  `scale` = max(trace I, M (2r)^2) sets what counts
+// as zero: the inertia of a one-particle body is rounding noise, and a body
+// whose particles lie on a line has one vanishing eigenvalue.  Well
+// conditioned tensors use the closed-form inverse; otherwise an
+// eigen-decomposition drops eigenvalues at or below 1e-6 * scale.
+__device__ void solve_inertia(const float* I6, const float* L, float scale, float* w)
 {
     const float I[9] = {I6[0], I6[3], I6[4], I6[3], I6[1], I6[5], I6[4], I6[5], I6[2]};
-    const float tr = I6[0] + I6[1] + I6[2];
     w[0] = w[1] = w[2] = 0.0f;
-    if (!(tr > 0.0f)) return;
+    if (!(scale > 0.0f)) return;
     float C[9];
     cof3(I, C);
     const float det = I[0] * C[0] + I[1] * C[1] + I[2] * C[2];
-    const float t3 = tr * (1.0f / 3.0f);
+    const float t3 = scale * (1.0f / 3.0f);
     if (det > 1e-3f * t3 * t3 * t3) {
         const float id = 1.0f / det;    // I^-1 = cof^T / det, cof symmetric here
         for (int r = 0; r < 3; ++r) w[r] = (C[3 * r] * L[0] + C[3 * r + 1] * L[1] + C[3 * r + 2] * L[2]) * id;
@@ -459,7 +460,7 @@ __device__ void solve_inertia(const float* I6, const float* L, float* w)
     sym_eig3(a, Q);
     for (int k = 0; k < 3; ++k) {
         const float lam = a[4 * k];
-        if (!(lam > 1e-6f * tr)) continue;
+        if (!(lam > 1e-6f * scale)) continue;
         const float proj = (Q[k] * L[0] + Q[3 + k] * L[1] + Q[6 + k] * L[2]) / lam;
         for (int r = 0; r < 3; ++r) w[r] += proj * Q[3 * r + k];
     }
@@ -679,7 +680,8 @@ __global__ void __launch_bounds__(kBlock) k_iterate(Scene s, StepConsts c, int s
                 I6[3] = S[21] + M * ca[0] * ca[1];
                 I6[4] = S[22] + M * ca[0] * ca[2];
                 I6[5] = S[23] + M * ca[1] * ca[2];
-                solve_inertia(I6, dL, w);
+                const float scale = fmaxf(I6[0] + I6[1] + I6[2], M * c.two_r * c.two_r);
+                solve_inertia(I6, dL, scale, w);
             }
             for (int j = 0; j < 3; ++j) {
                 bc[j] = dv[j];

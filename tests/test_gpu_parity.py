@@ -157,12 +157,14 @@ def test_dense_pile_full_size(orc):
 # ragged sizes and edge cases
 # ---------------------------------------------------------------------------
 
-def _touching_bodies(sizes, r=0.01, seed=0, speed=0.3, **kw):
-    """Bodies of the given particle counts (lattice balls) spawned overlapping."""
+def _touching_bodies(sizes, r=0.01, seed=0, speed=0.3, pen=0.6, **kw):
+    """Bodies of the given particle counts (partial lattice cubes, random
+    orientation) in a row along x, each moved so that its closest particle pair
+    with the previous body is 2r - pen*r apart."""
     rng = np.random.default_rng(seed)
     parts, vels, masses = [], [], []
-    x0 = 0.0
-    for k, n in enumerate(sizes):
+    prev = None
+    for n in sizes:
         if n == 1:
             off = np.zeros((3, 1))
         else:
@@ -170,9 +172,16 @@ def _touching_bodies(sizes, r=0.01, seed=0, speed=0.3, **kw):
             off = scenes.lattice_box(a, a, a, 2 * r)[:, :n]
             off = off - off.mean(axis=1, keepdims=True)
         off = scenes.random_rotation(rng) @ off
-        ext = np.abs(off[0]).max() + r
-        parts.append(off + np.array([[x0 + ext], [0.0], [0.05 + np.abs(off[2]).max()]]))
-        x0 += 2 * ext - 0.6 * r
+        pts = off + np.array([[0.0], [0.0], [0.1 + np.abs(off[2]).max()]])
+        if prev is not None:
+            pts[0] += prev[0].max() + 2 * r - pts[0].min() + 4 * r
+            for _ in range(200):
+                d = np.sqrt(((pts[:, :, None] - prev[:, None, :]) ** 2).sum(axis=0)).min()
+                if abs(d - (2 - pen) * r) < 1e-4 * r:
+                    break
+                pts[0] -= d - (2 - pen) * r
+        parts.append(pts)
+        prev = pts
         vels.append(rng.normal(0, speed, size=3))
         masses.append(rng.uniform(0.01, 0.03))
     return scenes.from_bodies(parts, vels, masses, radius=r, **kw)
@@ -187,7 +196,8 @@ def _touching_bodies(sizes, r=0.01, seed=0, speed=0.3, **kw):
 ])
 def test_ragged_body_sizes(orc, sizes):
     sc = _touching_bodies(sizes)
-    check_substep(orc, sc, sc.x, sc.v, label="ragged %s" % sizes)
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, label="ragged %s" % sizes)
+    assert c >= (1 if len(sizes) > 1 else 0)
 
 
 def test_empty_scene():
@@ -202,7 +212,8 @@ def test_empty_scene():
 @pytest.mark.parametrize("flags", [B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN, B.PP_AVG_NONE])
 def test_flags_match_reference(orc, flags):
     sc = _touching_bodies([27, 64, 8, 125], seed=3)
-    check_substep(orc, sc, sc.x, sc.v, flags=flags, label="flags %#x" % flags)
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, flags=flags, label="flags %#x" % flags)
+    assert c >= 1
 
 
 def test_walls_friction_and_external_acceleration(orc):
@@ -220,13 +231,15 @@ def test_heavy_hash_aliasing(orc):
 
 
 def test_capacity_overflow_is_reported(orc):
-    sc = _touching_bodies([64, 64, 64], seed=4)
-    s = _gpu_solver(sc, cap=1)
+    # two interpenetrating lattices, offset by half a spacing: 8 neighbours each
+    off = scenes.lattice_box(4, 4, 4, 0.02)
+    sc = scenes.from_bodies([off + 0.5, off + 0.5 + 0.01], [np.zeros(3)] * 2, [0.01, 0.01], radius=0.01)
+    s = _gpu_solver(sc, cap=4)
     s.substep(1)
     with pytest.raises(B.PbdrError) as e:
         s.read_state()
     assert e.value.status == B.ERR_CAPACITY
-    assert s.neighbour_stats()[0] > 1
+    assert s.neighbour_stats()[0] == 8
 
 
 def test_non_finite_state_is_reported():
