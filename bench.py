@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--iter-launches", type=int, default=200, help="launches timed for the roofline")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB (3 times), the "
+                         "reference for scaling HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -115,6 +118,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: %d bytes read and %d bytes written per launch" % (nbytes, nbytes),
+              file=sys.stderr, flush=True)
+        del src, dst
     sc = scenes.WORKLOADS[args.workload](args.seed)
     print("[bench] workload %s: %d particles, %d bodies" % (sc.name, sc.n, sc.n_bodies), file=sys.stderr,
           flush=True)

@@ -128,7 +128,8 @@ typedef struct {
     double substep_h;
     double search_radius;
     double cell_size;
-    int32_t particles_per_thread; /* iteration-kernel register tiling */
+    int32_t waves_per_block;      /* iteration kernel: 64-lane waves per workgroup */
+    int32_t iteration_blocks;     /* iteration kernel: workgroups per launch */
     int32_t max_body_particles;
     size_t workspace_bytes;
 } pbdr_scene_info;

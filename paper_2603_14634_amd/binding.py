@@ -72,7 +72,8 @@ class SceneInfo(ctypes.Structure):
         ("substep_h", ctypes.c_double),
         ("search_radius", ctypes.c_double),
         ("cell_size", ctypes.c_double),
-        ("particles_per_thread", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32),
+        ("iteration_blocks", ctypes.c_int32),
         ("max_body_particles", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_size_t),
     ]

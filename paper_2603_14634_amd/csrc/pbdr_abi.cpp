@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -92,8 +93,18 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
 
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt, sbody, key, rank,
-        sorted_raw, sorted, nbr_n, nbr, cell_count, cell_start, tile_sums, body_rot, counters, total;
+        sorted_raw, sorted, nbr_n, nbr, cell_count, cell_local, tile_off, tile_sums, scan_done, cell_body, body_rot,
+        counters, wave_body, body_wave0, block_body, total;
 };
+
+// Upper bound on the padded wave count of the iteration kernel's body packing:
+// each body needs ceil(n_b / 64) <= n_b / 64 + 1 waves; greedy packing into
+// workgroups of W waves wastes less than half of every closed workgroup, and
+// the last workgroup is padded by at most W - 1 waves.
+size_t max_iteration_waves(int32_t n, int32_t nb)
+{
+    return 2 * ((size_t)n / 64 + (size_t)nb + 1) + pbdr::kMaxWaves;
+}
 
 Layout make_layout(int32_t n, int32_t nb, int k, int cap)
 {
@@ -127,10 +138,16 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
     L.cell_count = take(4 * T);
-    L.cell_start = take(4 * T);
+    L.cell_local = take(4 * T);
+    L.tile_off = take(4 * tiles);
     L.tile_sums = take(4 * tiles);
+    L.scan_done = take(4);
+    L.cell_body = take(4 * T);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
+    L.wave_body = take(4 * max_iteration_waves(n, nb));
+    L.body_wave0 = take(4 * B);
+    L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 1));
     L.total = off;
     return L;
 }
@@ -148,7 +165,6 @@ struct pbdr_scene {
     hipGraphExec_t exec = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
-    int ppt = 1;
     int max_body = 0;
     bool stepped = false;
 };
@@ -237,10 +253,16 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
     d.cell_count = (uint32_t*)(w + L.cell_count);
-    d.cell_start = (uint32_t*)(w + L.cell_start);
+    d.cell_local = (uint32_t*)(w + L.cell_local);
+    d.tile_off = (uint32_t*)(w + L.tile_off);
     d.tile_sums = (uint32_t*)(w + L.tile_sums);
+    d.scan_done = (uint32_t*)(w + L.scan_done);
+    d.cell_body = (int32_t*)(w + L.cell_body);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
+    d.wave_body = (const int32_t*)(w + L.wave_body);
+    d.body_wave0 = (const int32_t*)(w + L.body_wave0);
+    d.block_body = (const int32_t*)(w + L.block_body);
     d.accel = nullptr;
 }
 
@@ -253,7 +275,7 @@ pbdr_status check_host_finite(const float* a, size_t count, const char* what)
 
 pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
 {
-    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->ppt, substeps_total, s->stream);
+    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, substeps_total, s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     s->stepped = true;
     return PBDR_OK;
@@ -264,8 +286,7 @@ pbdr_status ensure_graph(pbdr_scene* s)
     if (s->exec) return PBDR_OK;
     if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->ppt, s->res.p.substeps,
-                                          s->cap_stream);
+    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->res.p.substeps, s->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -342,9 +363,43 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     s->ws = (char*)dev_workspace;
     s->ws_bytes = ws_bytes;
     s->max_body = max_body;
-    s->ppt = max_body <= pbdr::kBlock ? 1 : (max_body <= 2 * pbdr::kBlock ? 2 : 4);
     fill_device(s, n, nb);
     fill_consts(s);
+
+    // iteration-kernel packing: each body takes ceil(n_b / 64) consecutive
+    // waves; bodies are packed greedily, in order, into workgroups of W waves
+    const int W = std::max(4, (max_body + 63) / 64);
+    std::vector<int32_t> wave_body, body_wave0((size_t)nb);
+    for (int32_t b = 0; b < nb; ++b) {
+        const int need = (desc->body_start[b + 1] - desc->body_start[b] + 63) / 64;
+        const int used = (int)(wave_body.size() % (size_t)W);
+        if (used + need > W) wave_body.resize(wave_body.size() + (size_t)(W - used), -1);
+        body_wave0[(size_t)b] = (int32_t)wave_body.size();
+        wave_body.resize(wave_body.size() + (size_t)need, b);
+    }
+    if (wave_body.size() % (size_t)W) wave_body.resize(wave_body.size() + (size_t)W - wave_body.size() % (size_t)W, -1);
+    if (wave_body.size() > max_iteration_waves(n, nb)) {
+        delete s;
+        return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
+    }
+    s->dev.waves_per_block = W;
+    s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
+    std::vector<int32_t> block_body(2 * (size_t)s->dev.n_iter_blocks);   // first body, body count
+    for (int32_t blk = 0; blk < s->dev.n_iter_blocks; ++blk) {
+        int32_t first = -1, last = -1;
+        for (int w = 0; w < W; ++w) {
+            const int32_t bb = wave_body[(size_t)blk * W + w];
+            if (bb < 0) continue;
+            if (first < 0) first = bb;
+            last = bb;
+        }
+        block_body[2 * (size_t)blk] = first < 0 ? 0 : first;
+        block_body[2 * (size_t)blk + 1] = first < 0 ? 0 : last - first + 1;
+    }
+    if ((size_t)s->dev.n_iter_blocks > max_iteration_waves(n, nb) / 4 + 1) {   // W >= 4
+        delete s;
+        return fail(PBDR_ERR_INVALID_ARG, "internal: block table exceeds its bound");
+    }
 
     // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
     std::vector<int32_t> body((size_t)n);
@@ -378,8 +433,12 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         if (e == hipSuccess) e = h2d(lay.q, q.data(), 12 * (size_t)n);
         if (e == hipSuccess) e = h2d(lay.body_start, desc->body_start, 4 * ((size_t)nb + 1));
         if (e == hipSuccess) e = h2d(lay.body_mass, bmass.data(), 4 * (size_t)nb);
+        if (e == hipSuccess) e = h2d(lay.wave_body, wave_body.data(), 4 * wave_body.size());
+        if (e == hipSuccess) e = h2d(lay.body_wave0, body_wave0.data(), 4 * (size_t)nb);
+        if (e == hipSuccess) e = h2d(lay.block_body, block_body.data(), 4 * block_body.size());
     }
     if (e == hipSuccess) e = pbdr::enqueue_clear_counters(s->dev, s->stream);
+    if (e == hipSuccess) e = pbdr::enqueue_init_tables(s->dev, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;
@@ -419,7 +478,7 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
     if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
-    hipError_t e = pbdr::enqueue_iterations(s->dev, s->consts, s->ppt, n_launches, s->stream);
+    hipError_t e = pbdr::enqueue_iterations(s->dev, s->consts, n_launches, s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return PBDR_OK;
 }
@@ -500,8 +559,21 @@ pbdr_status pbdr_scene_read_debug(pbdr_scene* s, int32_t what, void* dst)
     case PBDR_DEBUG_XT: off = s->lay.xt; bytes = 12 * N; break;
     case PBDR_DEBUG_KEYS: off = s->lay.key; bytes = 4 * N; break;
     case PBDR_DEBUG_SORTED: off = s->lay.sorted; bytes = 4 * N; break;
-    case PBDR_DEBUG_CELL_START: off = s->lay.cell_start; bytes = 4 * T; break;
-    case PBDR_DEBUG_CELL_COUNT: off = s->lay.cell_count; bytes = 4 * T; break;
+    case PBDR_DEBUG_CELL_START:
+    case PBDR_DEBUG_CELL_COUNT: {   // start(k) = tile-local prefix + tile offset; counts from differences
+        const size_t tiles = (T + pbdr::kScanTile - 1) / pbdr::kScanTile;
+        std::vector<uint32_t> loc(T), off(tiles);
+        HIP_TRY(hipMemcpyAsync(loc.data(), s->ws + s->lay.cell_local, 4 * T, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(off.data(), s->ws + s->lay.tile_off, 4 * tiles, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        uint32_t* out = (uint32_t*)dst;
+        for (size_t k = 0; k < T; ++k) {
+            const uint32_t st = loc[k] + off[k / pbdr::kScanTile];
+            const uint32_t nx = k + 1 < T ? loc[k + 1] + off[(k + 1) / pbdr::kScanTile] : (uint32_t)N;
+            out[k] = what == PBDR_DEBUG_CELL_START ? st : nx - st;
+        }
+        return PBDR_OK;
+    }
     case PBDR_DEBUG_NBR_COUNT: off = s->lay.nbr_n; bytes = 4 * N; break;
     case PBDR_DEBUG_NBR: off = s->lay.nbr; bytes = 4 * N * (size_t)s->res.cap; break;
     case PBDR_DEBUG_DELTA:
@@ -525,7 +597,8 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->substep_h = s->res.h;
     out->search_radius = s->res.rs;
     out->cell_size = s->res.a;
-    out->particles_per_thread = s->ppt;
+    out->waves_per_block = s->dev.waves_per_block;
+    out->iteration_blocks = s->dev.n_iter_blocks;
     out->max_body_particles = s->max_body;
     out->workspace_bytes = s->lay.total;
     return PBDR_OK;

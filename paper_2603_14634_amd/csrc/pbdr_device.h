@@ -7,12 +7,13 @@
 namespace pbdr {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kMaxWaves = 16;    // iteration kernel: waves per workgroup (bodies <= 1024 particles)
 constexpr int kMaxPlanes = 8;
 constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
-constexpr int kScanItems = 8;    // cell-table scan: counts per thread
+constexpr int kScanItems = 4;    // cell-table scan: counts per thread
 constexpr int kScanTile = kBlock * kScanItems;
 
-enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u };
+enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u };
 
 enum : uint32_t {
     kFlagStdVelocity = 0x1u,
@@ -57,6 +58,11 @@ struct Scene {
     const float* q;           // [3][N] rest offsets
     const int32_t* body_start;// [B+1]
     const float* body_mass;   // [B]
+    const int32_t* wave_body; // [n_iter_blocks * waves_per_block] body of each wave, -1 = idle
+    const int32_t* body_wave0;// [B] first (global) wave of each body
+    const int32_t* block_body;// [2 * n_iter_blocks] first body and body count of each workgroup
+    int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
+    int32_t n_iter_blocks;
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
     float* xt;                // [3][N] FP32 predicted positions
@@ -68,23 +74,27 @@ struct Scene {
     uint32_t* sorted;         // [N] ids sorted by (key, id)
     uint32_t* nbr_n;          // [N] neighbour-list length
     uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
-    uint32_t* cell_count;     // [T]
-    uint32_t* cell_start;     // [T]
-    uint32_t* tile_sums;      // [n_scan_tiles]
+    uint32_t* cell_count;     // [T] per-key counts (zero outside a substep)
+    uint32_t* cell_local;     // [T] exclusive prefix of the counts within each scan tile
+    uint32_t* tile_off;       // [n_scan_tiles] exclusive prefix of the tile totals
+    uint32_t* tile_sums;      // [n_scan_tiles] tile totals
+    uint32_t* scan_done;      // tiles finished (the last one scans the tile totals)
+    int32_t* cell_body;       // [T] body of all particles of a key, -1 empty, -2 mixed
     float* body_rot;          // [B][9] last rotation of shape matching
     Counters* counters;
     const float* accel;       // [3][N] external acceleration or nullptr
 };
 
-// Enqueues `count` substeps.  iterations = K; ppt = particles per thread of
-// the iteration kernel (1, 2 or 4).
-hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int ppt,
-                            int count, hipStream_t stream);
+// Enqueues `count` substeps of K = iterations solver iterations.
+hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream);
 
 // Enqueues `count` launches of the iteration kernel alone (measurement).
-hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int ppt, int count, hipStream_t stream);
+hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream);
 
 // Clears the latched counters.
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream);
+
+// Zeroes the per-key counts and marks every key empty (once, at creation).
+hipError_t enqueue_init_tables(const Scene& s, hipStream_t stream);
 
 }  // namespace pbdr
