@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed frames")
     ap.add_argument("--workload", default="cuboid_rain_1000")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--hash-bits", type=int, default=0, help="override the hash-grid key bits (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--iter-launches", type=int, default=200, help="launches timed for the roofline")
@@ -131,7 +132,7 @@ def main():
     sc = scenes.WORKLOADS[args.workload](args.seed)
     print("[bench] workload %s: %d particles, %d bodies" % (sc.name, sc.n, sc.n_bodies), file=sys.stderr,
           flush=True)
-    solver = B.Solver.from_scene(sc)
+    solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits)
     stream = solver.stream
     solver.step(args.warmup)
     torch.cuda.synchronize()

@@ -96,6 +96,9 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libpbdr.so is not built (expected at %s); run "
                            "`python -m paper_2603_14634_amd.build`" % path)
+    # torch first: its HIP runtime has the same soname as the one libpbdr links,
+    # so the library then binds to it and the process holds a single runtime
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.pbdr_abi_version.restype = i32

@@ -83,7 +83,7 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
         r.k = p.hash_bits;
     } else {
         int k = 10;
-        while (k < kMaxHashBits && (1ll << k) < 2ll * (long long)n) ++k;
+        while (k < kMaxHashBits && (1ll << k) < 4ll * (long long)n) ++k;
         r.k = k;
     }
     r.cap = p.nbr_cap ? p.nbr_cap : 32;
@@ -93,8 +93,8 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
 
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt, sbody, key, rank,
-        sorted_raw, sorted, nbr_n, nbr, cell_count, cell_local, tile_off, tile_sums, scan_done, cell_body, body_rot,
-        counters, wave_body, body_wave0, block_body, total;
+        sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, scan_ticket, body_rot, counters, wave_body,
+        body_wave0, block_body, body_mq, total;
 };
 
 // Upper bound on the padded wave count of the iteration kernel's body packing:
@@ -138,16 +138,15 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
     L.cell_count = take(4 * T);
-    L.cell_local = take(4 * T);
-    L.tile_off = take(4 * tiles);
-    L.tile_sums = take(4 * tiles);
-    L.scan_done = take(4);
-    L.cell_body = take(4 * T);
+    L.cells = take(16 * T);
+    L.tile_state = take(8 * tiles);
+    L.scan_ticket = take(4);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
     L.wave_body = take(4 * max_iteration_waves(n, nb));
     L.body_wave0 = take(4 * B);
     L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 1));
+    L.body_mq = take(12 * B);
     L.total = off;
     return L;
 }
@@ -191,6 +190,7 @@ pbdr_status latched(pbdr_scene* s)
     pbdr::Counters c;
     pbdr_status st = read_counters(s, &c);
     if (st != PBDR_OK) return st;
+    if (c.err & pbdr::kErrInternal) return fail(PBDR_ERR_DEVICE, "a device-side wait gave up (cell-table scan)");
     if (c.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity became non-finite");
     if (c.err & pbdr::kErrCapacity)
         return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", c.max_nbr, s->res.cap);
@@ -253,16 +253,15 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
     d.cell_count = (uint32_t*)(w + L.cell_count);
-    d.cell_local = (uint32_t*)(w + L.cell_local);
-    d.tile_off = (uint32_t*)(w + L.tile_off);
-    d.tile_sums = (uint32_t*)(w + L.tile_sums);
-    d.scan_done = (uint32_t*)(w + L.scan_done);
-    d.cell_body = (int32_t*)(w + L.cell_body);
+    d.cells = (uint4*)(w + L.cells);
+    d.tile_state = (unsigned long long*)(w + L.tile_state);
+    d.scan_ticket = (uint32_t*)(w + L.scan_ticket);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
     d.wave_body = (const int32_t*)(w + L.wave_body);
     d.body_wave0 = (const int32_t*)(w + L.body_wave0);
     d.block_body = (const int32_t*)(w + L.block_body);
+    d.body_mq = (const float*)(w + L.body_mq);
     d.accel = nullptr;
 }
 
@@ -403,7 +402,7 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
 
     // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
     std::vector<int32_t> body((size_t)n);
-    std::vector<float> bmass((size_t)nb), q(3 * (size_t)n);
+    std::vector<float> bmass((size_t)nb), q(3 * (size_t)n), bmq(3 * (size_t)nb);
     for (int32_t b = 0; b < nb; ++b) {
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i) {
@@ -414,11 +413,14 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         }
         bmass[(size_t)b] = (float)M;
         for (int k = 0; k < 3; ++k) cm[k] /= M;
+        double mq[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i)
             for (int k = 0; k < 3; ++k) {
                 const size_t j = (size_t)k * n + i;
                 q[j] = desc->rest_q ? desc->rest_q[j] : (float)((double)desc->x[j] - cm[k]);
+                mq[k] += (double)desc->mass[i] * (double)q[j];   // of the stored FP32 offsets
             }
+        for (int k = 0; k < 3; ++k) bmq[3 * (size_t)b + k] = (float)mq[k];
     }
     auto h2d = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
         if (bytes == 0) return hipSuccess;
@@ -436,6 +438,7 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         if (e == hipSuccess) e = h2d(lay.wave_body, wave_body.data(), 4 * wave_body.size());
         if (e == hipSuccess) e = h2d(lay.body_wave0, body_wave0.data(), 4 * (size_t)nb);
         if (e == hipSuccess) e = h2d(lay.block_body, block_body.data(), 4 * block_body.size());
+        if (e == hipSuccess) e = h2d(lay.body_mq, bmq.data(), 12 * (size_t)nb);
     }
     if (e == hipSuccess) e = pbdr::enqueue_clear_counters(s->dev, s->stream);
     if (e == hipSuccess) e = pbdr::enqueue_init_tables(s->dev, s->stream);
@@ -560,18 +563,13 @@ pbdr_status pbdr_scene_read_debug(pbdr_scene* s, int32_t what, void* dst)
     case PBDR_DEBUG_KEYS: off = s->lay.key; bytes = 4 * N; break;
     case PBDR_DEBUG_SORTED: off = s->lay.sorted; bytes = 4 * N; break;
     case PBDR_DEBUG_CELL_START:
-    case PBDR_DEBUG_CELL_COUNT: {   // start(k) = tile-local prefix + tile offset; counts from differences
-        const size_t tiles = (T + pbdr::kScanTile - 1) / pbdr::kScanTile;
-        std::vector<uint32_t> loc(T), off(tiles);
-        HIP_TRY(hipMemcpyAsync(loc.data(), s->ws + s->lay.cell_local, 4 * T, hipMemcpyDeviceToHost, s->stream));
-        HIP_TRY(hipMemcpyAsync(off.data(), s->ws + s->lay.tile_off, 4 * tiles, hipMemcpyDeviceToHost, s->stream));
+    case PBDR_DEBUG_CELL_COUNT: {   // fields of the per-key entries
+        std::vector<uint32_t> e(4 * T);
+        HIP_TRY(hipMemcpyAsync(e.data(), s->ws + s->lay.cells, 16 * T, hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         uint32_t* out = (uint32_t*)dst;
-        for (size_t k = 0; k < T; ++k) {
-            const uint32_t st = loc[k] + off[k / pbdr::kScanTile];
-            const uint32_t nx = k + 1 < T ? loc[k + 1] + off[(k + 1) / pbdr::kScanTile] : (uint32_t)N;
-            out[k] = what == PBDR_DEBUG_CELL_START ? st : nx - st;
-        }
+        const int f = what == PBDR_DEBUG_CELL_START ? 0 : 1;
+        for (size_t k = 0; k < T; ++k) out[k] = e[4 * k + f];
         return PBDR_OK;
     }
     case PBDR_DEBUG_NBR_COUNT: off = s->lay.nbr_n; bytes = 4 * N; break;

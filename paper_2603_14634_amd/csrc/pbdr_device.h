@@ -10,7 +10,7 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kMaxWaves = 16;    // iteration kernel: waves per workgroup (bodies <= 1024 particles)
 constexpr int kMaxPlanes = 8;
 constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
-constexpr int kScanItems = 4;    // cell-table scan: counts per thread
+constexpr int kScanItems = 16;   // cell-table scan: counts per thread
 constexpr int kScanTile = kBlock * kScanItems;
 
 enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u };
@@ -61,6 +61,7 @@ struct Scene {
     const int32_t* wave_body; // [n_iter_blocks * waves_per_block] body of each wave, -1 = idle
     const int32_t* body_wave0;// [B] first (global) wave of each body
     const int32_t* block_body;// [2 * n_iter_blocks] first body and body count of each workgroup
+    const float* body_mq;     // [B][3] sum of m q over the body (rest frame, ~0)
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
     float* dl[2];             // [3][N] X_i - X_init, double buffered
@@ -75,11 +76,10 @@ struct Scene {
     uint32_t* nbr_n;          // [N] neighbour-list length
     uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
     uint32_t* cell_count;     // [T] per-key counts (zero outside a substep)
-    uint32_t* cell_local;     // [T] exclusive prefix of the counts within each scan tile
-    uint32_t* tile_off;       // [n_scan_tiles] exclusive prefix of the tile totals
-    uint32_t* tile_sums;      // [n_scan_tiles] tile totals
-    uint32_t* scan_done;      // tiles finished (the last one scans the tile totals)
-    int32_t* cell_body;       // [T] body of all particles of a key, -1 empty, -2 mixed
+    uint4* cells;             // [T] per key: first sorted slot, count, body signature
+                              //     (the one body of all its particles, -1 empty, -2 mixed), 0
+    unsigned long long* tile_state;  // [n_scan_tiles] scan look-back: (status << 32) | value
+    uint32_t* scan_ticket;    // order in which scan tiles start
     float* body_rot;          // [B][9] last rotation of shape matching
     Counters* counters;
     const float* accel;       // [3][N] external acceleration or nullptr
@@ -88,7 +88,8 @@ struct Scene {
 // Enqueues `count` substeps of K = iterations solver iterations.
 hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream);
 
-// Enqueues `count` launches of the iteration kernel alone (measurement).
+// Enqueues `count` launches of the iteration kernel alone (measurement); all
+// but the first continue from the rotation of the launch before.
 hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream);
 
 // Clears the latched counters.

@@ -9,7 +9,7 @@
 //                  the second substep of a call on, it first folds the previous
 //                  substep's result into the state (x += dX, v = V)
 //   scan           exclusive prefix sum of the per-key counts in one launch
-//                  (tile prefixes; the last tile scans the tile totals);
+//                  (decoupled look-back) -> per-key first slot and count;
 //                  re-zeroes the counts
 //   scatter        particles grouped by key, with sorted copies of the FP32
 //                  predicted positions and body ids, and each key's body
@@ -122,6 +122,8 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 {
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
+    if (i == 0) *s.scan_ticket = 0u;
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     float xt[3];
@@ -154,9 +156,9 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the cell counts in one launch: every tile writes its local
-// prefix and total; the last tile to finish scans the totals.  A key's start
-// is cell_local[k] + tile_off[k / kScanTile].
+// exclusive scan of the cell counts in one launch (decoupled look-back: each
+// tile publishes its total at once and its inclusive prefix as soon as it is
+// known; a wave inspects 64 predecessors per step)
 // ---------------------------------------------------------------------------
 
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot, uint32_t* total)
@@ -174,66 +176,79 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot, 
         if (w < wave) before += wave_tot[w];
         all += wave_tot[w];
     }
-    __syncthreads();          // wave_tot may be reused by the caller
     *total = all;
     return before + x - v;
 }
 
-__device__ inline uint32_t cell_start(const Scene& s, uint32_t k)
-{
-    return k < s.T ? s.cell_local[k] + s.tile_off[k / kScanTile] : (uint32_t)s.n;
-}
+constexpr unsigned long long kTileAggregate = 1ull << 32, kTileInclusive = 2ull << 32;
+constexpr uint32_t kSpinLimit = 1u << 22;   // bounded wait: flag an error, never hang
 
 __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
 {
     __shared__ uint32_t wave_tot[kWaves];
-    __shared__ int s_last;
-    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanItems;
+    __shared__ uint32_t s_tile, s_prefix;
+    if (threadIdx.x == 0) s_tile = atomicAdd(s.scan_ticket, 1u);   // tiles start in ticket order
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const size_t base = (size_t)tile * kScanTile + (size_t)threadIdx.x * kScanItems;
     uint32_t vals[kScanItems];
     uint32_t sum = 0;
     for (int k = 0; k < kScanItems; ++k) {
         const bool in = base + k < s.T;
         vals[k] = in ? s.cell_count[base + k] : 0u;
-        if (in) {
-            s.cell_count[base + k] = 0u;     // ready for the next substep's counting pass
-            s.cell_body[base + k] = -1;      // filled by the scatter that follows
-        }
+        if (in) s.cell_count[base + k] = 0u;      // ready for the next substep's counting pass
         sum += vals[k];
     }
     uint32_t total;
     uint32_t run = block_exclusive_scan(sum, wave_tot, &total);
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < s.T) s.cell_local[base + k] = run;
-        run += vals[k];
-    }
-    if (threadIdx.x == 0) {
-        s.tile_sums[blockIdx.x] = total;
-        __threadfence();
-        s_last = atomicAdd(s.scan_done, 1u) == s.n_scan_tiles - 1u;
+    if (threadIdx.x < 64) {                       // wave 0: publish and look back
+        const int lane = threadIdx.x;
+        uint32_t prefix = 0;
+        if (tile == 0) {
+            if (lane == 0)
+                __hip_atomic_store(&s.tile_state[0], kTileInclusive | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(&s.tile_state[tile], kTileAggregate | total, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int top = (int)tile - 1;               // newest predecessor not yet summed
+            uint32_t spins = 0;
+            while (true) {
+                const int t = top - lane;
+                const unsigned long long st =
+                    t >= 0 ? __hip_atomic_load(&s.tile_state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                           : kTileInclusive;
+                const uint32_t status = (uint32_t)(st >> 32);
+                const unsigned long long incl = __ballot(status == 2u);
+                const unsigned long long empty = __ballot(status == 0u);
+                const int stop = incl ? __ffsll((long long)incl) - 1 : 63;   // lanes 0..stop matter
+                const unsigned long long mask = stop == 63 ? ~0ull : ((1ull << (stop + 1)) - 1ull);
+                if (empty & mask) {               // a predecessor has not published yet
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicOr(&s.counters->err, kErrInternal);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                uint32_t v = lane <= stop ? (uint32_t)st : 0u;
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                prefix += v;
+                if (incl) break;
+                top -= 64;
+            }
+            if (lane == 0)
+                __hip_atomic_store(&s.tile_state[tile], kTileInclusive | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) s_prefix = prefix;
     }
     __syncthreads();
-    if (!s_last) return;
-    // last tile: exclusive scan of the tile totals
-    __threadfence();
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < s.n_scan_tiles; c0 += kScanTile) {
-        const uint32_t b0 = c0 + threadIdx.x * kScanItems;
-        uint32_t tv[kScanItems], tsum = 0;
-        for (int k = 0; k < kScanItems; ++k) {
-            tv[k] = b0 + k < s.n_scan_tiles
-                        ? __hip_atomic_load(&s.tile_sums[b0 + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                        : 0u;
-            tsum += tv[k];
-        }
-        uint32_t ttot;
-        uint32_t trun = carry + block_exclusive_scan(tsum, wave_tot, &ttot);
-        for (int k = 0; k < kScanItems; ++k) {
-            if (b0 + k < s.n_scan_tiles) s.tile_off[b0 + k] = trun;
-            trun += tv[k];
-        }
-        carry += ttot;
+    run += s_prefix;
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < s.T) s.cells[base + k] = make_uint4(run, vals[k], 0xffffffffu, 0u);   // signature: empty
+        run += vals[k];
     }
-    if (threadIdx.x == 0) *s.scan_done = 0u;
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
@@ -242,7 +257,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     const uint32_t key = s.key[i];
-    const uint32_t slot = cell_start(s, key) + s.rank[i];
+    const uint32_t slot = s.cells[key].x + s.rank[i];
     const int32_t b = s.body[i];
     s.sorted_raw[slot] = (uint32_t)i;
     s.sxt[slot] = s.xt[i];
@@ -250,8 +265,9 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
     s.sxt[2 * n + slot] = s.xt[2 * n + i];
     s.sbody[slot] = b;
     // body signature of the key: the one body of all its particles, or -2
-    const int32_t old = atomicCAS(&s.cell_body[key], -1, b);
-    if (old != -1 && old != b && old != -2) atomicExch(&s.cell_body[key], -2);
+    int* sig = (int*)&s.cells[key].z;
+    const int32_t old = atomicCAS(sig, -1, b);
+    if (old != -1 && old != b && old != -2) atomicExch(sig, -2);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,9 +296,10 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
         for (int t = 0; t < 27; ++t) {
             const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
                                       cz + (uint32_t)(t / 9 - 1), c.key_mask);
-            lo[t] = cell_start(s, k);
-            hi[t] = cell_start(s, k + 1);
-            sig[t] = s.cell_body[k];
+            const uint4 e = s.cells[k];
+            lo[t] = e.x;
+            hi[t] = e.x + e.y;
+            sig[t] = (int32_t)e.z;
         }
         // canonical slot of i inside its own key (stencil centre, t = 13)
         {
@@ -533,6 +550,61 @@ __device__ void polar_rotation(const float* A, float* R)
     for (int k = 0; k < 9; ++k) R[k] = X[k];
 }
 
+// Rotation maximising tr(R^T A), refined from a nearby rotation R0 (the
+// previous solver iteration's): Newton steps on SO(3).  With B = R^T A the
+// gradient of tr(Q^T B) at Q = I is -g, g = (B12 - B21, B20 - B02, B01 - B10),
+// and the Hessian is sym(B) - tr(B) I, so the step is omega = -(tr(B) I -
+// sym(B))^-1 g, applied through the Cayley map; one unscaled Newton polar step
+// then restores orthogonality.  Returns false when the start is too far (the
+// step does not shrink below 3e-5 rad within two steps) or the Hessian is not
+// definite; the caller then uses polar_rotation.
+__device__ bool polar_refine(const float* A, const float* R0, float* R)
+{
+    float X[9];
+    for (int k = 0; k < 9; ++k) X[k] = R0[k];
+    bool done = false;
+    for (int step = 0; step < 2 && !done; ++step) {
+        float B[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) B[3 * a + b] = X[a] * A[b] + X[3 + a] * A[3 + b] + X[6 + a] * A[6 + b];
+        const float g[3] = {B[5] - B[7], B[6] - B[2], B[1] - B[3]};
+        const float tr = B[0] + B[4] + B[8];
+        const float H[9] = {tr - B[0], -0.5f * (B[1] + B[3]), -0.5f * (B[2] + B[6]),
+                            -0.5f * (B[1] + B[3]), tr - B[4], -0.5f * (B[5] + B[7]),
+                            -0.5f * (B[2] + B[6]), -0.5f * (B[5] + B[7]), tr - B[8]};
+        float C[9];
+        cof3(H, C);
+        const float det = H[0] * C[0] + H[1] * C[1] + H[2] * C[2];
+        const float t3 = tr * (1.0f / 3.0f);
+        if (!(tr > 0.0f) || !(det > 1e-4f * t3 * t3 * t3)) return false;
+        const float id = frcp(det);
+        float w[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) w[r] = -0.5f * (C[3 * r] * g[0] + C[3 * r + 1] * g[1] + C[3 * r + 2] * g[2]) * id;
+        const float w2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];   // |omega / 2|^2
+        done = w2 < 2.25e-10f;                                        // |omega| < 3e-5
+        // Cayley: Q = I + 2 / (1 + |w|^2) ([w]x + [w]x^2)
+        const float f = 2.0f * frcp(1.0f + w2);
+        const float Q[9] = {1.0f + f * (w[0] * w[0] - w2), f * (w[0] * w[1] - w[2]), f * (w[0] * w[2] + w[1]),
+                            f * (w[0] * w[1] + w[2]), 1.0f + f * (w[1] * w[1] - w2), f * (w[1] * w[2] - w[0]),
+                            f * (w[0] * w[2] - w[1]), f * (w[1] * w[2] + w[0]), 1.0f + f * (w[2] * w[2] - w2)};
+        float Y[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) Y[3 * a + b] = X[3 * a] * Q[b] + X[3 * a + 1] * Q[3 + b] + X[3 * a + 2] * Q[6 + b];
+        for (int k = 0; k < 9; ++k) X[k] = Y[k];
+    }
+    if (!done) return false;
+    float C[9];
+    cof3(X, C);
+    const float id = frcp(X[0] * C[0] + X[1] * C[1] + X[2] * C[2]);
+    for (int k = 0; k < 9; ++k) R[k] = 0.5f * (X[k] + C[k] * id);
+    return true;
+}
+
 // omega = I^+ L for a symmetric positive semi-definite inertia tensor
 // (xx, yy, zz, xy, xz, yz).  `scale` = max(trace I, M (2r)^2) sets what counts
 // as zero: the inertia of a one-particle body is rounding noise, and a body
@@ -569,15 +641,18 @@ __device__ void solve_inertia(const float* I6, const float* L, float scale, floa
 // ---------------------------------------------------------------------------
 
 // Bodies are packed into workgroups of W waves; each body owns ceil(n/64)
-// consecutive waves, one particle per lane, so every per-body sum is a wave
-// sum plus a fixed-order sum over the body's waves.
-__global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src)
+// consecutive waves, one particle per lane.  Per-body sums are wave sums (DPP)
+// combined over the body's waves; the per-body 3x3 algebra runs on lane j of
+// wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
+// the substep: from the second iteration on, the rotation is refined from the
+// previous iteration's.
+__global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
 {
-    __shared__ float red_sm[kMaxWaves * 15];
-    __shared__ float red_mom[kMaxWaves * 24];
+    constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
+    __shared__ float4 red_sm[kMaxWaves * NSM / 4];
+    __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
     __shared__ float body_sm[kMaxWaves * 12];    // per body of the workgroup: R (9), centre (3)
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
-    constexpr int PPT = 1;
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = blockIdx.x * s.waves_per_block + wave;
@@ -589,8 +664,9 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
         e0 = s.body_start[b + 1];
         lw0 = s.body_wave0[b] - blockIdx.x * s.waves_per_block;
     }
-    const int lb = b - blk_b0;                    // body slot within the workgroup
-    const int ip = s0 + (wave - lw0) * 64 + lane;  // this lane's particle
+    const int lb = b >= blk_b0 ? b - blk_b0 : 0;  // body slot within the workgroup
+    const int i = s0 + (wave - lw0) * 64 + lane;  // this lane's particle
+    const bool act = b >= 0 && i < e0;
     const size_t n = (size_t)s.n;
     const float* dl = s.dl[src];
     const float* vl = s.vel[src];
@@ -601,49 +677,44 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
 
     // per-body lane of wave 0: body slot `lane` of this workgroup
     const bool body_lane = wave == 0 && lane < blk_nb;
+    const int bb = blk_b0 + (body_lane ? lane : 0);
     int bl_w0 = 0, bl_nw = 0;
-    float bl_M = 1.0f;
+    float bl_M = 1.0f, Rprev[9];
     if (body_lane) {
-        const int bb = blk_b0 + lane;
         bl_w0 = s.body_wave0[bb] - blockIdx.x * s.waves_per_block;
         bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
         bl_M = s.body_mass[bb];
+        if (it > 0)
+            for (int j = 0; j < 9; ++j) Rprev[j] = s.body_rot[9 * (size_t)bb + j];
     }
 
-    float x0[PPT][3], del[PPT][3], V[PPT][3], q[PPT][3], m[PPT], Cd[PPT][3];
-    bool act[PPT];
-    for (int k = 0; k < PPT; ++k) {
-        const int i = ip;
-        act[k] = b >= 0 && i < e0;
-        for (int j = 0; j < 3; ++j) x0[k][j] = del[k][j] = V[k][j] = q[k][j] = Cd[k][j] = 0.0f;
-        m[k] = 0.0f;
-        if (!act[k]) continue;
+    float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
+    float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
         for (int j = 0; j < 3; ++j) {
-            x0[k][j] = s.x[j * n + i];
-            del[k][j] = dl[j * n + i];
-            V[k][j] = vl[j * n + i];
-            q[k][j] = s.q[j * n + i];
+            x0[j] = s.x[j * n + i];
+            del[j] = dl[j * n + i];
+            V[j] = vl[j * n + i];
+            q[j] = s.q[j * n + i];
         }
-        m[k] = s.mass[i];
+        m = s.mass[i];
     }
 
     // contacts, from X_i (Jacobi): planes (constraint (1)) and particles of
     // other bodies (constraint (2)); friction from the displacement since X_init
-    for (int k = 0; k < PPT; ++k) {
-        if (!act[k]) continue;
-        const int i = ip;
+    if (act) {
         for (int pl = 0; pl < c.n_planes; ++pl) {
             const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
-            const float un = nx * del[k][0] + ny * del[k][1] + nz * del[k][2];
-            const float e = ((nx * x0[k][0] + ny * x0[k][1] + nz * x0[k][2]) - c.plane_d[pl]) + un;
+            const float un = nx * del[0] + ny * del[1] + nz * del[2];
+            const float e = ((nx * x0[0] + ny * x0[1] + nz * x0[2]) - c.plane_d[pl]) + un;
             if (!(e < c.radius)) continue;
             const float pen = c.radius - e;
-            const float ux = del[k][0] - un * nx, uy = del[k][1] - un * ny, uz = del[k][2] - un * nz;
+            const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
             const float ut2 = ux * ux + uy * uy + uz * uz;
             const float f = ut2 > 0.0f ? fminf(1.0f, c.mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
-            Cd[k][0] += pen * nx - f * ux;
-            Cd[k][1] += pen * ny - f * uy;
-            Cd[k][2] += pen * nz - f * uz;
+            Cd[0] += pen * nx - f * ux;
+            Cd[1] += pen * ny - f * uy;
+            Cd[2] += pen * nz - f * uz;
         }
         const uint32_t ni = s.nbr_n[i];
         const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
@@ -652,8 +723,8 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
             float d[3], u[3];
             for (int j = 0; j < 3; ++j) {
                 const float dj = dl[j * n + jq];
-                d[j] = (x0[k][j] - s.x[j * n + jq]) + (del[k][j] - dj);
-                u[j] = del[k][j] - dj;
+                d[j] = (x0[j] - s.x[j * n + jq]) + (del[j] - dj);
+                u[j] = del[j] - dj;
             }
             const float l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
             const float l = __builtin_amdgcn_sqrtf(l2);
@@ -662,7 +733,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
             const float nx = d[0] * il, ny = d[1] * il, nz = d[2] * il;
             const float pen = c.two_r - l;
             const float mq = s.mass[jq];
-            const float alpha = mq * frcp(m[k] + mq);       // w_p / (w_p + w_q)
+            const float alpha = mq * frcp(m + mq);          // w_p / (w_p + w_q)
             const float un = u[0] * nx + u[1] * ny + u[2] * nz;
             const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
             const float ut2 = ux * ux + uy * uy + uz * uz;
@@ -675,124 +746,130 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
                 wgt = frcp((float)ni);
             }
             const float sc = alpha * wgt;
-            Cd[k][0] += sc * (pen * nx - f * ux);
-            Cd[k][1] += sc * (pen * ny - f * uy);
-            Cd[k][2] += sc * (pen * nz - f * uz);
+            Cd[0] += sc * (pen * nx - f * ux);
+            Cd[1] += sc * (pen * ny - f * uy);
+            Cd[2] += sc * (pen * nz - f * uz);
         }
     }
 
     // shape matching on X_i: centre and covariance in one reduction,
     // A = sum m (x - c) q^T = sum m y q^T - c (sum m q)^T, y = x - anchor
-    float y[PPT][3];
-    float cyv[3], R[9];
+    float y[3];
+    y[0] = (x0[0] - ax) + del[0];
+    y[1] = (x0[1] - ay) + del[1];
+    y[2] = (x0[2] - az) + del[2];
     {
-        float S[15];
-        for (int j = 0; j < 15; ++j) S[j] = 0.0f;
-        for (int k = 0; k < PPT; ++k) {
-            y[k][0] = (x0[k][0] - ax) + del[k][0];
-            y[k][1] = (x0[k][1] - ay) + del[k][1];
-            y[k][2] = (x0[k][2] - az) + del[k][2];
-            for (int j = 0; j < 3; ++j) {
-                S[j] += m[k] * y[k][j];
-                S[3 + j] += m[k] * q[k][j];
-            }
-            for (int a = 0; a < 3; ++a)
-                for (int bb = 0; bb < 3; ++bb) S[6 + 3 * a + bb] += m[k] * y[k][a] * q[k][bb];
-        }
-        for (int j = 0; j < 15; ++j) S[j] = wave_sum_to_63(S[j]);
+        float S[NSM];
+        for (int j = 0; j < 3; ++j) S[j] = m * y[j];
+        for (int a = 0; a < 3; ++a)
+            for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
+        for (int j = 0; j < NSM; ++j) S[j] = wave_sum_to_63(S[j]);
         if (lane == 63)
-            for (int j = 0; j < 15; ++j) red_sm[wave * 15 + j] = S[j];
-        __syncthreads();
-        if (body_lane) {            // one lane per body: centre, covariance, polar
-            float T[15];
-            for (int j = 0; j < 15; ++j) {
-                float t = red_sm[bl_w0 * 15 + j];
-                for (int w = 1; w < bl_nw; ++w) t += red_sm[(bl_w0 + w) * 15 + j];
-                T[j] = t;
-            }
-            const float im = frcp(bl_M);
-            float cc[3], A[9], Rb[9];
-            for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
-            for (int a = 0; a < 3; ++a)
-                for (int bb = 0; bb < 3; ++bb) A[3 * a + bb] = T[6 + 3 * a + bb] - cc[a] * T[3 + bb];
-            polar_rotation(A, Rb);
-            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
-            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
-        }
-        __syncthreads();
-        const int sl = lb >= 0 ? lb : 0;
-        for (int j = 0; j < 9; ++j) R[j] = body_sm[sl * 12 + j];
-        for (int j = 0; j < 3; ++j) cyv[j] = body_sm[sl * 12 + 9 + j];
+            for (int j = 0; j < NSM / 4; ++j)
+                red_sm[wave * (NSM / 4) + j] = make_float4(S[4 * j], S[4 * j + 1], S[4 * j + 2], S[4 * j + 3]);
     }
+    __syncthreads();
+    if (body_lane) {            // one lane per body: centre, covariance, rotation
+        float T[NSM];
+        for (int j = 0; j < NSM; ++j) T[j] = 0.0f;
+        for (int w = 0; w < bl_nw; ++w)
+#pragma unroll
+            for (int j = 0; j < NSM / 4; ++j) {
+                const float4 p = red_sm[(bl_w0 + w) * (NSM / 4) + j];
+                T[4 * j] += p.x;
+                T[4 * j + 1] += p.y;
+                T[4 * j + 2] += p.z;
+                T[4 * j + 3] += p.w;
+            }
+        const float im = frcp(bl_M);
+        const float mq3[3] = {s.body_mq[3 * bb], s.body_mq[3 * bb + 1], s.body_mq[3 * bb + 2]};
+        float cc[3], A[9], Rb[9];
+        for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
+        for (int a = 0; a < 3; ++a)
+            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+        if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
+        for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
+        for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+        if (s.body_rot)
+            for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rb[j];
+    }
+    __syncthreads();
+    float R[9], cyv[3];
+    for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+    for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
 
     // goal offsets D = R q - (x - c) and the momentum sums, in the frame
     // centred on c_i: z_b = r + C (before shape matching), z_a = z_b + D
-    float r[PPT][3], Dd[PPT][3];
-    float S[24];
-    for (int j = 0; j < 24; ++j) S[j] = 0.0f;
-    for (int k = 0; k < PPT; ++k) {
-        for (int j = 0; j < 3; ++j) r[k][j] = y[k][j] - cyv[j];
-        for (int a = 0; a < 3; ++a)
-            Dd[k][a] = act[k] ? (R[3 * a] * q[k][0] + R[3 * a + 1] * q[k][1] + R[3 * a + 2] * q[k][2]) - r[k][a] : 0.0f;
-        const float mk = m[k];
+    float r[3], Dd[3];
+    for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
+    for (int a = 0; a < 3; ++a)
+        Dd[a] = act ? (R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2]) - r[a] : 0.0f;
+    {
+        float S[NMOM];
         float zb[3], za[3], vb[3], t[3];
         for (int j = 0; j < 3; ++j) {
-            zb[j] = r[k][j] + Cd[k][j];
-            za[j] = zb[j] + Dd[k][j];
-            vb[j] = V[k][j] + Cd[k][j] * c.inv_h;
-            S[j] += mk * r[k][j];           // S0 = sum m r (rounding residual of c)
-            S[3 + j] += mk * Cd[k][j];      // S1 = sum m C
-            S[6 + j] += mk * Dd[k][j];      // S2 = sum m D
-            S[9 + j] += mk * vb[j];         // S3 = P_bsm
+            zb[j] = r[j] + Cd[j];
+            za[j] = zb[j] + Dd[j];
+            vb[j] = V[j] + Cd[j] * c.inv_h;
+            S[j] = m * Cd[j];               // S1 = sum m C
+            S[3 + j] = m * Dd[j];           // S2 = sum m D
+            S[6 + j] = m * vb[j];           // S3 = P_bsm
         }
-        cross(zb, Dd[k], t);
-        for (int j = 0; j < 3; ++j) S[12 + j] += mk * t[j];     // S4 = sum m z_b x D
-        cross(Dd[k], vb, t);
-        for (int j = 0; j < 3; ++j) S[15 + j] += mk * t[j];     // S5 = sum m D x v_b
-        S[18] += mk * (za[1] * za[1] + za[2] * za[2]);          // S6: inertia about c_i
-        S[19] += mk * (za[0] * za[0] + za[2] * za[2]);
-        S[20] += mk * (za[0] * za[0] + za[1] * za[1]);
-        S[21] -= mk * za[0] * za[1];
-        S[22] -= mk * za[0] * za[2];
-        S[23] -= mk * za[1] * za[2];
+        cross(zb, Dd, t);
+        for (int j = 0; j < 3; ++j) S[9 + j] = m * t[j];          // S4 = sum m z_b x D
+        cross(Dd, vb, t);
+        for (int j = 0; j < 3; ++j) S[12 + j] = m * t[j];         // S5 = sum m D x v_b
+        S[15] = m * (za[1] * za[1] + za[2] * za[2]);              // S6: inertia about c_i
+        S[16] = m * (za[0] * za[0] + za[2] * za[2]);
+        S[17] = m * (za[0] * za[0] + za[1] * za[1]);
+        S[18] = -m * za[0] * za[1];
+        S[19] = -m * za[0] * za[2];
+        S[20] = -m * za[1] * za[2];
+        S[21] = S[22] = S[23] = 0.0f;
+        for (int j = 0; j < 21; ++j) S[j] = wave_sum_to_63(S[j]);
+        if (lane == 63)
+            for (int j = 0; j < NMOM / 4; ++j)
+                red_mom[wave * (NMOM / 4) + j] = make_float4(S[4 * j], S[4 * j + 1], S[4 * j + 2], S[4 * j + 3]);
     }
-    for (int j = 0; j < 24; ++j) S[j] = wave_sum_to_63(S[j]);
-    if (lane == 63)
-        for (int j = 0; j < 24; ++j) red_mom[wave * 24 + j] = S[j];
     __syncthreads();
 
     // momentum conservation constraint, one lane per body
     if (body_lane) {
-        float T[24];
-        for (int j = 0; j < 24; ++j) {
-            float t = red_mom[bl_w0 * 24 + j];
-            for (int w = 1; w < bl_nw; ++w) t += red_mom[(bl_w0 + w) * 24 + j];
-            T[j] = t;
-        }
+        float T[NMOM];
+        for (int j = 0; j < NMOM; ++j) T[j] = 0.0f;
+        for (int w = 0; w < bl_nw; ++w)
+#pragma unroll
+            for (int j = 0; j < NMOM / 4; ++j) {
+                const float4 p = red_mom[(bl_w0 + w) * (NMOM / 4) + j];
+                T[4 * j] += p.x;
+                T[4 * j + 1] += p.y;
+                T[4 * j + 2] += p.z;
+                T[4 * j + 3] += p.w;
+            }
         const float Mb = bl_M, im = frcp(Mb);
         float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
         for (int j = 0; j < 3; ++j) {
-            cb[j] = (T[j] + T[3 + j]) * im;      // c_bsm - c_i
-            Db[j] = T[6 + j] * im;               // mean shape-matching shift
+            cb[j] = T[j] * im;                   // c_bsm - c_i
+            Db[j] = T[3 + j] * im;               // mean shape-matching shift
             cab[j] = cb[j] + Db[j];              // c_asm - c_i
         }
         // Eq. (4): dv = (P_bsm - P_asm) / M,  P_asm - P_bsm = sum m D / dt
         if (!(c.flags & kFlagNoLinMom))
-            for (int j = 0; j < 3; ++j) dvb[j] = -T[6 + j] * c.inv_h * im;
+            for (int j = 0; j < 3; ++j) dvb[j] = -T[3 + j] * c.inv_h * im;
         // Eq. (5): omega = I^-1 (L_asm - L_bsm); the difference is formed from
         // the small quantities: (sum m r_b x D)/dt + sum m D x v_b - Db x P_bsm
         if (!(c.flags & kFlagNoAngMom)) {
             float cbxD[3], DbxP[3], dL[3], I6[6];
-            cross(cb, &T[6], cbxD);
-            cross(Db, &T[9], DbxP);
-            for (int j = 0; j < 3; ++j) dL[j] = (T[12 + j] - cbxD[j]) * c.inv_h + T[15 + j] - DbxP[j];
+            cross(cb, &T[3], cbxD);
+            cross(Db, &T[6], DbxP);
+            for (int j = 0; j < 3; ++j) dL[j] = (T[9 + j] - cbxD[j]) * c.inv_h + T[12 + j] - DbxP[j];
             // parallel-axis shift of the inertia from c_i to c_asm
-            I6[0] = T[18] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
-            I6[1] = T[19] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
-            I6[2] = T[20] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
-            I6[3] = T[21] + Mb * cab[0] * cab[1];
-            I6[4] = T[22] + Mb * cab[0] * cab[2];
-            I6[5] = T[23] + Mb * cab[1] * cab[2];
+            I6[0] = T[15] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
+            I6[1] = T[16] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
+            I6[2] = T[17] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
+            I6[3] = T[18] + Mb * cab[0] * cab[1];
+            I6[4] = T[19] + Mb * cab[0] * cab[2];
+            I6[5] = T[20] + Mb * cab[1] * cab[2];
             const float scale = fmaxf(I6[0] + I6[1] + I6[2], Mb * c.two_r * c.two_r);
             solve_inertia(I6, dL, scale, wb);
         }
@@ -803,35 +880,27 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
         }
     }
     __syncthreads();
+    if (!act) return;
     float dv[3], w[3], ca[3];
-    {
-        const int sl = lb >= 0 ? lb : 0;
-        for (int j = 0; j < 3; ++j) {
-            dv[j] = body_mom[sl * 9 + j];
-            w[j] = body_mom[sl * 9 + 3 + j];
-            ca[j] = body_mom[sl * 9 + 6 + j];
-        }
+    for (int j = 0; j < 3; ++j) {
+        dv[j] = body_mom[lb * 9 + j];
+        w[j] = body_mom[lb * 9 + 3 + j];
+        ca[j] = body_mom[lb * 9 + 6 + j];
     }
-    if (b >= 0 && wave == lw0 && lane == 0 && s.body_rot)
-        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)b + j] = R[j];
-    for (int k = 0; k < PPT; ++k) {
-        if (!act[k]) continue;
-        const int i = ip;
-        float ra[3], wr[3];
-        for (int j = 0; j < 3; ++j) ra[j] = r[k][j] + Cd[k][j] + Dd[k][j] - ca[j];
-        cross(w, ra, wr);
-        for (int j = 0; j < 3; ++j) {
-            const float step = Cd[k][j] + Dd[k][j];
-            const float dvi = dv[j] - wr[j];
-            const float dnew = (del[k][j] + step) + c.h * dvi;
-            dn[j * n + i] = dnew;
-            if (c.flags & kFlagStdVelocity) {
-                // standard PBD: V = (X_{i+1} - X_init) / dt in world FP32 coordinates
-                const float xw = x0[k][j] + dnew;
-                vn[j * n + i] = (xw - x0[k][j]) * c.inv_h;
-            } else {
-                vn[j * n + i] = (V[k][j] + step * c.inv_h) + dvi;
-            }
+    float ra[3], wr[3];
+    for (int j = 0; j < 3; ++j) ra[j] = r[j] + Cd[j] + Dd[j] - ca[j];
+    cross(w, ra, wr);
+    for (int j = 0; j < 3; ++j) {
+        const float step = Cd[j] + Dd[j];
+        const float dvi = dv[j] - wr[j];
+        const float dnew = (del[j] + step) + c.h * dvi;
+        dn[j * n + i] = dnew;
+        if (c.flags & kFlagStdVelocity) {
+            // standard PBD: V = (X_{i+1} - X_init) / dt in world FP32 coordinates
+            const float xw = x0[j] + dnew;
+            vn[j * n + i] = (xw - x0[j]) * c.inv_h;
+        } else {
+            vn[j * n + i] = (V[j] + step * c.inv_h) + dvi;
         }
     }
 }
@@ -864,18 +933,14 @@ __global__ void k_clear_counters(Counters* c)
 __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < s.T) {
-        s.cell_count[i] = 0u;
-        s.cell_body[i] = -1;
-    }
-    if (i == 0) *s.scan_done = 0u;
+    if (i < s.T) s.cell_count[i] = 0u;
 }
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-void launch_iterate(const Scene& s, const StepConsts& c, int src, hipStream_t stream)
+void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src);
+    hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src, it);
 }
 
 }  // namespace
@@ -897,7 +962,7 @@ hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hi
     if (s.n <= 0 || count <= 0) return hipSuccess;
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        launch_iterate(s, c, src, stream);
+        launch_iterate(s, c, src, it, stream);
         src ^= 1;
     }
     return hipGetLastError();
@@ -907,16 +972,17 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     const unsigned nb = blocks_for((size_t)s.n);
+    const unsigned nb_pred = blocks_for((size_t)s.n > (size_t)s.n_scan_tiles ? (size_t)s.n : (size_t)s.n_scan_tiles);
     const size_t nbr_lds = (size_t)c.nbr_cap * kBlock * sizeof(uint32_t);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
     for (int sub = 0; sub < count; ++sub) {
-        hipLaunchKernelGGL(k_predict_keys, dim3(nb), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
+        hipLaunchKernelGGL(k_predict_keys, dim3(nb_pred), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
         hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, stream, s);
         hipLaunchKernelGGL(k_neighbours, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
         int src = 0;
         for (int it = 0; it < iterations; ++it) {
-            launch_iterate(s, c, src, stream);
+            launch_iterate(s, c, src, it, stream);
             src ^= 1;
         }
     }
