@@ -92,8 +92,8 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
 }
 
 struct Layout {
-    size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt, sbody, key, rank,
-        sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, scan_ticket, body_rot, counters, wave_body,
+    size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
+        sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
         body_wave0, block_body, body_mq, total;
 };
 
@@ -129,8 +129,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.vel0 = take(12 * N);
     L.vel1 = take(12 * N);
     L.xt = take(12 * N);
-    L.sxt = take(12 * N);
-    L.sbody = take(4 * N);
+    L.sxt4 = take(16 * N);
     L.key = take(4 * N);
     L.rank = take(4 * N);
     L.sorted_raw = take(4 * N);
@@ -140,9 +139,9 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.cell_count = take(4 * T);
     L.cells = take(16 * T);
     L.tile_state = take(8 * tiles);
-    L.scan_ticket = take(4);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
+    L.nbr_stats = take(sizeof(pbdr::NbrStats) * ((N + pbdr::kBlock - 1) / pbdr::kBlock));
     L.wave_body = take(4 * max_iteration_waves(n, nb));
     L.body_wave0 = take(4 * B);
     L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 1));
@@ -185,6 +184,26 @@ pbdr_status read_counters(pbdr_scene* s, pbdr::Counters* c)
     return PBDR_OK;
 }
 
+// Reduces the per-workgroup neighbour statistics (synchronises).
+pbdr_status read_nbr_stats(pbdr_scene* s, uint32_t* max_nbr, double* mean)
+{
+    const size_t slots = ((size_t)s->dev.n + pbdr::kBlock - 1) / pbdr::kBlock;
+    std::vector<pbdr::NbrStats> st(slots);
+    if (slots) HIP_TRY(hipMemcpyAsync(st.data(), s->ws + s->lay.nbr_stats, slots * sizeof(pbdr::NbrStats),
+                                      hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    uint32_t mx = 0;
+    unsigned long long sum = 0, rows = 0;
+    for (const auto& e : st) {
+        mx = std::max(mx, e.max_nbr);
+        sum += e.sum;
+        rows += e.rows;
+    }
+    if (max_nbr) *max_nbr = mx;
+    if (mean) *mean = rows ? (double)sum / (double)rows : 0.0;
+    return PBDR_OK;
+}
+
 pbdr_status latched(pbdr_scene* s)
 {
     pbdr::Counters c;
@@ -192,8 +211,11 @@ pbdr_status latched(pbdr_scene* s)
     if (st != PBDR_OK) return st;
     if (c.err & pbdr::kErrInternal) return fail(PBDR_ERR_DEVICE, "a device-side wait gave up (cell-table scan)");
     if (c.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity became non-finite");
-    if (c.err & pbdr::kErrCapacity)
-        return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", c.max_nbr, s->res.cap);
+    if (c.err & pbdr::kErrCapacity) {
+        uint32_t mx = 0;
+        read_nbr_stats(s, &mx, nullptr);
+        return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", mx, s->res.cap);
+    }
     return PBDR_OK;
 }
 
@@ -244,8 +266,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.vel[0] = (float*)(w + L.vel0);
     d.vel[1] = (float*)(w + L.vel1);
     d.xt = (float*)(w + L.xt);
-    d.sxt = (float*)(w + L.sxt);
-    d.sbody = (int32_t*)(w + L.sbody);
+    d.sxt4 = (float4*)(w + L.sxt4);
     d.key = (uint32_t*)(w + L.key);
     d.rank = (uint32_t*)(w + L.rank);
     d.sorted_raw = (uint32_t*)(w + L.sorted_raw);
@@ -255,9 +276,9 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.cell_count = (uint32_t*)(w + L.cell_count);
     d.cells = (uint4*)(w + L.cells);
     d.tile_state = (unsigned long long*)(w + L.tile_state);
-    d.scan_ticket = (uint32_t*)(w + L.scan_ticket);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
+    d.nbr_stats = (pbdr::NbrStats*)(w + L.nbr_stats);
     d.wave_body = (const int32_t*)(w + L.wave_body);
     d.body_wave0 = (const int32_t*)(w + L.body_wave0);
     d.block_body = (const int32_t*)(w + L.block_body);
@@ -535,21 +556,22 @@ pbdr_status pbdr_scene_read_rest(pbdr_scene* s, float* rest_q)
 pbdr_status pbdr_scene_check(pbdr_scene* s, int32_t* max_neighbours)
 {
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
-    pbdr::Counters c;
-    pbdr_status st = read_counters(s, &c);
-    if (st != PBDR_OK) return st;
-    if (max_neighbours) *max_neighbours = (int32_t)c.max_nbr;
+    if (max_neighbours) {
+        uint32_t mx = 0;
+        pbdr_status st = read_nbr_stats(s, &mx, nullptr);
+        if (st != PBDR_OK) return st;
+        *max_neighbours = (int32_t)mx;
+    }
     return latched(s);
 }
 
 pbdr_status pbdr_scene_neighbour_stats(pbdr_scene* s, int32_t* max_neighbours, double* mean_neighbours)
 {
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
-    pbdr::Counters c;
-    pbdr_status st = read_counters(s, &c);
+    uint32_t mx = 0;
+    pbdr_status st = read_nbr_stats(s, &mx, mean_neighbours);
     if (st != PBDR_OK) return st;
-    if (max_neighbours) *max_neighbours = (int32_t)c.max_nbr;
-    if (mean_neighbours) *mean_neighbours = c.nbr_rows ? (double)c.nbr_sum / (double)c.nbr_rows : 0.0;
+    if (max_neighbours) *max_neighbours = (int32_t)mx;
     return PBDR_OK;
 }
 

@@ -22,12 +22,19 @@ enum : uint32_t {
     kAvgShift = 8u,
 };
 
-// Device-side counters, latched across substeps until read by the host.
+// Device-side error bits, latched until read by the host.
 struct Counters {
     uint32_t err;                  // kErr* bits
-    uint32_t max_nbr;              // largest neighbour-list length seen
-    unsigned long long nbr_sum;    // sum of list lengths (for the mean)
-    unsigned long long nbr_rows;   // particles counted in nbr_sum
+    uint32_t pad;
+};
+
+// Neighbour-list statistics, one slot per neighbour-kernel workgroup (no
+// contended atomics); the host reduces them when asked.
+struct NbrStats {
+    uint32_t max_nbr;              // largest list length seen
+    uint32_t pad;
+    unsigned long long sum;        // sum of list lengths
+    unsigned long long rows;       // particles counted in sum
 };
 
 // FP32 constants of one substep.
@@ -67,8 +74,7 @@ struct Scene {
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
     float* xt;                // [3][N] FP32 predicted positions
-    float* sxt;               // [3][N] predicted positions in raw sorted order
-    int32_t* sbody;           // [N] body ids in raw sorted order
+    float4* sxt4;             // [N] predicted position and body id (bits) in raw sorted order
     uint32_t* key;            // [N]
     uint32_t* rank;           // [N] slot within the key from the counting pass
     uint32_t* sorted_raw;     // [N] ids grouped by key, arbitrary order within a key
@@ -79,9 +85,10 @@ struct Scene {
     uint4* cells;             // [T] per key: first sorted slot, count, body signature
                               //     (the one body of all its particles, -1 empty, -2 mixed), 0
     unsigned long long* tile_state;  // [n_scan_tiles] scan look-back: (status << 32) | value
-    uint32_t* scan_ticket;    // order in which scan tiles start
+
     float* body_rot;          // [B][9] last rotation of shape matching
     Counters* counters;
+    NbrStats* nbr_stats;      // [ceil(N / kBlock)]
     const float* accel;       // [3][N] external acceleration or nullptr
 };
 

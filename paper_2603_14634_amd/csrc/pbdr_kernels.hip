@@ -123,7 +123,6 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
-    if (i == 0) *s.scan_ticket = 0u;
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     float xt[3];
@@ -183,24 +182,36 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot, 
 constexpr unsigned long long kTileAggregate = 1ull << 32, kTileInclusive = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded wait: flag an error, never hang
 
+// A tile is kScanTile keys in kChunks chunks of 4 keys per thread, so every
+// count load and entry store of a chunk is one contiguous, coalesced access.
+constexpr int kChunks = kScanTile / (4 * kBlock);
+
 __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
 {
-    __shared__ uint32_t wave_tot[kWaves];
-    __shared__ uint32_t s_tile, s_prefix;
-    if (threadIdx.x == 0) s_tile = atomicAdd(s.scan_ticket, 1u);   // tiles start in ticket order
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const size_t base = (size_t)tile * kScanTile + (size_t)threadIdx.x * kScanItems;
-    uint32_t vals[kScanItems];
-    uint32_t sum = 0;
-    for (int k = 0; k < kScanItems; ++k) {
-        const bool in = base + k < s.T;
-        vals[k] = in ? s.cell_count[base + k] : 0u;
-        if (in) s.cell_count[base + k] = 0u;      // ready for the next substep's counting pass
-        sum += vals[k];
+    __shared__ uint32_t wave_tot[kChunks][kWaves];
+    __shared__ uint32_t s_prefix;
+    // workgroups are dispatched in index order, so a tile only waits on tiles
+    // that already run; the wait is bounded all the same
+    const uint32_t tile = blockIdx.x;
+    const size_t tbase = (size_t)tile * kScanTile;
+    uint32_t vals[kChunks][4], excl[kChunks], chunk_tot[kChunks];
+    for (int ch = 0; ch < kChunks; ++ch) {
+        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
+        if (base + 3 < s.T) {
+            const uint4 v = *(const uint4*)&s.cell_count[base];
+            vals[ch][0] = v.x; vals[ch][1] = v.y; vals[ch][2] = v.z; vals[ch][3] = v.w;
+            *(uint4*)&s.cell_count[base] = make_uint4(0u, 0u, 0u, 0u);   // ready for the next substep
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                vals[ch][k] = base + k < s.T ? s.cell_count[base + k] : 0u;
+                if (base + k < s.T) s.cell_count[base + k] = 0u;
+            }
+        }
+        excl[ch] = block_exclusive_scan(vals[ch][0] + vals[ch][1] + vals[ch][2] + vals[ch][3], wave_tot[ch],
+                                        &chunk_tot[ch]);
     }
-    uint32_t total;
-    uint32_t run = block_exclusive_scan(sum, wave_tot, &total);
+    uint32_t total = 0;
+    for (int ch = 0; ch < kChunks; ++ch) total += chunk_tot[ch];
     if (threadIdx.x < 64) {                       // wave 0: publish and look back
         const int lane = threadIdx.x;
         uint32_t prefix = 0;
@@ -244,10 +255,15 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
         if (lane == 0) s_prefix = prefix;
     }
     __syncthreads();
-    run += s_prefix;
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < s.T) s.cells[base + k] = make_uint4(run, vals[k], 0xffffffffu, 0u);   // signature: empty
-        run += vals[k];
+    uint32_t run_chunk = s_prefix;
+    for (int ch = 0; ch < kChunks; ++ch) {
+        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
+        uint32_t run = run_chunk + excl[ch];
+        for (int k = 0; k < 4; ++k) {
+            if (base + k < s.T) s.cells[base + k] = make_uint4(run, vals[ch][k], 0xffffffffu, 0u);   // signature: empty
+            run += vals[ch][k];
+        }
+        run_chunk += chunk_tot[ch];
     }
 }
 
@@ -260,10 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
     const uint32_t slot = s.cells[key].x + s.rank[i];
     const int32_t b = s.body[i];
     s.sorted_raw[slot] = (uint32_t)i;
-    s.sxt[slot] = s.xt[i];
-    s.sxt[n + slot] = s.xt[n + i];
-    s.sxt[2 * n + slot] = s.xt[2 * n + i];
-    s.sbody[slot] = b;
+    s.sxt4[slot] = make_float4(s.xt[i], s.xt[n + i], s.xt[2 * n + i], __int_as_float(b));
     // body signature of the key: the one body of all its particles, or -2
     int* sig = (int*)&s.cells[key].z;
     const int32_t old = atomicCAS(sig, -1, b);
@@ -285,51 +298,63 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
     uint32_t count = 0;
     if (live) {
         const uint32_t i = s.sorted_raw[j];
-        const float px = s.sxt[j], py = s.sxt[n + j], pz = s.sxt[2 * n + j];
-        const int32_t pb = s.sbody[j];
+        const float4 me = s.sxt4[j];
+        const float px = me.x, py = me.y, pz = me.z;
+        const int32_t pb = __float_as_int(me.w);
         const uint32_t cx = cell_axis(px, c.origin[0], c.inv_cell);
         const uint32_t cy = cell_axis(py, c.origin[1], c.inv_cell);
         const uint32_t cz = cell_axis(pz, c.origin[2], c.inv_cell);
         uint32_t lo[27], hi[27];
-        int32_t sig[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
             const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
                                       cz + (uint32_t)(t / 9 - 1), c.key_mask);
             const uint4 e = s.cells[k];
             lo[t] = e.x;
-            hi[t] = e.x + e.y;
-            sig[t] = (int32_t)e.z;
+            // a key holding only this particle's body has no candidates
+            hi[t] = (int32_t)e.z == pb ? e.x : e.x + e.y;
         }
         // canonical slot of i inside its own key (stencil centre, t = 13)
         {
+            const uint4 e = s.cells[morton(cx, cy, cz, c.key_mask)];
             uint32_t below = 0;
-            for (uint32_t q = lo[13]; q < hi[13]; ++q) below += (s.sorted_raw[q] < i) ? 1u : 0u;
-            s.sorted[lo[13] + below] = i;
+            for (uint32_t q = e.x; q < e.x + e.y; ++q) below += (s.sorted_raw[q] < i) ? 1u : 0u;
+            s.sorted[e.x + below] = i;
         }
+        auto consider = [&](uint32_t q, const float4 o) {
+            if (__float_as_int(o.w) == pb) return;            // same body (also excludes i)
+            if (!within(px, py, pz, o.x, o.y, o.z, c.search_r2)) return;
+            const uint32_t id = s.sorted_raw[q];
+            // insert keeping the `cap` smallest ids in ascending order
+            const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
+            ++count;
+            if (m == cap && id > lst[(cap - 1) * kBlock + tid]) return;
+            int pos = (m == cap) ? cap - 1 : m;
+            while (pos > 0 && lst[(pos - 1) * kBlock + tid] > id) {
+                lst[pos * kBlock + tid] = lst[(pos - 1) * kBlock + tid];
+                --pos;
+            }
+            lst[pos * kBlock + tid] = id;
+        };
         for (int t = 0; t < 27; ++t) {
-            if (sig[t] == pb) continue;                // every particle of this key is ours
-            for (uint32_t q = lo[t]; q < hi[t]; ++q) {
-                if (s.sbody[q] == pb) continue;      // same body (also excludes i)
-                if (!within(px, py, pz, s.sxt[q], s.sxt[n + q], s.sxt[2 * n + q], c.search_r2)) continue;
-                const uint32_t id = s.sorted_raw[q];
-                // insert keeping the `cap` smallest ids in ascending order
-                const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
-                ++count;
-                if (m == cap && id > lst[(cap - 1) * kBlock + tid]) continue;
-                int pos = (m == cap) ? cap - 1 : m;
-                while (pos > 0 && lst[(pos - 1) * kBlock + tid] > id) {
-                    lst[pos * kBlock + tid] = lst[(pos - 1) * kBlock + tid];
-                    --pos;
-                }
-                lst[pos * kBlock + tid] = id;
+            // candidates four at a time, so their loads are in flight together
+            for (uint32_t q = lo[t]; q < hi[t]; q += 4) {
+                float4 o[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) o[u] = q + u < hi[t] ? s.sxt4[q + u] : me;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q + u < hi[t]) consider(q + u, o[u]);
             }
         }
         s.nbr_n[i] = count;
         const uint32_t stored = count < (uint32_t)cap ? count : (uint32_t)cap;
         for (uint32_t k = 0; k < stored; ++k) s.nbr[k * n + i] = lst[k * kBlock + tid];
     }
-    // statistics and capacity check, one atomic per wave
+    // statistics: this workgroup's own slot (no contention); the capacity
+    // error is latched only when it happens
+    __shared__ uint32_t st_max[kWaves];
+    __shared__ unsigned long long st_sum[kWaves];
     uint32_t mx = count;
     unsigned long long sum = count;
     for (int off = 32; off > 0; off >>= 1) {
@@ -337,14 +362,23 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
         sum += __shfl_xor(sum, off, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        const int lo_row = blockIdx.x * kBlock + (threadIdx.x & ~63);
-        const int rows = min(64, s.n - lo_row);
-        if (rows > 0) {
-            atomicMax(&s.counters->max_nbr, mx);
-            atomicAdd(&s.counters->nbr_sum, sum);
-            atomicAdd(&s.counters->nbr_rows, (unsigned long long)rows);
-            if (mx > (uint32_t)cap) atomicOr(&s.counters->err, kErrCapacity);
+        st_max[threadIdx.x >> 6] = mx;
+        st_sum[threadIdx.x >> 6] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t bm = 0;
+        unsigned long long bs = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            bm = max(bm, st_max[w]);
+            bs += st_sum[w];
         }
+        const int rows = min(kBlock, s.n - (int)(blockIdx.x * kBlock));
+        NbrStats& slot = s.nbr_stats[blockIdx.x];
+        slot.max_nbr = max(slot.max_nbr, bm);
+        slot.sum += bs;
+        slot.rows += (unsigned long long)rows;
+        if (bm > (uint32_t)cap) atomicOr(&s.counters->err, kErrCapacity);
     }
 }
 
@@ -922,12 +956,15 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
     if (!finite) atomicOr(&s.counters->err, kErrNonFinite);
 }
 
-__global__ void k_clear_counters(Counters* c)
+__global__ void __launch_bounds__(kBlock) k_clear_counters(Counters* c, NbrStats* st, uint32_t n_slots)
 {
-    c->err = 0u;
-    c->max_nbr = 0u;
-    c->nbr_sum = 0ull;
-    c->nbr_rows = 0ull;
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i == 0) c->err = 0u;
+    if (i < n_slots) {
+        st[i].max_nbr = 0u;
+        st[i].sum = 0ull;
+        st[i].rows = 0ull;
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
@@ -947,7 +984,9 @@ void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStr
 
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(1), 0, stream, s.counters);
+    const uint32_t slots = (uint32_t)blocks_for((size_t)s.n);
+    hipLaunchKernelGGL(k_clear_counters, dim3(blocks_for(slots > 0 ? slots : 1)), dim3(kBlock), 0, stream, s.counters,
+                       s.nbr_stats, slots);
     return hipGetLastError();
 }
 
