@@ -77,7 +77,7 @@ typedef enum {
  *  search_radius       neighbour predicate radius R_s, 0 = 2r.
  *  cell_size           hash-grid cell edge a >= R_s, 0 = R_s * (1 + 2^-10).
  *  grid_origin         hash-grid origin o.
- *  hash_bits           key bits k in [6, 28], 0 = max(10, ceil(log2(4N))).
+ *  hash_bits           key bits k in [6, 28], 0 = max(10, ceil(log2(8N))).
  *  planes              half-spaces n.x >= d + r, rows (nx, ny, nz, d), |n| = 1.
  *  nbr_cap             neighbour-list capacity per particle, 0 = 32, max 64.
  */

@@ -85,8 +85,8 @@ def _f32(a):
 
 
 def default_hash_bits(n: int) -> int:
-    """k = max(10, ceil(log2(4n))), at most 28."""
-    return int(min(28, max(10, math.ceil(math.log2(max(4 * n, 2))))))
+    """k = max(10, ceil(log2(8n))), at most 28."""
+    return int(min(28, max(10, math.ceil(math.log2(max(8 * n, 2))))))
 
 
 def make_params(h: float, iterations: int, radius: float, gravity=(0.0, 0.0, -9.81), mu: float = 0.4,

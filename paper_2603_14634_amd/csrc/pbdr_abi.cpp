@@ -83,7 +83,7 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
         r.k = p.hash_bits;
     } else {
         int k = 10;
-        while (k < kMaxHashBits && (1ll << k) < 4ll * (long long)n) ++k;
+        while (k < kMaxHashBits && (1ll << k) < 8ll * (long long)n) ++k;
         r.k = k;
     }
     r.cap = p.nbr_cap ? p.nbr_cap : 32;
@@ -137,7 +137,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
     L.cell_count = take(4 * T);
-    L.cells = take(16 * T);
+    L.cells = take(8 * (T + 1));
     L.tile_state = take(8 * tiles);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
@@ -159,8 +159,10 @@ struct pbdr_scene {
     pbdr::StepConsts consts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;          // one frame
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_n = nullptr;        // kGraphFrames frames
+    hipGraphExec_t exec_n = nullptr;
     char* ws = nullptr;
     size_t ws_bytes = 0;
     int max_body = 0;
@@ -169,12 +171,20 @@ struct pbdr_scene {
 
 namespace {
 
+// Frames per graph for long step() calls: replaying one graph per frame
+// leaves the GPU waiting on the host between graphs.
+constexpr int kGraphFrames = 8;
+
 void drop_graph(pbdr_scene* s)
 {
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->exec_n) (void)hipGraphExecDestroy(s->exec_n);
+    if (s->graph_n) (void)hipGraphDestroy(s->graph_n);
     s->exec = nullptr;
     s->graph = nullptr;
+    s->exec_n = nullptr;
+    s->graph_n = nullptr;
 }
 
 pbdr_status read_counters(pbdr_scene* s, pbdr::Counters* c)
@@ -274,7 +284,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
     d.cell_count = (uint32_t*)(w + L.cell_count);
-    d.cells = (uint4*)(w + L.cells);
+    d.cells = (uint2*)(w + L.cells);
     d.tile_state = (unsigned long long*)(w + L.tile_state);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
@@ -301,21 +311,24 @@ pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
     return PBDR_OK;
 }
 
-pbdr_status ensure_graph(pbdr_scene* s)
+// Captures `frames` frames (each ending with the state written back) into a
+// graph, instantiated once and replayed on the scene's stream.
+pbdr_status capture(pbdr_scene* s, int frames, hipGraph_t* graph, hipGraphExec_t* exec)
 {
-    if (s->exec) return PBDR_OK;
+    if (*exec) return PBDR_OK;
     if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
-    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->res.p.substeps, s->cap_stream);
+    hipError_t e = hipSuccess;
+    for (int f = 0; f < frames && e == hipSuccess; ++f)
+        e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->res.p.substeps, s->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        return fail(PBDR_ERR_DEVICE, "graph capture failed: %s",
-                    hipGetErrorString(e != hipSuccess ? e : e2));
+        return fail(PBDR_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    s->graph = g;
-    HIP_TRY(hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0));
+    *graph = g;
+    HIP_TRY(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0));
     return PBDR_OK;
 }
 
@@ -490,9 +503,17 @@ pbdr_status pbdr_scene_step(pbdr_scene* s, int32_t n_frames)
         if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
         return enqueue(s, (int32_t)total);
     }
-    pbdr_status st = ensure_graph(s);
-    if (st != PBDR_OK) return st;
-    for (int32_t f = 0; f < n_frames; ++f) HIP_TRY(hipGraphLaunch(s->exec, s->stream));
+    int32_t left = n_frames;
+    if (left >= kGraphFrames) {
+        pbdr_status st = capture(s, kGraphFrames, &s->graph_n, &s->exec_n);
+        if (st != PBDR_OK) return st;
+        for (; left >= kGraphFrames; left -= kGraphFrames) HIP_TRY(hipGraphLaunch(s->exec_n, s->stream));
+    }
+    if (left > 0) {
+        pbdr_status st = capture(s, 1, &s->graph, &s->exec);
+        if (st != PBDR_OK) return st;
+        for (; left > 0; --left) HIP_TRY(hipGraphLaunch(s->exec, s->stream));
+    }
     s->stepped = true;
     return PBDR_OK;
 }
@@ -583,15 +604,20 @@ pbdr_status pbdr_scene_read_debug(pbdr_scene* s, int32_t what, void* dst)
     switch (what) {
     case PBDR_DEBUG_XT: off = s->lay.xt; bytes = 12 * N; break;
     case PBDR_DEBUG_KEYS: off = s->lay.key; bytes = 4 * N; break;
-    case PBDR_DEBUG_SORTED: off = s->lay.sorted; bytes = 4 * N; break;
+    case PBDR_DEBUG_SORTED:
+        if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
+        HIP_TRY(pbdr::enqueue_canonical_order(s->dev, s->stream));
+        off = s->lay.sorted;
+        bytes = 4 * N;
+        break;
     case PBDR_DEBUG_CELL_START:
     case PBDR_DEBUG_CELL_COUNT: {   // fields of the per-key entries
-        std::vector<uint32_t> e(4 * T);
-        HIP_TRY(hipMemcpyAsync(e.data(), s->ws + s->lay.cells, 16 * T, hipMemcpyDeviceToHost, s->stream));
+        std::vector<uint32_t> e(2 * (T + 1));
+        HIP_TRY(hipMemcpyAsync(e.data(), s->ws + s->lay.cells, 8 * (T + 1), hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         uint32_t* out = (uint32_t*)dst;
-        const int f = what == PBDR_DEBUG_CELL_START ? 0 : 1;
-        for (size_t k = 0; k < T; ++k) out[k] = e[4 * k + f];
+        for (size_t k = 0; k < T; ++k)
+            out[k] = what == PBDR_DEBUG_CELL_START ? e[2 * k] : e[2 * (k + 1)] - e[2 * k];
         return PBDR_OK;
     }
     case PBDR_DEBUG_NBR_COUNT: off = s->lay.nbr_n; bytes = 4 * N; break;

@@ -78,12 +78,13 @@ struct Scene {
     uint32_t* key;            // [N]
     uint32_t* rank;           // [N] slot within the key from the counting pass
     uint32_t* sorted_raw;     // [N] ids grouped by key, arbitrary order within a key
-    uint32_t* sorted;         // [N] ids sorted by (key, id)
+    uint32_t* sorted;         // [N] ids sorted by (key, id), written on demand
     uint32_t* nbr_n;          // [N] neighbour-list length
     uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
     uint32_t* cell_count;     // [T] per-key counts (zero outside a substep)
-    uint4* cells;             // [T] per key: first sorted slot, count, body signature
-                              //     (the one body of all its particles, -1 empty, -2 mixed), 0
+    uint2* cells;             // [T + 1] per key: first sorted slot, body signature (the one
+                              //     body of all its particles, -1 empty, -2 mixed); the count of
+                              //     key k is cells[k + 1].x - cells[k].x, cells[T].x = N
     unsigned long long* tile_state;  // [n_scan_tiles] scan look-back: (status << 32) | value
 
     float* body_rot;          // [B][9] last rotation of shape matching
@@ -99,10 +100,13 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
 // but the first continue from the rotation of the launch before.
 hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream);
 
+// Writes the canonical (key, id) order of the last substep into `sorted`.
+hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream);
+
 // Clears the latched counters.
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream);
 
-// Zeroes the per-key counts and marks every key empty (once, at creation).
+// Zeroes the per-key counts and writes the end sentinel cells[T] (once, at creation).
 hipError_t enqueue_init_tables(const Scene& s, hipStream_t stream);
 
 }  // namespace pbdr

@@ -16,8 +16,7 @@
 //                  signature (its single body, or "mixed")
 //   neighbours     walks particles in key order: 27-cell stencil (skipping
 //                  keys that hold only the particle's own body), FP32
-//                  predicate, ascending lists; writes the canonical (key, id)
-//                  order
+//                  predicate, ascending lists
 //   iterate x K    bodies packed into workgroups, whole waves per body, one
 //                  particle per lane: particle contacts, shape matching
 //                  (Sec. III-C, Mueller et al. 2005), incremental velocity update
@@ -260,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
         const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
         uint32_t run = run_chunk + excl[ch];
         for (int k = 0; k < 4; ++k) {
-            if (base + k < s.T) s.cells[base + k] = make_uint4(run, vals[ch][k], 0xffffffffu, 0u);   // signature: empty
+            if (base + k < s.T) s.cells[base + k] = make_uint2(run, 0xffffffffu);   // signature: empty
             run += vals[ch][k];
         }
         run_chunk += chunk_tot[ch];
@@ -278,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
     s.sorted_raw[slot] = (uint32_t)i;
     s.sxt4[slot] = make_float4(s.xt[i], s.xt[n + i], s.xt[2 * n + i], __int_as_float(b));
     // body signature of the key: the one body of all its particles, or -2
-    int* sig = (int*)&s.cells[key].z;
+    int* sig = (int*)&s.cells[key].y;
     const int32_t old = atomicCAS(sig, -1, b);
     if (old != -1 && old != b && old != -2) atomicExch(sig, -2);
 }
@@ -309,17 +308,11 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
         for (int t = 0; t < 27; ++t) {
             const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
                                       cz + (uint32_t)(t / 9 - 1), c.key_mask);
-            const uint4 e = s.cells[k];
+            const uint2 e = s.cells[k];
+            const uint32_t end = s.cells[k + 1].x;
             lo[t] = e.x;
             // a key holding only this particle's body has no candidates
-            hi[t] = (int32_t)e.z == pb ? e.x : e.x + e.y;
-        }
-        // canonical slot of i inside its own key (stencil centre, t = 13)
-        {
-            const uint4 e = s.cells[morton(cx, cy, cz, c.key_mask)];
-            uint32_t below = 0;
-            for (uint32_t q = e.x; q < e.x + e.y; ++q) below += (s.sorted_raw[q] < i) ? 1u : 0u;
-            s.sorted[e.x + below] = i;
+            hi[t] = (int32_t)e.y == pb ? e.x : end;
         }
         auto consider = [&](uint32_t q, const float4 o) {
             if (__float_as_int(o.w) == pb) return;            // same body (also excludes i)
@@ -336,15 +329,24 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
             }
             lst[pos * kBlock + tid] = id;
         };
-        for (int t = 0; t < 27; ++t) {
-            // candidates four at a time, so their loads are in flight together
-            for (uint32_t q = lo[t]; q < hi[t]; q += 4) {
-                float4 o[4];
+        // one z-layer of 9 keys at a time: the first candidate of every key is
+        // loaded before any is examined, so the loads are in flight together;
+        // further candidates of a key (rare with >= 8 keys per particle) follow
 #pragma unroll
-                for (int u = 0; u < 4; ++u) o[u] = q + u < hi[t] ? s.sxt4[q + u] : me;
+        for (int dz = 0; dz < 3; ++dz) {
+            float4 o[9];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (q + u < hi[t]) consider(q + u, o[u]);
+            for (int u = 0; u < 9; ++u) {
+                const int t = 9 * dz + u;
+                o[u] = hi[t] > lo[t] ? s.sxt4[lo[t]] : me;
+            }
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                const int t = 9 * dz + u;
+                if (hi[t] > lo[t]) {
+                    consider(lo[t], o[u]);
+                    for (uint32_t q = lo[t] + 1; q < hi[t]; ++q) consider(q, s.sxt4[q]);
+                }
             }
         }
         s.nbr_n[i] = count;
@@ -939,6 +941,22 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
     }
 }
 
+// Canonical (key, id) order from the key grouping of the last substep: the
+// grouping keeps an arbitrary order inside a key (slots from atomic ranks);
+// particle i goes to its key's first slot plus the number of smaller ids
+// sharing its key.  Run on demand, outside the substep.
+__global__ void __launch_bounds__(kBlock) k_canonical(Scene s)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= s.n) return;
+    const uint32_t i = s.sorted_raw[j];
+    const uint32_t k = s.key[i];
+    const uint32_t b0 = s.cells[k].x, b1 = s.cells[k + 1].x;
+    uint32_t below = 0;
+    for (uint32_t q = b0; q < b1; ++q) below += (s.sorted_raw[q] < i) ? 1u : 0u;
+    s.sorted[b0 + below] = i;
+}
+
 __global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -971,6 +989,7 @@ __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
     if (i < s.T) s.cell_count[i] = 0u;
+    if (i == 0) s.cells[s.T] = make_uint2((uint32_t)s.n, 0xffffffffu);
 }
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -993,6 +1012,13 @@ hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
 hipError_t enqueue_init_tables(const Scene& s, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_init_tables, dim3(blocks_for((size_t)s.T)), dim3(kBlock), 0, stream, s);
+    return hipGetLastError();
+}
+
+hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream)
+{
+    if (s.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_canonical, dim3(blocks_for((size_t)s.n)), dim3(kBlock), 0, stream, s);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ def _gpu():
 
 
 def _hash_bits(n):
-    return int(min(28, max(10, math.ceil(math.log2(max(4 * n, 2))))))
+    return int(min(28, max(10, math.ceil(math.log2(max(8 * n, 2))))))
 
 
 def _orc_params(orc, sc, flags=0, cap=32, bits=None, threads=THREADS):
