@@ -1,0 +1,190 @@
+"""The paper's physics Tests 1-3 and the ablation of its two additions, on the GPU.
+
+Tests 1-3 (Table I, closed forms; Table II parameters; Sec. IV-B solver
+settings: 100 Hz frames, 10 substeps, 10 iterations): a 4x4x4 sphere box of
+4 kg pushed by 17 N against friction mu = 0.4, spun by a 0.01 N m torque without
+friction, and sliding down a slope (tilted gravity).  The closed forms are
+stated in tests/golden/paper_tests_1_3.json; the GPU path must meet them within
+the same bounds as the FP64 reference and stay close to the reference's own
+trajectory (these single-body runs are not chaotic).
+
+Ablation (Table III): the same sliding box with the modified velocity update
+replaced by the standard one, or with either momentum correction dropped.  The
+errors are printed; the full method must meet the closed form, and each
+ablation must show the direction of Table III: dropping the linear correction
+lets linear momentum drift, and the standard velocity update or dropping the
+angular correction lets the box turn (FP32 rounding drives both).  The paper's
+magnitudes come from its own engine and are not a pin here (parity unpinned).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_14634_amd import binding as B
+from paper_2603_14634_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tests_1_3.json")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load_library()
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _box(gd, test_id):
+    g = gd["not_in_paper"]["g_m_per_s2"]
+    r = gd["not_in_paper"]["sphere_radius_m"]
+    n = gd["spheres_per_axis"]
+    if test_id == 3:
+        th = gd["slope_angle_test_3_rad"]
+        grav, mu = (g * math.sin(th), 0.0, -g * math.cos(th)), gd["mu_tests_1_3"]
+    else:
+        grav, mu = (0.0, 0.0, -g), gd["mu_tests_1_3"] if test_id == 1 else gd["mu_test_2"]
+    off = scenes.lattice_box(n, n, n, 2 * r)
+    return scenes.single_body(off, centre=(0.0, 0.0, (n - 1) * r + r), mass=gd["box_mass_kg"] / n ** 3,
+                              radius=r, dt_frame=1.0 / gd["frame_rate_hz"], substeps=gd["substeps"],
+                              iterations=gd["iterations"], mu=mu, gravity=grav)
+
+
+def _lam(sc):
+    m = sc.mass.astype(np.float64)
+    x = sc.x.astype(np.float64)
+    c = (x * m).sum(axis=1) / m.sum()
+    return float((m * ((x[0] - c[0]) ** 2 + (x[1] - c[1]) ** 2)).sum())    # discrete I_zz
+
+
+def _accel(gd, test_id, sc, x, lam):
+    """External acceleration a_p = f_p / m_p of each test (force at the centre of
+    mass; torque as a_p = alpha z x (x_p - c), alpha = tau / I_zz)."""
+    acc = np.zeros((3, sc.n), np.float32)
+    if test_id == 1:
+        acc[0] = gd["force_test_1_N"] / gd["box_mass_kg"]
+    elif test_id == 2:
+        m = sc.mass.astype(np.float64)
+        xd = x.astype(np.float64)
+        c = (xd * m).sum(axis=1) / m.sum()
+        alpha = gd["torque_test_2_Nm"] / lam
+        acc[0] = -alpha * (xd[1] - c[1])
+        acc[1] = alpha * (xd[0] - c[0])
+    return acc
+
+
+def _run_gpu(gd, test_id, sc, frames, flags=0):
+    import torch
+
+    lam = _lam(sc)
+    s = B.Solver(B.params_for(sc, flags=flags), sc.x, sc.v, sc.mass, sc.body_start)
+    acc_d = torch.zeros((3, sc.n), dtype=torch.float32, device="cuda")
+    s.set_accel(acc_d)
+    if test_id == 2:
+        x = sc.x
+        for _ in range(frames):        # the torque's force field follows the body every frame
+            acc_d.copy_(torch.from_numpy(_accel(gd, test_id, sc, x, lam)))
+            s.step(1)
+            x, _ = s.read_state()
+    else:
+        acc_d.copy_(torch.from_numpy(_accel(gd, test_id, sc, sc.x, lam)))
+        s.step(frames)
+    x, v = s.read_state()
+    s.check()
+    s.close()
+    return x, v
+
+
+def _run_reference(orc, gd, test_id, sc, frames):
+    p = orc.params_for(sc, threads=1)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    lam = _lam(sc)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    for _ in range(frames):
+        x, v, _ = orc.substep(p, rest, x, v, accel=_accel(gd, test_id, sc, x, lam).astype(np.float64),
+                              n_substeps=sc.substeps)
+    return x, v
+
+
+def _observables(orc, sc, x):
+    m = sc.mass.astype(np.float64)
+    xd = np.asarray(x, dtype=np.float64)
+    c = (xd * m).sum(axis=1) / m.sum()
+    x0 = sc.x.astype(np.float64)
+    c0 = (x0 * m).sum(axis=1) / m.sum()
+    A = ((xd - c[:, None]) * m) @ (x0 - c0[:, None]).T
+    R = orc.polar(A)
+    return c, math.atan2(R[1, 0], R[0, 0])
+
+
+def _closed_form(gd, test_id, t):
+    g = gd["not_in_paper"]["g_m_per_s2"]
+    mu = gd["mu_tests_1_3"]
+    if test_id == 1:
+        return 0.5 * (gd["force_test_1_N"] - mu * gd["box_mass_kg"] * g) / gd["box_mass_kg"] * t * t
+    if test_id == 3:
+        th = gd["slope_angle_test_3_rad"]
+        return 0.5 * (g * math.sin(th) - mu * g * math.cos(th)) * t * t
+    return None
+
+
+@pytest.mark.parametrize("test_id", [1, 2, 3])
+def test_paper_tests_1_to_3(orc, test_id):
+    gd = _golden()
+    sc = _box(gd, test_id)
+    t_end = 2.0
+    frames = int(round(t_end * gd["frame_rate_hz"]))
+    print("[paper] test %d: %d frames" % (test_id, frames), flush=True)
+    xg, _ = _run_gpu(gd, test_id, sc, frames)
+    xr, _ = _run_reference(orc, gd, test_id, sc, frames)
+    cg, thg = _observables(orc, sc, xg)
+    cr, thr = _observables(orc, sc, xr)
+    if test_id == 2:
+        ref = 0.5 * gd["torque_test_2_Nm"] / _lam(sc) * t_end ** 2
+        print("[paper] test 2: theta gpu %.6f  reference %.6f  closed form %.6f" % (thg, thr, ref), flush=True)
+        assert thg == pytest.approx(ref, rel=0.03)
+        assert abs(thg - thr) <= 1e-3 * abs(ref)
+        assert np.abs(cg[:2]).max() < 1e-5
+    else:
+        ref = _closed_form(gd, test_id, t_end)
+        print("[paper] test %d: x gpu %.6f  reference %.6f  closed form %.6f" % (test_id, cg[0], cr[0], ref),
+              flush=True)
+        assert cg[0] == pytest.approx(ref, rel=0.03 if test_id == 1 else 0.05)
+        assert abs(cg[0] - cr[0]) <= 1e-3 * abs(ref)
+
+
+def test_ablation_of_velocity_update_and_momentum_constraint(orc):
+    """Table III's runs: the sliding box of Test 1 over 10 s, full method and
+    ablations.  Prints the position and momentum errors against the closed form."""
+    gd = _golden()
+    sc = _box(gd, 1)
+    t_end = 10.0
+    frames = int(round(t_end * gd["frame_rate_hz"]))
+    ref = _closed_form(gd, 1, t_end)
+    M = gd["box_mass_kg"]
+    a = 2.0 * _closed_form(gd, 1, 1.0)
+    p_ref = M * a * t_end
+    errs = {}
+    for name, flags in (("PBD-R", 0), ("standard velocity", B.FLAG_STD_VELOCITY),
+                        ("no linear momentum", B.FLAG_NO_LIN_MOM), ("no angular momentum", B.FLAG_NO_ANG_MOM)):
+        x, v = _run_gpu(gd, 1, sc, frames, flags=flags)
+        c, th = _observables(orc, sc, x)
+        p = float((v.astype(np.float64) * sc.mass.astype(np.float64)).sum(axis=1)[0])
+        errs[name] = (abs(c[0] - ref), abs(p - p_ref), abs(th))
+        print("[ablation] %-20s |x - x*| %.3e m  |P - P*| %.3e kg m/s  |rotation| %.3e rad"
+              % ((name,) + errs[name]), flush=True)
+    assert errs["PBD-R"][0] <= 0.03 * ref
+    full_p, full_rot = errs["PBD-R"][1], max(errs["PBD-R"][2], 1e-7)
+    assert errs["no linear momentum"][1] > 3.0 * full_p
+    assert errs["no angular momentum"][2] > 20.0 * full_rot
+    assert errs["standard velocity"][2] > 20.0 * full_rot
