@@ -220,6 +220,111 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* scene, pbdr_scene_info* out);
 /* Frees the host handle (and any captured graph).  The workspace is untouched. */
 void pbdr_scene_destroy(pbdr_scene* scene);
 
+/* ------------------------------------------------------------------------
+ * Scene pools: many independent small scenes stepped together.
+ *
+ * A pool holds up to max_scenes scenes of at most PBDR_POOL_MAX_PARTICLES
+ * particles and PBDR_POOL_MAX_BODIES bodies each, in arenas of max_particles
+ * particles and max_bodies bodies, all inside one device workspace owned by
+ * the caller (pbdr_pool_bytes).  Each scene is one workgroup that runs every
+ * substep of a step call on its own (Alg. 1 as for a single scene), so a
+ * call is a handful of launches however many scenes are resident.  Scenes
+ * share the pool's pbdr_params (time step, substeps, iterations, radius,
+ * planes, flags, nbr_cap; hash_bits and PBDR_FLAG_NO_GRAPH are ignored) and
+ * bring their own gravity and friction coefficient.
+ *
+ * A scene's result depends only on the scene: it is bitwise the same alone
+ * or among others and for every launch shape the tuner may choose.
+ * Admission: pbdr_pool_add fails with PBDR_ERR_CAPACITY when no slot, no
+ * contiguous particle range or no body range is free; pbdr_pool_info reports
+ * what is free.  Slots are reused after pbdr_pool_remove.
+ * ------------------------------------------------------------------------ */
+#define PBDR_POOL_MAX_PARTICLES 8192
+#define PBDR_POOL_MAX_BODIES 64
+#define PBDR_POOL_CLASSES 7      /* size classes: class c holds scenes of n <= 128 << c */
+
+typedef struct pbdr_pool pbdr_pool;
+
+/* One scene for a pool, in HOST memory (copied by pbdr_pool_add; the caller
+ * may free it on return).  x, v [3][N], mass [N], body_start [B+1] as in
+ * pbdr_scene_desc; rest offsets are derived from x in FP64. */
+typedef struct {
+    int32_t n_particles;
+    int32_t n_bodies;
+    const float* x;
+    const float* v;
+    const float* mass;
+    const int32_t* body_start;
+    double gravity[3];
+    double friction_mu;
+} pbdr_pool_scene_desc;
+
+typedef struct {
+    int32_t max_scenes, scenes_used;
+    int32_t max_particles, particles_used, largest_free_particles;
+    int32_t max_bodies, bodies_used, largest_free_bodies;
+    int32_t max_scene_particles;   /* largest scene this device can hold (LDS of its class) */
+    size_t workspace_bytes;
+} pbdr_pool_info;
+
+/* Device workspace bytes of a pool; 0 if invalid (see pbdr_last_error). */
+size_t pbdr_pool_bytes(const pbdr_params* params, int32_t max_scenes, int32_t max_particles, int32_t max_bodies);
+
+/* Creates an empty pool in dev_workspace (256-byte aligned, >= pbdr_pool_bytes)
+ * working on hip_stream (hipStream_t or NULL); synchronises it. */
+pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int32_t max_particles, int32_t max_bodies,
+                             void* dev_workspace, size_t ws_bytes, void* hip_stream, pbdr_pool** out);
+
+/* Adds a scene; *slot receives its slot.  The upload is enqueued on the pool's
+ * stream (asynchronous).  PBDR_ERR_CAPACITY if it does not fit now. */
+pbdr_status pbdr_pool_add(pbdr_pool* pool, const pbdr_pool_scene_desc* desc, int32_t* slot);
+
+/* Frees a slot and its arena ranges (its data is no longer readable). */
+pbdr_status pbdr_pool_remove(pbdr_pool* pool, int32_t slot);
+
+/* Advances every resident scene by n_frames frames (asynchronous). */
+pbdr_status pbdr_pool_step(pbdr_pool* pool, int32_t n_frames);
+
+/* Advances the listed slots by frames[j] frames each (0 = stays); the others
+ * stay.  For continuous batching, where scenes have different horizons. */
+pbdr_status pbdr_pool_step_slots(pbdr_pool* pool, int32_t count, const int32_t* slots, const int32_t* frames);
+
+/* Advances every resident scene by n_substeps substeps (for substep checks). */
+pbdr_status pbdr_pool_substep(pbdr_pool* pool, int32_t n_substeps);
+
+/* Copies a scene's positions and velocities ([3][N] each; host or device
+ * pointers; either may be NULL), synchronises, and returns the scene's latched
+ * device condition (PBDR_ERR_CAPACITY, PBDR_ERR_NONFINITE) if any. */
+pbdr_status pbdr_pool_read_state(pbdr_pool* pool, int32_t slot, float* x, float* v, int32_t on_device);
+
+/* Debug buffers of a scene's last substep, to HOST memory (synchronises):
+ * PBDR_DEBUG_XT, PBDR_DEBUG_NBR_COUNT, PBDR_DEBUG_NBR ([nbr_cap][N], ascending
+ * scene-local ids) and PBDR_DEBUG_DELTA, with the layouts of
+ * pbdr_scene_read_debug. */
+pbdr_status pbdr_pool_read_debug(pbdr_pool* pool, int32_t slot, int32_t what, void* dst_host);
+
+/* Synchronises; returns the scene's latched device condition and (if not
+ * NULL) its largest neighbour count so far. */
+pbdr_status pbdr_pool_check(pbdr_pool* pool, int32_t slot, int32_t* max_neighbours);
+
+/* Launch shape of each size class ([PBDR_POOL_CLASSES] arrays): waves per
+ * workgroup, 1, 2, 4, 8 or 16.  Each launch then gives every lane the fewest
+ * particle slots (1-6 or 8) that cover the class's largest stepped scene;
+ * a class whose scenes need more than 8 slots at the set width is widened. */
+pbdr_status pbdr_pool_get_tuning(const pbdr_pool* pool, int32_t* waves);
+pbdr_status pbdr_pool_set_tuning(pbdr_pool* pool, const int32_t* waves);
+
+/* Tuner: for every size class with resident scenes, times each admissible
+ * launch shape over n_frames frames of the class's scenes (best of `repeats`)
+ * and keeps the fastest.  Scene states are restored afterwards; synchronises.
+ * ms_out (may be NULL) receives [PBDR_POOL_CLASSES] the chosen shape's time. */
+pbdr_status pbdr_pool_autotune(pbdr_pool* pool, int32_t n_frames, int32_t repeats, double* ms_out);
+
+pbdr_status pbdr_pool_info_get(const pbdr_pool* pool, pbdr_pool_info* out);
+
+/* Frees the host handle; the workspace is untouched. */
+void pbdr_pool_destroy(pbdr_pool* pool);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,12 @@ EXPORTED = [
     "pbdr_scene_set_accel", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
     "pbdr_scene_read_state", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
     "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations", "pbdr_scene_destroy",
+    "pbdr_pool_bytes", "pbdr_pool_create", "pbdr_pool_add", "pbdr_pool_remove", "pbdr_pool_step",
+    "pbdr_pool_step_slots", "pbdr_pool_substep", "pbdr_pool_read_state", "pbdr_pool_read_debug",
+    "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
+    "pbdr_pool_info_get", "pbdr_pool_destroy",
 ]
+POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES = 8192, 64, 7
 
 
 class Params(ctypes.Structure):
@@ -79,6 +84,30 @@ class SceneInfo(ctypes.Structure):
     ]
 
 
+class PoolSceneDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_particles", ctypes.c_int32),
+        ("n_bodies", ctypes.c_int32),
+        ("x", ctypes.c_void_p),
+        ("v", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("body_start", ctypes.c_void_p),
+        ("gravity", ctypes.c_double * 3),
+        ("friction_mu", ctypes.c_double),
+    ]
+
+
+class PoolInfo(ctypes.Structure):
+    _fields_ = [
+        ("max_scenes", ctypes.c_int32), ("scenes_used", ctypes.c_int32),
+        ("max_particles", ctypes.c_int32), ("particles_used", ctypes.c_int32),
+        ("largest_free_particles", ctypes.c_int32),
+        ("max_bodies", ctypes.c_int32), ("bodies_used", ctypes.c_int32), ("largest_free_bodies", ctypes.c_int32),
+        ("max_scene_particles", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
 class PbdrError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("pbdr status %d: %s" % (status, message))
@@ -121,6 +150,23 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     lib.pbdr_scene_destroy.restype = None
     lib.pbdr_scene_destroy.argtypes = [vp]
+    pi32 = ctypes.POINTER(i32)
+    lib.pbdr_pool_bytes.restype = sz
+    lib.pbdr_pool_bytes.argtypes = [ctypes.POINTER(Params), i32, i32, i32]
+    lib.pbdr_pool_create.restype = i32
+    lib.pbdr_pool_create.argtypes = [ctypes.POINTER(Params), i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    for name, args in [("pbdr_pool_add", [vp, ctypes.POINTER(PoolSceneDesc), pi32]), ("pbdr_pool_remove", [vp, i32]),
+                       ("pbdr_pool_step", [vp, i32]), ("pbdr_pool_step_slots", [vp, i32, vp, vp]),
+                       ("pbdr_pool_substep", [vp, i32]), ("pbdr_pool_read_state", [vp, i32, vp, vp, i32]),
+                       ("pbdr_pool_read_debug", [vp, i32, i32, vp]), ("pbdr_pool_check", [vp, i32, pi32]),
+                       ("pbdr_pool_get_tuning", [vp, vp]), ("pbdr_pool_set_tuning", [vp, vp]),
+                       ("pbdr_pool_autotune", [vp, i32, i32, vp]),
+                       ("pbdr_pool_info_get", [vp, ctypes.POINTER(PoolInfo)])]:
+        fn = getattr(lib, name)
+        fn.restype = i32
+        fn.argtypes = args
+    lib.pbdr_pool_destroy.restype = None
+    lib.pbdr_pool_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -296,6 +342,135 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.pbdr_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def pool_bytes(params: Params, max_scenes: int, max_particles: int, max_bodies: int) -> int:
+    return int(load_library().pbdr_pool_bytes(ctypes.byref(params), max_scenes, max_particles, max_bodies))
+
+
+class Pool:
+    """Many small scenes resident together (include/pbdr.h, scene pools)."""
+
+    def __init__(self, params: Params, max_scenes: int, max_particles: int, max_bodies: int,
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        self._lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP GPU is required")
+        self.device = torch.device(device)
+        self.params = params
+        nbytes = self._lib.pbdr_pool_bytes(ctypes.byref(params), max_scenes, max_particles, max_bodies)
+        if nbytes == 0:
+            raise PbdrError(ERR_INVALID_ARG, last_error())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        _check(self._lib.pbdr_pool_create(ctypes.byref(params), max_scenes, max_particles, max_bodies,
+                                          self.workspace.data_ptr(), int(nbytes),
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
+        self._h = handle
+        self.sizes = {}
+
+    def try_add(self, scene):
+        """Adds a ``scenes.Scene``; returns its slot, or None if it does not fit now."""
+        x = _host_f32(scene.x, (3, scene.n))
+        v = _host_f32(scene.v, (3, scene.n))
+        m = _host_f32(scene.mass, (scene.n,))
+        bs = np.ascontiguousarray(scene.body_start, dtype=np.int32)
+        desc = PoolSceneDesc(scene.n, scene.n_bodies, x.ctypes.data, v.ctypes.data, m.ctypes.data, bs.ctypes.data)
+        desc.gravity[:] = [float(g) for g in scene.gravity]
+        desc.friction_mu = float(scene.mu)
+        slot = ctypes.c_int32(-1)
+        st = self._lib.pbdr_pool_add(self._h, ctypes.byref(desc), ctypes.byref(slot))
+        if st == ERR_CAPACITY:
+            return None
+        _check(st)
+        self.sizes[int(slot.value)] = scene.n
+        return int(slot.value)
+
+    def add(self, scene) -> int:
+        slot = self.try_add(scene)
+        if slot is None:
+            raise PbdrError(ERR_CAPACITY, last_error())
+        return slot
+
+    def remove(self, slot: int):
+        _check(self._lib.pbdr_pool_remove(self._h, slot))
+        self.sizes.pop(slot, None)
+
+    def step(self, n_frames: int = 1):
+        _check(self._lib.pbdr_pool_step(self._h, n_frames))
+
+    def step_slots(self, slots, frames):
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        f = np.ascontiguousarray(frames, dtype=np.int32)
+        if s.shape != f.shape:
+            raise ValueError("slots and frames differ in length")
+        _check(self._lib.pbdr_pool_step_slots(self._h, int(s.shape[0]), s.ctypes.data, f.ctypes.data))
+
+    def substep(self, n_substeps: int = 1):
+        _check(self._lib.pbdr_pool_substep(self._h, n_substeps))
+
+    def read_state(self, slot: int):
+        n = self.sizes[slot]
+        x = np.empty((3, n), dtype=np.float32)
+        v = np.empty((3, n), dtype=np.float32)
+        _check(self._lib.pbdr_pool_read_state(self._h, slot, x.ctypes.data, v.ctypes.data, 0))
+        return x, v
+
+    def status(self, slot: int) -> int:
+        mx = ctypes.c_int32()
+        return int(self._lib.pbdr_pool_check(self._h, slot, ctypes.byref(mx)))
+
+    def check(self, slot: int) -> int:
+        mx = ctypes.c_int32()
+        _check(self._lib.pbdr_pool_check(self._h, slot, ctypes.byref(mx)))
+        return int(mx.value)
+
+    def read_debug(self, slot: int, what: int) -> np.ndarray:
+        n = self.sizes[slot]
+        cap = self.params.nbr_cap or 32
+        shapes = {DEBUG_XT: ((3, n), np.float32), DEBUG_NBR_COUNT: ((n,), np.uint32),
+                  DEBUG_NBR: ((cap, n), np.uint32), DEBUG_DELTA: ((3, n), np.float32)}
+        shape, dt = shapes[what]
+        out = np.empty(shape, dtype=dt)
+        _check(self._lib.pbdr_pool_read_debug(self._h, slot, what, out.ctypes.data))
+        return out
+
+    @property
+    def tuning(self):
+        w = np.zeros(POOL_CLASSES, dtype=np.int32)
+        _check(self._lib.pbdr_pool_get_tuning(self._h, w.ctypes.data))
+        return [int(a) for a in w]
+
+    @tuning.setter
+    def tuning(self, waves):
+        w = np.ascontiguousarray(waves, dtype=np.int32)
+        if w.shape != (POOL_CLASSES,):
+            raise ValueError("one entry per size class")
+        _check(self._lib.pbdr_pool_set_tuning(self._h, w.ctypes.data))
+
+    def autotune(self, n_frames: int = 2, repeats: int = 2):
+        ms = np.zeros(POOL_CLASSES, dtype=np.float64)
+        _check(self._lib.pbdr_pool_autotune(self._h, n_frames, repeats, ms.ctypes.data))
+        return [float(a) for a in ms]
+
+    def info(self) -> PoolInfo:
+        out = PoolInfo()
+        _check(self._lib.pbdr_pool_info_get(self._h, ctypes.byref(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pbdr_pool_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -15,8 +15,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbdr.so")
-SOURCES = ["pbdr_kernels.hip", "pbdr_abi.cpp"]
+SOURCES = ["pbdr_kernels.hip", "pbdr_pool_kernels.hip", "pbdr_abi.cpp", "pbdr_pool.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+# The pool kernel is instantiated for several launch shapes; contraction only
+# within one source expression keeps its rounding identical in all of them.
+EXTRA_FLAGS = {"pbdr_pool_kernels.hip": ["-ffp-contract=on"]}
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -29,7 +33,7 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+        cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + EXTRA_FLAGS.get(src, [])
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

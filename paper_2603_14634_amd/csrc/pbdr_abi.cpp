@@ -14,8 +14,10 @@
 #include <vector>
 
 #include "pbdr_device.h"
+#include "pbdr_host.h"
 
-namespace {
+namespace pbdr {
+namespace host {
 
 thread_local char g_err[512] = "";
 
@@ -28,22 +30,7 @@ pbdr_status fail(pbdr_status st, const char* fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess) return fail(PBDR_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-constexpr uint32_t kKnownFlags = PBDR_FLAG_STD_VELOCITY | PBDR_FLAG_NO_LIN_MOM | PBDR_FLAG_NO_ANG_MOM |
-                                 PBDR_FLAG_NO_GRAPH | PBDR_PP_AVG_MASK;
-constexpr int32_t kMaxParticles = 1 << 28;
-constexpr int kMinHashBits = 6, kMaxHashBits = 28;
-
-struct Resolved {
-    pbdr_params p;
-    double h, rs, a;
-    int k, cap;
-};
+void clear_error() { g_err[0] = 0; }
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
@@ -90,6 +77,16 @@ pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
     *out = r;
     return PBDR_OK;
 }
+
+}  // namespace host
+}  // namespace pbdr
+
+namespace {
+
+using pbdr::host::fail;
+using pbdr::host::Resolved;
+using pbdr::host::resolve;
+using pbdr::host::g_err;
 
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,

@@ -1,0 +1,581 @@
+// Scene pools on gfx950: many independent small scenes, one workgroup each.
+//
+// A workgroup runs every substep of its scene for the whole call (units x
+// substeps), with workgroup barriers only: scenes never interact, so no grid
+// synchronisation or relaunch is needed between substeps or iterations.  The
+// substep is the same as the single-scene path (Alg. 1 with the velocity update
+// of Sec. III-B and the momentum constraint of Sec. III-C, Eqs. (4)-(5)):
+//
+//   predict      integration step; the particle's state stays in registers
+//                across substeps (X_init, V), X_init is also published for
+//                neighbours
+//   index        cell keys counted into a workgroup-local hash table in LDS,
+//                scanned, particles grouped by key (scene-local ids and bodies
+//                in LDS, predicted positions in global memory)
+//   neighbours   27-cell walk, same-body candidates skipped from LDS before any
+//                position is loaded, FP32 predicate, ascending lists
+//   iterate x K  contacts, shape matching and momentum constraint; per-body
+//                sums are deterministic segmented wave scans (DPP) over
+//                64-particle slots, combined in slot order by one lane per body
+//
+// Particle i of a scene sits in slot i / 64, lane i % 64; slot s is handled by
+// wave s % W in register set s / W.  Every sum and every list is independent of
+// W, of the register sets per lane and of the hash-table size, so a scene's
+// result does not depend on the launch shape the tuner picks or on the other
+// scenes of the pool.
+#include "pbdr_math.h"
+#include "pbdr_pool_device.h"
+
+namespace pbdr {
+namespace {
+
+using namespace dev;
+
+constexpr int kSums = 24;             // per-segment partial sums (12 shape matching, 21 momentum)
+
+// DPP move of v within the wave (0 where the pattern has no source lane).
+template <int CTRL, int ROWS>
+__device__ inline float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, true));
+}
+
+// Inclusive segmented sum over the wave, in a fixed order: lane l ends with the
+// sum of lanes lo..l, where lo <= l is the first lane of l's segment (segments
+// are runs of consecutive lanes).  Row-local Hillis-Steele steps (row_shr),
+// then the row carries (row_bcast 15 and 31), each taken only if the source
+// lane lies in the same segment.
+__device__ inline float seg_sum(float v, int lane, int lo)
+{
+    const int row0 = lane & ~15;
+    const int lo_row = lo > row0 ? lo : row0;
+    float y;
+    y = dpp_mov<0x111, 0xf>(v); v += (lane - 1 >= lo_row) ? y : 0.0f;
+    y = dpp_mov<0x112, 0xf>(v); v += (lane - 2 >= lo_row) ? y : 0.0f;
+    y = dpp_mov<0x114, 0xf>(v); v += (lane - 4 >= lo_row) ? y : 0.0f;
+    y = dpp_mov<0x118, 0xf>(v); v += (lane - 8 >= lo_row) ? y : 0.0f;
+    y = dpp_mov<0x142, 0xa>(v); v += ((lane & 16) && row0 - 1 >= lo) ? y : 0.0f;   // rows 1, 3 from 15, 47
+    y = dpp_mov<0x143, 0xc>(v); v += (lane >= 32 && 31 >= lo) ? y : 0.0f;          // rows 2, 3 from 31
+    return v;
+}
+
+// Exclusive scan of one value per thread over the workgroup; `tot` gets the total.
+__device__ inline uint32_t wg_exclusive_scan(uint32_t v, uint32_t* wave_tot, uint32_t* tot)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wave_tot[wave] = x;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int w = 0; w < W; ++w) {
+        const uint32_t t = wave_tot[w];
+        if (w < wave) before += t;
+        all += t;
+    }
+    *tot = all;
+    __syncthreads();          // wave_tot may be reused right after
+    return before + x - v;
+}
+
+// Per-body LDS record (floats).
+enum : int {
+    kBM = 0,          // body mass
+    kBMq = 1,         // sum m q (3)
+    kBAnchor = 4,     // X_init of the body's first particle (3)
+    kBR = 7,          // rotation (9)
+    kBC = 16,         // centre relative to the anchor (3)
+    kBDv = 19,        // linear correction (3)
+    kBW = 22,         // angular velocity correction (3)
+    kBCa = 25,        // c_asm - c_i (3)
+    kBRprev = 28,     // previous iteration's rotation (9)
+    kBFirst = 37,     // first particle (int bits)
+    kBEnd = 38,       // one past the last particle (int bits)
+};
+
+// Offsets of a particle in the frame centred on the body's current centre:
+// r = (X_i - anchor) - c and the shape-matching goal offset D = R q - r.
+__device__ inline void goal_offsets(bool act, const float* br, const float* x0, const float* del, const float* q,
+                                    float* rr, float* Dd)
+{
+    for (int k = 0; k < 3; ++k) rr[k] = ((x0[k] - br[kBAnchor + k]) + del[k]) - br[kBC + k];
+    for (int a = 0; a < 3; ++a)
+        Dd[a] = act ? (br[kBR + 3 * a] * q[0] + br[kBR + 3 * a + 1] * q[1] + br[kBR + 3 * a + 2] * q[2]) - rr[a] : 0.0f;
+}
+
+template <int S, int LB>
+__global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first, int subs_per_unit,
+                                                              int kb, int bound)
+{
+    extern __shared__ uint32_t lds[];
+    const uint32_t Tc = 1u << kb;
+    uint32_t* tab = lds;                                          // [Tc + 1] key counts -> first slots
+    uint32_t* sid = tab + ((Tc + 1 + 3) & ~3u);                   // [bound] id | body << 16, key-grouped
+    float* part = (float*)(sid + bound);                          // [(64 + bound / 64) * kSums]
+    float* bod = part + (kPoolMaxBodies + bound / 64) * kSums;    // [64 * kPoolBodyFloats]
+    uint32_t* misc = (uint32_t*)(bod + kPoolMaxBodies * kPoolBodyFloats);   // wave totals [16], flags
+
+    const int slot = d.order[first + blockIdx.x];
+    const PoolScene& sc = d.scenes[slot];
+    const int n = sc.n, nb = sc.nb, p0 = sc.p0, b0 = sc.b0;
+    const int units = sc.units;
+    if (units <= 0 || n <= 0) return;                              // uniform over the workgroup
+    const int total_subs = units * subs_per_unit;
+    const int T = blockDim.x, W = T >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
+    const size_t P = (size_t)d.P;
+    const float gx = sc.g[0], gy = sc.g[1], gz = sc.g[2], mu = sc.mu;
+    const uint32_t avg = (c.flags >> kAvgShift) & 3u;
+    const uint32_t mask = Tc - 1u;
+    const int cap = c.nbr_cap;
+    uint32_t* lists = d.nbr + (size_t)cap * p0;
+
+    // body records
+    for (int b = tid; b < nb; b += T) {
+        float* r = bod + b * kPoolBodyFloats;
+        r[kBM] = d.body_mass[b0 + b];
+        for (int k = 0; k < 3; ++k) r[kBMq + k] = d.body_mq[3 * (size_t)(b0 + b) + k];
+        const int f = d.body_first[b0 + b];
+        const int e = b + 1 < nb ? d.body_first[b0 + b + 1] : n;
+        r[kBFirst] = __int_as_float(f);
+        r[kBEnd] = __int_as_float(e);
+    }
+    if (tid == 0) {
+        misc[16] = 0u;   // error bits
+        misc[17] = 0u;   // largest list
+    }
+
+    // per-lane particles: register set r holds particle ((r * W + wave) * 64 + lane)
+    float x0[S][3], V[S][3], del[S][3], q[S][3], m[S], Cd[S][3];
+    int bdy[S], lo[S];
+    uint32_t nn[S];
+    bool act[S];
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const int i = (r * W + wave) * 64 + lane;
+        act[r] = i < n;
+        m[r] = 0.0f;
+        bdy[r] = 0;
+        nn[r] = 0u;
+        for (int k = 0; k < 3; ++k) x0[r][k] = V[r][k] = del[r][k] = q[r][k] = Cd[r][k] = 0.0f;
+        if (act[r]) {
+            const size_t g = (size_t)p0 + i;
+            for (int k = 0; k < 3; ++k) {
+                x0[r][k] = d.x[k * P + g];
+                V[r][k] = d.v[k * P + g];
+                q[r][k] = d.q[k * P + g];
+            }
+            m[r] = d.mass[g];
+            bdy[r] = d.pbody[g];
+        }
+    }
+    __syncthreads();   // body records
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        const int s = r * W + wave;
+        const int f = __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBFirst]);
+        lo[r] = act[r] ? (f > s * 64 ? f - s * 64 : 0) : lane;    // first lane of this particle's segment
+    }
+
+    for (int sub = 0; sub < total_subs; ++sub) {
+        const bool last_sub = sub + 1 == total_subs;
+        // ---- predict + key counts -------------------------------------------
+        for (uint32_t k = tid; k <= Tc; k += T) tab[k] = 0u;
+        __syncthreads();
+        uint32_t key[S], rank[S];
+        float xt[S][3];
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            key[r] = 0u;
+            rank[r] = 0u;
+            if (!act[r]) continue;
+            const int i = (r * W + wave) * 64 + lane;
+            const size_t g = (size_t)p0 + i;
+            const float gg[3] = {gx, gy, gz};
+            {
+#pragma clang fp contract(off)
+                for (int k = 0; k < 3; ++k) {
+                    const float dv = c.h * gg[k];
+                    const float vt = V[r][k] + dv;
+                    const float dx = c.h * vt;
+                    xt[r][k] = x0[r][k] + dx;
+                    del[r][k] = dx;        // delta_0 = X~ - X_init
+                    V[r][k] = vt;          // V_0 = V~
+                }
+            }
+            for (int k = 0; k < 3; ++k) {
+                d.x[k * P + g] = x0[r][k];       // X_init, read by neighbours
+                d.dl[k * P + g] = del[r][k];
+                if (last_sub) d.xt[k * P + g] = xt[r][k];
+            }
+            key[r] = morton(cell_axis(xt[r][0], c.origin[0], c.inv_cell), cell_axis(xt[r][1], c.origin[1], c.inv_cell),
+                            cell_axis(xt[r][2], c.origin[2], c.inv_cell), mask);
+            rank[r] = atomicAdd(&tab[key[r]], 1u);
+            if (i == __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBFirst]))   // body anchor: X_init of its first particle
+                for (int k = 0; k < 3; ++k) bod[bdy[r] * kPoolBodyFloats + kBAnchor + k] = x0[r][k];
+        }
+        __syncthreads();
+        // ---- scan of the key counts ------------------------------------------
+        {
+            const uint32_t per = Tc > (uint32_t)T ? Tc / (uint32_t)T : 1u;
+            const uint32_t k0 = (uint32_t)tid * per;
+            uint32_t run = 0;
+            if (k0 < Tc)
+                for (uint32_t j = 0; j < per; ++j) run += tab[k0 + j];
+            uint32_t tot;
+            uint32_t ex = wg_exclusive_scan(run, misc, &tot);
+            if (k0 < Tc)
+                for (uint32_t j = 0; j < per; ++j) {
+                    const uint32_t cnt = tab[k0 + j];
+                    tab[k0 + j] = ex;
+                    ex += cnt;
+                }
+            if (tid == 0) tab[Tc] = (uint32_t)n;
+        }
+        __syncthreads();
+        // ---- group by key ----------------------------------------------------
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act[r]) continue;
+            const int i = (r * W + wave) * 64 + lane;
+            const uint32_t at = tab[key[r]] + rank[r];
+            sid[at] = (uint32_t)i | ((uint32_t)bdy[r] << 16);
+            d.sxt4[(size_t)p0 + at] = make_float4(xt[r][0], xt[r][1], xt[r][2], 0.0f);
+        }
+        __syncthreads();
+        // ---- neighbour lists ---------------------------------------------------
+        uint32_t my_max = 0;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act[r]) continue;
+            const int i = (r * W + wave) * 64 + lane;
+            const uint32_t cx = cell_axis(xt[r][0], c.origin[0], c.inv_cell);
+            const uint32_t cy = cell_axis(xt[r][1], c.origin[1], c.inv_cell);
+            const uint32_t cz = cell_axis(xt[r][2], c.origin[2], c.inv_cell);
+            uint32_t cnt = 0;
+            for (int t = 0; t < 27; ++t) {
+                const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
+                                          cz + (uint32_t)(t / 9 - 1), mask);
+                const uint32_t a = tab[k], e = tab[k + 1];
+                for (uint32_t qq = a; qq < e; ++qq) {
+                    const uint32_t en = sid[qq];
+                    if ((int)(en >> 16) == bdy[r]) continue;              // same body (also i itself)
+                    const float4 o = d.sxt4[(size_t)p0 + qq];
+                    if (!within(xt[r][0], xt[r][1], xt[r][2], o.x, o.y, o.z, c.search_r2)) continue;
+                    const uint32_t id = en & 0xffffu;
+                    // insert keeping the `cap` smallest ids in ascending order
+                    const int mm = (int)(cnt < (uint32_t)cap ? cnt : (uint32_t)cap);
+                    ++cnt;
+                    if (mm == cap && id > lists[(size_t)(cap - 1) * n + i]) continue;
+                    int pos = mm == cap ? cap - 1 : mm;
+                    while (pos > 0) {
+                        const uint32_t prev = lists[(size_t)(pos - 1) * n + i];
+                        if (prev < id) break;
+                        lists[(size_t)pos * n + i] = prev;
+                        --pos;
+                    }
+                    lists[(size_t)pos * n + i] = id;
+                }
+            }
+            nn[r] = cnt;
+            d.nbr_n[(size_t)p0 + i] = cnt;
+            my_max = cnt > my_max ? cnt : my_max;
+        }
+        for (int off = 32; off > 0; off >>= 1) my_max = max(my_max, (uint32_t)__shfl_xor(my_max, off, 64));
+        if (lane == 0 && my_max) {
+            atomicMax(&misc[17], my_max);
+            if (my_max > (uint32_t)cap) atomicOr(&misc[16], kErrCapacity);
+        }
+        __syncthreads();   // lists, counts, X_init and delta_0 visible to the workgroup
+
+        // ---- K Jacobi iterations ---------------------------------------------
+        for (int it = 0; it < c.iterations; ++it) {
+            // contacts from X_i and the shape-matching sums
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                for (int k = 0; k < 3; ++k) Cd[r][k] = 0.0f;
+                const int s = r * W + wave;
+                const int i = s * 64 + lane;
+                if (act[r]) {
+                    for (int pl = 0; pl < c.n_planes; ++pl) {
+                        const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
+                        const float un = nx * del[r][0] + ny * del[r][1] + nz * del[r][2];
+                        const float e = ((nx * x0[r][0] + ny * x0[r][1] + nz * x0[r][2]) - c.plane_d[pl]) + un;
+                        if (!(e < c.radius)) continue;
+                        const float pen = c.radius - e;
+                        const float ux = del[r][0] - un * nx, uy = del[r][1] - un * ny, uz = del[r][2] - un * nz;
+                        const float ut2 = ux * ux + uy * uy + uz * uz;
+                        const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+                        Cd[r][0] += pen * nx - f * ux;
+                        Cd[r][1] += pen * ny - f * uy;
+                        Cd[r][2] += pen * nz - f * uz;
+                    }
+                    const uint32_t ni = nn[r];
+                    const uint32_t stored = ni < (uint32_t)cap ? ni : (uint32_t)cap;
+                    for (uint32_t sl = 0; sl < stored; ++sl) {
+                        const uint32_t jq = lists[(size_t)sl * n + i];
+                        const size_t gq = (size_t)p0 + jq;
+                        float dd[3], u[3];
+                        for (int k = 0; k < 3; ++k) {
+                            const float dj = d.dl[k * P + gq];
+                            dd[k] = (x0[r][k] - d.x[k * P + gq]) + (del[r][k] - dj);
+                            u[k] = del[r][k] - dj;
+                        }
+                        const float l2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+                        const float l = __builtin_amdgcn_sqrtf(l2);
+                        if (!(l > 0.0f) || !(l < c.two_r)) continue;
+                        const float il = frcp(l);
+                        const float nx = dd[0] * il, ny = dd[1] * il, nz = dd[2] * il;
+                        const float pen = c.two_r - l;
+                        const float mq = d.mass[gq];
+                        const float alpha = mq * frcp(m[r] + mq);
+                        const float un = u[0] * nx + u[1] * ny + u[2] * nz;
+                        const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
+                        const float ut2 = ux * ux + uy * uy + uz * uz;
+                        const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+                        float wgt = 1.0f;
+                        if (avg == 0u) {
+                            const uint32_t nq = d.nbr_n[gq];
+                            wgt = frcp((float)(ni > nq ? ni : nq));
+                        } else if (avg == 1u) {
+                            wgt = frcp((float)ni);
+                        }
+                        const float scl = alpha * wgt;
+                        Cd[r][0] += scl * (pen * nx - f * ux);
+                        Cd[r][1] += scl * (pen * ny - f * uy);
+                        Cd[r][2] += scl * (pen * nz - f * uz);
+                    }
+                }
+                const float* br = bod + bdy[r] * kPoolBodyFloats;
+                float y[3];
+                for (int k = 0; k < 3; ++k) y[k] = act[r] ? (x0[r][k] - br[kBAnchor + k]) + del[r][k] : 0.0f;
+                // shape matching: sum m y and sum m y q^T (Sec. III-C)
+                float Sv[12];
+                for (int k = 0; k < 3; ++k) Sv[k] = m[r] * y[k];
+                for (int a = 0; a < 3; ++a)
+                    for (int k2 = 0; k2 < 3; ++k2) Sv[3 + 3 * a + k2] = m[r] * y[a] * q[r][k2];
+                for (int j = 0; j < 12; ++j) Sv[j] = seg_sum(Sv[j], lane, lo[r]);
+                if (act[r]) {
+                    const int bend = __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBEnd]);
+                    if (lane == 63 || i + 1 == bend) {
+                        float* pp = part + (bdy[r] + s) * kSums;
+                        for (int j = 0; j < 12; ++j) pp[j] = Sv[j];
+                    }
+                }
+            }
+            __syncthreads();
+            // per body: centre, covariance, rotation
+            for (int b = tid; b < nb; b += T) {
+                float* br = bod + b * kPoolBodyFloats;
+                const int f = __float_as_int(br[kBFirst]), e = __float_as_int(br[kBEnd]);
+                float Tt[12];
+                for (int j = 0; j < 12; ++j) Tt[j] = 0.0f;
+                for (int s = f >> 6; s <= (e - 1) >> 6; ++s) {
+                    const float* pp = part + (b + s) * kSums;
+                    for (int j = 0; j < 12; ++j) Tt[j] += pp[j];
+                }
+                const float im = frcp(br[kBM]);
+                float cc[3], A[9], Rb[9];
+                for (int k = 0; k < 3; ++k) cc[k] = Tt[k] * im;
+                for (int a = 0; a < 3; ++a)
+                    for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = Tt[3 + 3 * a + k2] - cc[a] * br[kBMq + k2];
+                if (!(it > 0 && polar_refine(A, br + kBRprev, Rb))) polar_rotation(A, Rb);
+                for (int j = 0; j < 9; ++j) br[kBR + j] = br[kBRprev + j] = Rb[j];
+                for (int k = 0; k < 3; ++k) br[kBC + k] = cc[k];
+            }
+            __syncthreads();
+            // goal offsets and the momentum sums
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                const int s = r * W + wave;
+                const int i = s * 64 + lane;
+                const float* br = bod + bdy[r] * kPoolBodyFloats;
+                float rr[3], Dd[3];
+                goal_offsets(act[r], br, x0[r], del[r], q[r], rr, Dd);
+                float Sv[21], zb[3], za[3], vb[3], t3[3];
+                for (int k = 0; k < 3; ++k) {
+                    zb[k] = rr[k] + Cd[r][k];
+                    za[k] = zb[k] + Dd[k];
+                    vb[k] = V[r][k] + Cd[r][k] * c.inv_h;
+                    Sv[k] = m[r] * Cd[r][k];
+                    Sv[3 + k] = m[r] * Dd[k];
+                    Sv[6 + k] = m[r] * vb[k];
+                }
+                cross(zb, Dd, t3);
+                for (int k = 0; k < 3; ++k) Sv[9 + k] = m[r] * t3[k];
+                cross(Dd, vb, t3);
+                for (int k = 0; k < 3; ++k) Sv[12 + k] = m[r] * t3[k];
+                Sv[15] = m[r] * (za[1] * za[1] + za[2] * za[2]);
+                Sv[16] = m[r] * (za[0] * za[0] + za[2] * za[2]);
+                Sv[17] = m[r] * (za[0] * za[0] + za[1] * za[1]);
+                Sv[18] = -m[r] * za[0] * za[1];
+                Sv[19] = -m[r] * za[0] * za[2];
+                Sv[20] = -m[r] * za[1] * za[2];
+                for (int j = 0; j < 21; ++j) Sv[j] = seg_sum(Sv[j], lane, lo[r]);
+                if (act[r]) {
+                    const int bend = __float_as_int(br[kBEnd]);
+                    if (lane == 63 || i + 1 == bend) {
+                        float* pp = part + (bdy[r] + s) * kSums;
+                        for (int j = 0; j < 21; ++j) pp[j] = Sv[j];
+                    }
+                }
+            }
+            __syncthreads();
+            // per body: momentum conservation constraint, Eqs. (4)-(5)
+            for (int b = tid; b < nb; b += T) {
+                float* br = bod + b * kPoolBodyFloats;
+                const int f = __float_as_int(br[kBFirst]), e = __float_as_int(br[kBEnd]);
+                float Tt[21];
+                for (int j = 0; j < 21; ++j) Tt[j] = 0.0f;
+                for (int s = f >> 6; s <= (e - 1) >> 6; ++s) {
+                    const float* pp = part + (b + s) * kSums;
+                    for (int j = 0; j < 21; ++j) Tt[j] += pp[j];
+                }
+                const float Mb = br[kBM], im = frcp(Mb);
+                float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
+                for (int k = 0; k < 3; ++k) {
+                    cb[k] = Tt[k] * im;
+                    Db[k] = Tt[3 + k] * im;
+                    cab[k] = cb[k] + Db[k];
+                }
+                if (!(c.flags & kFlagNoLinMom))
+                    for (int k = 0; k < 3; ++k) dvb[k] = -Tt[3 + k] * c.inv_h * im;
+                if (!(c.flags & kFlagNoAngMom)) {
+                    float cbxD[3], DbxP[3], dL[3], I6[6];
+                    cross(cb, &Tt[3], cbxD);
+                    cross(Db, &Tt[6], DbxP);
+                    for (int k = 0; k < 3; ++k) dL[k] = (Tt[9 + k] - cbxD[k]) * c.inv_h + Tt[12 + k] - DbxP[k];
+                    I6[0] = Tt[15] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
+                    I6[1] = Tt[16] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
+                    I6[2] = Tt[17] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
+                    I6[3] = Tt[18] + Mb * cab[0] * cab[1];
+                    I6[4] = Tt[19] + Mb * cab[0] * cab[2];
+                    I6[5] = Tt[20] + Mb * cab[1] * cab[2];
+                    const float scale = fmaxf(I6[0] + I6[1] + I6[2], Mb * c.two_r * c.two_r);
+                    solve_inertia(I6, dL, scale, wb);
+                }
+                for (int k = 0; k < 3; ++k) {
+                    br[kBDv + k] = dvb[k];
+                    br[kBW + k] = wb[k];
+                    br[kBCa + k] = cab[k];
+                }
+            }
+            __syncthreads();
+            // particle update: X_{i+1}, V_{i+1}
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                if (!act[r]) continue;
+                const int i = (r * W + wave) * 64 + lane;
+                const size_t g = (size_t)p0 + i;
+                const float* br = bod + bdy[r] * kPoolBodyFloats;
+                float rr[3], Dd[3], ra[3], wr[3], w3[3];
+                goal_offsets(true, br, x0[r], del[r], q[r], rr, Dd);
+                for (int k = 0; k < 3; ++k) {
+                    ra[k] = rr[k] + Cd[r][k] + Dd[k] - br[kBCa + k];
+                    w3[k] = br[kBW + k];
+                }
+                cross(w3, ra, wr);
+                for (int k = 0; k < 3; ++k) {
+                    const float step = Cd[r][k] + Dd[k];
+                    const float dvi = br[kBDv + k] - wr[k];
+                    const float dnew = (del[r][k] + step) + c.h * dvi;
+                    if (c.flags & kFlagStdVelocity) {
+                        const float xw = x0[r][k] + dnew;
+                        V[r][k] = (xw - x0[r][k]) * c.inv_h;
+                    } else {
+                        V[r][k] = (V[r][k] + step * c.inv_h) + dvi;
+                    }
+                    del[r][k] = dnew;
+                    d.dl[k * P + g] = dnew;
+                }
+            }
+            __syncthreads();   // X_{i+1} visible to neighbours before the next iteration
+        }
+        // ---- end of substep: X_K, V_K become the state ---------------------------
+        bool finite = true;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!act[r]) continue;
+            for (int k = 0; k < 3; ++k) {
+                x0[r][k] = x0[r][k] + del[r][k];
+                finite = finite && isfinite(x0[r][k]) && isfinite(V[r][k]);
+            }
+        }
+        if (!finite) atomicOr(&misc[16], kErrNonFinite);
+    }
+    // state out
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        if (!act[r]) continue;
+        const size_t g = (size_t)p0 + (r * W + wave) * 64 + lane;
+        for (int k = 0; k < 3; ++k) {
+            d.x[k * P + g] = x0[r][k];
+            d.v[k * P + g] = V[r][k];
+        }
+    }
+    if (tid == 0) {
+        PoolStat& st = d.stats[slot];
+        if (misc[16]) st.err |= misc[16];
+        if (misc[17] > st.max_nbr) st.max_nbr = misc[17];
+    }
+}
+
+}  // namespace
+
+size_t pool_lds_bytes(int cls)
+{
+    const size_t bound = (size_t)pool_class_bound(cls);
+    const size_t Tc = (size_t)1 << pool_class_key_bits(cls);
+    return 4 * ((Tc + 1 + 3) & ~(size_t)3) + 4 * bound + 4 * (kPoolMaxBodies + bound / 64) * kSums +
+           4 * kPoolMaxBodies * kPoolBodyFloats + 4 * 32;
+}
+
+hipError_t pool_prepare(size_t max_lds)
+{
+    hipError_t e = hipSuccess;
+#define PBDR_POOL_ATTR(S_, LB_)                                                                              \
+    if (e == hipSuccess)                                                                                     \
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_pool<S_, LB_>),                             \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+#define PBDR_POOL_ATTRS(S_) PBDR_POOL_ATTR(S_, 256) PBDR_POOL_ATTR(S_, 512) PBDR_POOL_ATTR(S_, 1024)
+    PBDR_POOL_ATTRS(1)
+    PBDR_POOL_ATTRS(2)
+    PBDR_POOL_ATTRS(3)
+    PBDR_POOL_ATTRS(4)
+    PBDR_POOL_ATTRS(5)
+    PBDR_POOL_ATTRS(6)
+    PBDR_POOL_ATTRS(8)
+#undef PBDR_POOL_ATTRS
+#undef PBDR_POOL_ATTR
+    return e;
+}
+
+hipError_t enqueue_pool_class(const PoolDev& d, const PoolConsts& c, int cls, int waves, int slots, int first,
+                              int count, int subs_per_unit, hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    const int kb = pool_class_key_bits(cls), bound = pool_class_bound(cls);
+    const size_t lds = pool_lds_bytes(cls);
+    const dim3 grid((unsigned)count), block((unsigned)(64 * waves));
+    const int lb = waves <= 4 ? 256 : (waves <= 8 ? 512 : 1024);
+#define PBDR_POOL_CASE(S_, LB_)                                                                                  \
+    if (slots == S_ && lb == LB_) {                                                                              \
+        hipLaunchKernelGGL((k_pool<S_, LB_>), grid, block, lds, stream, d, c, first, subs_per_unit, kb, bound); \
+        return hipGetLastError();                                                                                \
+    }
+#define PBDR_POOL_SLOTS(S_) PBDR_POOL_CASE(S_, 256) PBDR_POOL_CASE(S_, 512) PBDR_POOL_CASE(S_, 1024)
+    PBDR_POOL_SLOTS(1)
+    PBDR_POOL_SLOTS(2)
+    PBDR_POOL_SLOTS(3)
+    PBDR_POOL_SLOTS(4)
+    PBDR_POOL_SLOTS(5)
+    PBDR_POOL_SLOTS(6)
+    PBDR_POOL_SLOTS(8)
+#undef PBDR_POOL_SLOTS
+#undef PBDR_POOL_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace pbdr

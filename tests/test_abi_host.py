@@ -37,9 +37,10 @@ def test_header_compiles_as_c_and_struct_layout_matches_binding(tmp_path):
 #include <stddef.h>
 #include "pbdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pbdr_params), offsetof(pbdr_params, planes),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pbdr_params), offsetof(pbdr_params, planes),
          offsetof(pbdr_params, flags), sizeof(pbdr_scene_desc), sizeof(pbdr_scene_info),
-         offsetof(pbdr_scene_info, workspace_bytes));
+         offsetof(pbdr_scene_info, workspace_bytes), sizeof(pbdr_pool_scene_desc),
+         offsetof(pbdr_pool_scene_desc, gravity), sizeof(pbdr_pool_info), offsetof(pbdr_pool_info, workspace_bytes));
   return 0;
 }
 ''')
@@ -49,7 +50,8 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     got = [int(t) for t in out]
     want = [ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
-            ctypes.sizeof(B.SceneInfo), B.SceneInfo.workspace_bytes.offset]
+            ctypes.sizeof(B.SceneInfo), B.SceneInfo.workspace_bytes.offset, ctypes.sizeof(B.PoolSceneDesc),
+            B.PoolSceneDesc.gravity.offset, ctypes.sizeof(B.PoolInfo), B.PoolInfo.workspace_bytes.offset]
     assert got == want
 
 
@@ -121,8 +123,34 @@ def test_create_rejects_bad_scenes_before_any_device_call():
     assert st == B.ERR_INVALID_ARG and "max 1024" in B.last_error()
 
 
+def test_pool_bytes_and_create_validation_before_device_work():
+    sc, p = _params()
+    lib = B.load_library()
+    nbytes = B.pool_bytes(p, 16, 10000, 200)
+    assert nbytes > 0 and nbytes % 256 == 0
+    assert B.pool_bytes(p, 32, 10000, 200) > nbytes
+    for bad in [(0, 100, 10), (4, 0, 10), (4, 100, 0)]:
+        assert B.pool_bytes(p, *bad) == 0
+    h = ctypes.c_void_p()
+    assert lib.pbdr_pool_create(ctypes.byref(p), 4, 100, 10, None, 1 << 20, None, ctypes.byref(h)) == B.ERR_WORKSPACE
+    assert lib.pbdr_pool_create(ctypes.byref(p), 4, 100, 10, ctypes.c_void_p(0x1001), 1 << 20, None,
+                                ctypes.byref(h)) == B.ERR_WORKSPACE
+    assert lib.pbdr_pool_create(ctypes.byref(p), 4, 100, 10, ctypes.c_void_p(0x1000), 16, None,
+                                ctypes.byref(h)) == B.ERR_WORKSPACE
+    bad = B.make_params(sc.dt_frame, 0, sc.iterations, sc.radius)
+    assert lib.pbdr_pool_create(ctypes.byref(bad), 4, 100, 10, ctypes.c_void_p(0x1000), 1 << 30, None,
+                                ctypes.byref(h)) == B.ERR_INVALID_ARG
+    assert not h.value
+
+
 def test_null_handles_are_rejected():
     lib = B.load_library()
+    assert lib.pbdr_pool_step(None, 1) == B.ERR_INVALID_ARG
+    assert lib.pbdr_pool_substep(None, 1) == B.ERR_INVALID_ARG
+    assert lib.pbdr_pool_remove(None, 0) == B.ERR_INVALID_ARG
+    assert lib.pbdr_pool_read_state(None, 0, None, None, 0) == B.ERR_INVALID_ARG
+    assert lib.pbdr_pool_autotune(None, 1, 1, None) == B.ERR_INVALID_ARG
+    lib.pbdr_pool_destroy(None)
     assert lib.pbdr_scene_step(None, 1) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_substep(None, 1) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_read_state(None, None, None, 0) == B.ERR_INVALID_ARG
@@ -138,3 +166,5 @@ def test_solver_refuses_to_run_without_gpu_or_library(monkeypatch):
     sc = scenes.drop_cubes(0)
     with pytest.raises(RuntimeError):
         B.Solver.from_scene(sc)
+    with pytest.raises(RuntimeError):
+        B.Pool(B.params_for(sc), 4, 1000, 10)
