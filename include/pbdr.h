@@ -224,7 +224,8 @@ void pbdr_scene_destroy(pbdr_scene* scene);
  * Scene pools: many independent small scenes stepped together.
  *
  * A pool holds up to max_scenes scenes of at most PBDR_POOL_MAX_PARTICLES
- * particles and PBDR_POOL_MAX_BODIES bodies each, in arenas of max_particles
+ * particles, PBDR_POOL_MAX_BODIES bodies and 128 slots of 64 lanes (see
+ * pbdr_pool_set_tuning) each, in arenas of max_particles
  * particles and max_bodies bodies, all inside one device workspace owned by
  * the caller (pbdr_pool_bytes).  Each scene is one workgroup that runs every
  * substep of a step call on its own (Alg. 1 as for a single scene), so a
@@ -308,9 +309,11 @@ pbdr_status pbdr_pool_read_debug(pbdr_pool* pool, int32_t slot, int32_t what, vo
 pbdr_status pbdr_pool_check(pbdr_pool* pool, int32_t slot, int32_t* max_neighbours);
 
 /* Launch shape of each size class ([PBDR_POOL_CLASSES] arrays): waves per
- * workgroup, 1, 2, 4, 8 or 16.  Each launch then gives every lane the fewest
- * particle slots (1-6 or 8) that cover the class's largest stepped scene;
- * a class whose scenes need more than 8 slots at the set width is widened. */
+ * workgroup, 1, 2, 4, 8 or 16.  Bodies are laid out wave-aligned: body b
+ * fills ceil(n_b / 64) slots of 64 lanes, and a pooled scene may fill at most
+ * 128 slots.  Each launch gives every lane the fewest register sets (1-6 or 8)
+ * that cover the class's largest stepped scene; a class whose scenes need more
+ * than 8 sets at the set width is widened for that launch. */
 pbdr_status pbdr_pool_get_tuning(const pbdr_pool* pool, int32_t* waves);
 pbdr_status pbdr_pool_set_tuning(pbdr_pool* pool, const int32_t* waves);
 

@@ -114,6 +114,7 @@ private:
 struct SlotInfo {
     bool used = false;
     int32_t p0 = 0, n = 0, b0 = 0, nb = 0, cls = 0;
+    int32_t lanes_slots = 0;        // 64-lane slots of the wave-aligned bodies
     float g[3] = {0.0f, 0.0f, 0.0f};
     float mu = 0.0f;
     std::vector<char> staging;    // host copy of the upload, kept until the slot is freed
@@ -127,13 +128,20 @@ int class_of(int32_t n)
     return c;
 }
 
-// Fewest supported particle slots per lane covering n particles with `waves` waves.
-int slots_for(int32_t n, int waves)
+// Fewest supported register sets per lane covering `slots` 64-lane slots with `waves` waves.
+int sets_for(int32_t slots, int waves)
 {
-    int s = (int)((n + 64 * waves - 1) / (64 * waves));
+    int s = (int)((slots + waves - 1) / waves);
     if (s < 1) s = 1;
     while (s <= 8 && !pbdr::pool_slots_supported(s)) ++s;
     return s;
+}
+
+// The set width, widened until at most 8 register sets cover the slots.
+int width_for(int32_t slots, int waves)
+{
+    while (waves < 16 && sets_for(slots, waves) > 8) waves *= 2;
+    return waves;
 }
 
 bool valid_waves(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 16; }
@@ -202,7 +210,7 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
     pbdr::PoolScene* hs = p->h_scenes[b];
     int32_t* ho = p->h_order[b];
     std::vector<int32_t> by_class[kClasses];
-    int32_t nmax[kClasses] = {0};
+    int32_t nmax[kClasses] = {0};   // largest slot count per class
     for (int32_t j = 0; j < p->S; ++j) {
         const SlotInfo& si = p->slots[(size_t)j];
         pbdr::PoolScene& r = hs[j];
@@ -217,7 +225,7 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
         r.mu = si.mu;
         if (r.units > 0 && (only_class < 0 || si.cls == only_class)) {
             by_class[si.cls].push_back(j);
-            nmax[si.cls] = std::max(nmax[si.cls], si.n);
+            nmax[si.cls] = std::max(nmax[si.cls], si.lanes_slots);
         } else {
             r.units = 0;
         }
@@ -243,8 +251,8 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
     if (active == 1) {          // one class: launch on the pool's stream
         for (int c = 0; c < kClasses; ++c) {
             if (!count[c]) continue;
-            const int w = p->waves[c];
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, slots_for(nmax[c], w), first[c], count[c],
+            const int w = width_for(nmax[c], p->waves[c]);
+            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, sets_for(nmax[c], w), first[c], count[c],
                                                     subs_per_unit, p->stream);
             if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
         }
@@ -253,8 +261,8 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
         for (int c = 0; c < kClasses; ++c) {
             if (!count[c]) continue;
             HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork, 0));
-            const int w = p->waves[c];
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, slots_for(nmax[c], w), first[c], count[c],
+            const int w = width_for(nmax[c], p->waves[c]);
+            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, sets_for(nmax[c], w), first[c], count[c],
                                                     subs_per_unit, p->aux[c]);
             if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
             HIP_TRY(hipEventRecord(p->join[c], p->aux[c]));
@@ -346,7 +354,7 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     for (int32_t j = max_scenes - 1; j >= 0; --j) p->free_slots.push_back(j);
     p->parts.init(max_particles);
     p->bodies.init(max_bodies);
-    for (int c = 0; c < kClasses; ++c) p->waves[c] = std::min(16, std::max(1, pbdr::pool_class_bound(c) / 64));
+    for (int c = 0; c < kClasses; ++c) p->waves[c] = std::min(16, std::max(1, pbdr::pool_class_bound(c) / 64));   // one set
 
     pbdr::PoolConsts& c = p->consts;
     std::memset(&c, 0, sizeof(c));
@@ -355,6 +363,8 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     c.radius = (float)r.p.radius;
     c.two_r = (float)(2.0 * r.p.radius);
     c.search_r2 = (float)(r.rs * r.rs);
+    c.search_r = (float)r.rs;
+    c.box_margin = (float)(2.0 * r.rs);
     c.inv_cell = (float)(1.0 / r.a);
     for (int k = 0; k < 3; ++k) c.origin[k] = (float)r.p.grid_origin[k];
     c.nbr_cap = r.cap;
@@ -423,9 +433,15 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
         return fail(PBDR_ERR_INVALID_ARG, "desc arrays must not be NULL");
     if (desc->body_start[0] != 0 || desc->body_start[nb] != n)
         return fail(PBDR_ERR_INVALID_ARG, "body_start must begin at 0 and end at n_particles");
-    for (int32_t b = 0; b < nb; ++b)
-        if (desc->body_start[b + 1] - desc->body_start[b] < 1)
-            return fail(PBDR_ERR_INVALID_ARG, "body %d is empty or body_start decreases", b);
+    int32_t lanes_slots = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        const int32_t len = desc->body_start[b + 1] - desc->body_start[b];
+        if (len < 1) return fail(PBDR_ERR_INVALID_ARG, "body %d is empty or body_start decreases", b);
+        lanes_slots += (len + 63) / 64;
+    }
+    if (lanes_slots > pbdr::kPoolMaxSlots)
+        return fail(PBDR_ERR_INVALID_ARG, "a pooled scene's bodies may fill at most %d slots of 64 lanes (one body per "
+                    "slot), this one needs %d", pbdr::kPoolMaxSlots, lanes_slots);
     for (int32_t i = 0; i < n; ++i)
         if (!(std::isfinite(desc->mass[i]) && desc->mass[i] > 0.0f))
             return fail(PBDR_ERR_INVALID_ARG, "mass[%d] must be finite and > 0", i);
@@ -452,6 +468,7 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
     si.b0 = b0;
     si.nb = nb;
     si.cls = class_of(n);
+    si.lanes_slots = lanes_slots;
     for (int k = 0; k < 3; ++k) si.g[k] = (float)desc->gravity[k];
     si.mu = (float)desc->friction_mu;
 
@@ -631,11 +648,8 @@ pbdr_status pbdr_pool_get_tuning(const pbdr_pool* p, int32_t* waves)
 pbdr_status pbdr_pool_set_tuning(pbdr_pool* p, const int32_t* waves)
 {
     if (!p || !waves) return fail(PBDR_ERR_INVALID_ARG, "pool and waves must not be NULL");
-    for (int c = 0; c < kClasses; ++c) {
+    for (int c = 0; c < kClasses; ++c)
         if (!valid_waves(waves[c])) return fail(PBDR_ERR_INVALID_ARG, "waves[%d] = %d is not 1, 2, 4, 8 or 16", c, waves[c]);
-        if (slots_for(pbdr::pool_class_bound(c), waves[c]) > 8 && c <= p->max_cls)
-            return fail(PBDR_ERR_INVALID_ARG, "waves[%d] = %d is too narrow for the class's scenes", c, waves[c]);
-    }
     for (int c = 0; c < kClasses; ++c) p->waves[c] = waves[c];
     return PBDR_OK;
 }
@@ -665,13 +679,13 @@ pbdr_status pbdr_pool_autotune(pbdr_pool* p, int32_t n_frames, int32_t repeats, 
     for (int c = 0; c < kClasses && st == PBDR_OK; ++c) {
         int32_t nmax = 0;
         for (const SlotInfo& si : p->slots)
-            if (si.used && si.cls == c) nmax = std::max(nmax, si.n);
+            if (si.used && si.cls == c) nmax = std::max(nmax, si.lanes_slots);
         if (ms_out) ms_out[c] = 0.0;
         if (nmax == 0) continue;
         double best = 1e300;
         int best_w = p->waves[c];
         for (int w = 1; w <= 16 && st == PBDR_OK; w *= 2) {
-            if (slots_for(nmax, w) > 8) continue;
+            if (sets_for(nmax, w) > 8) continue;
             const int saved = p->waves[c];
             p->waves[c] = w;
             double t_best = 1e300;

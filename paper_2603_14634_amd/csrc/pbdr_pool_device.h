@@ -12,7 +12,8 @@ constexpr int kPoolClasses = 7;            // size classes: n <= 128 << c
 constexpr int kPoolMaxParticles = 8192;    // 128 << (kPoolClasses - 1)
 constexpr int kPoolMaxBodies = 64;         // bodies per pooled scene
 constexpr int kPoolMaxWaves = 16;          // waves per workgroup
-constexpr int kPoolBodyFloats = 40;        // per-body LDS record
+constexpr int kPoolBodyFloats = 48;        // per-body LDS record
+constexpr int kPoolMaxSlots = 128;         // 64-lane slots per scene (bodies wave-aligned) = 16 waves x 8
 
 inline int pool_class_bound(int cls) { return 128 << cls; }
 // key bits of a class's workgroup-local hash table (about one key per particle)
@@ -59,6 +60,8 @@ struct PoolConsts {
     float h, inv_h;
     float radius, two_r;
     float search_r2;           // fl32(R_s^2)
+    float search_r;            // R_s
+    float box_margin;          // 2 R_s: growth of the body boxes in the broad phase
     float inv_cell;            // fl32(1 / a)
     float origin[3];
     int32_t nbr_cap;
@@ -80,9 +83,9 @@ inline bool pool_slots_supported(int s) { return (s >= 1 && s <= 6) || s == 8; }
 
 // Launches the pool kernel over `count` scenes of class `cls` listed at
 // order[first ..]: each scene advances units * subs_per_unit substeps.
-// `waves` (1, 2, 4, 8 or 16) and `slots` (particle slots per lane, see
-// pool_slots_supported) must satisfy 64 * waves * slots >= the largest n of
-// the listed scenes.
+// `waves` (1, 2, 4, 8 or 16) and `slots` (register sets per lane, see
+// pool_slots_supported) must satisfy waves * slots >= the largest slot count
+// (sum over bodies of ceil(n_b / 64)) of the listed scenes.
 hipError_t enqueue_pool_class(const PoolDev& d, const PoolConsts& c, int cls, int waves, int slots, int first,
                               int count, int subs_per_unit, hipStream_t stream);
 

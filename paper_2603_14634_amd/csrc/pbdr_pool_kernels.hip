@@ -15,12 +15,13 @@
 //   neighbours   27-cell walk, same-body candidates skipped from LDS before any
 //                position is loaded, FP32 predicate, ascending lists
 //   iterate x K  contacts, shape matching and momentum constraint; per-body
-//                sums are deterministic segmented wave scans (DPP) over
-//                64-particle slots, combined in slot order by one lane per body
+//                sums are fixed-order wave reductions (DPP) over the body's
+//                64-lane slots, combined in slot order by one lane per body
 //
-// Particle i of a scene sits in slot i / 64, lane i % 64; slot s is handled by
-// wave s % W in register set s / W.  Every sum and every list is independent of
-// W, of the register sets per lane and of the hash-table size, so a scene's
+// Bodies are wave-aligned: body b owns ceil(n_b / 64) consecutive slots of 64
+// lanes, one particle per lane, so a slot never mixes bodies.  Slot s is handled
+// by wave s % W in register set s / W.  Every sum and every list is independent
+// of W, of the register sets per lane and of the hash-table size, so a scene's
 // result does not depend on the launch shape the tuner picks or on the other
 // scenes of the pool.
 #include "pbdr_math.h"
@@ -31,31 +32,36 @@ namespace {
 
 using namespace dev;
 
-constexpr int kSums = 24;             // per-segment partial sums (12 shape matching, 21 momentum)
+constexpr int kSums = 24;             // per-slot partial sums (12 shape matching, 21 momentum)
 
-// DPP move of v within the wave (0 where the pattern has no source lane).
+// Fixed-pattern DPP move; lanes the pattern does not feed keep v.
 template <int CTRL, int ROWS>
-__device__ inline float dpp_mov(float v)
+__device__ inline float dpp_keep(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xf, true));
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, v), __builtin_bit_cast(int, v),
+                                                                 CTRL, ROWS, 0xf, false));
 }
 
-// Inclusive segmented sum over the wave, in a fixed order: lane l ends with the
-// sum of lanes lo..l, where lo <= l is the first lane of l's segment (segments
-// are runs of consecutive lanes).  Row-local Hillis-Steele steps (row_shr),
-// then the row carries (row_bcast 15 and 31), each taken only if the source
-// lane lies in the same segment.
-__device__ inline float seg_sum(float v, int lane, int lo)
+// Minimum and maximum over the 64 lanes (valid in lane 63), same tree as the sums.
+__device__ inline float wave_min_to_63(float v)
 {
-    const int row0 = lane & ~15;
-    const int lo_row = lo > row0 ? lo : row0;
-    float y;
-    y = dpp_mov<0x111, 0xf>(v); v += (lane - 1 >= lo_row) ? y : 0.0f;
-    y = dpp_mov<0x112, 0xf>(v); v += (lane - 2 >= lo_row) ? y : 0.0f;
-    y = dpp_mov<0x114, 0xf>(v); v += (lane - 4 >= lo_row) ? y : 0.0f;
-    y = dpp_mov<0x118, 0xf>(v); v += (lane - 8 >= lo_row) ? y : 0.0f;
-    y = dpp_mov<0x142, 0xa>(v); v += ((lane & 16) && row0 - 1 >= lo) ? y : 0.0f;   // rows 1, 3 from 15, 47
-    y = dpp_mov<0x143, 0xc>(v); v += (lane >= 32 && 31 >= lo) ? y : 0.0f;          // rows 2, 3 from 31
+    v = fminf(v, dpp_keep<0xb1, 0xf>(v));
+    v = fminf(v, dpp_keep<0x4e, 0xf>(v));
+    v = fminf(v, dpp_keep<0x141, 0xf>(v));
+    v = fminf(v, dpp_keep<0x140, 0xf>(v));
+    v = fminf(v, dpp_keep<0x142, 0xa>(v));
+    v = fminf(v, dpp_keep<0x143, 0xc>(v));
+    return v;
+}
+
+__device__ inline float wave_max_to_63(float v)
+{
+    v = fmaxf(v, dpp_keep<0xb1, 0xf>(v));
+    v = fmaxf(v, dpp_keep<0x4e, 0xf>(v));
+    v = fmaxf(v, dpp_keep<0x141, 0xf>(v));
+    v = fmaxf(v, dpp_keep<0x140, 0xf>(v));
+    v = fmaxf(v, dpp_keep<0x142, 0xa>(v));
+    v = fmaxf(v, dpp_keep<0x143, 0xc>(v));
     return v;
 }
 
@@ -93,7 +99,11 @@ enum : int {
     kBCa = 25,        // c_asm - c_i (3)
     kBRprev = 28,     // previous iteration's rotation (9)
     kBFirst = 37,     // first particle (int bits)
-    kBEnd = 38,       // one past the last particle (int bits)
+    kBSlot0 = 38,     // first slot (int bits)
+    kBSlots = 39,     // slot count (int bits)
+    kBLo = 40,        // box of the predicted positions: lower corner (3)
+    kBHi = 43,        // upper corner (3)
+    kBFar = 46,       // 1: coordinates too large for the box test (int bits)
 };
 
 // Offsets of a particle in the frame centred on the body's current centre:
@@ -110,13 +120,17 @@ template <int S, int LB>
 __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first, int subs_per_unit,
                                                               int kb, int bound)
 {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ float4 lds4[];
+    uint32_t* lds = (uint32_t*)lds4;
     const uint32_t Tc = 1u << kb;
     uint32_t* tab = lds;                                          // [Tc + 1] key counts -> first slots
     uint32_t* sid = tab + ((Tc + 1 + 3) & ~3u);                   // [bound] id | body << 16, key-grouped
-    float* part = (float*)(sid + bound);                          // [(64 + bound / 64) * kSums]
-    float* bod = part + (kPoolMaxBodies + bound / 64) * kSums;    // [64 * kPoolBodyFloats]
-    uint32_t* misc = (uint32_t*)(bod + kPoolMaxBodies * kPoolBodyFloats);   // wave totals [16], flags
+    float* part = (float*)(sid + bound);                          // [kPoolMaxSlots * kSums]
+    float* bod = part + kPoolMaxSlots * kSums;                    // [64 * kPoolBodyFloats]
+    int2* slot_tab = (int2*)(bod + kPoolMaxBodies * kPoolBodyFloats);   // [kPoolMaxSlots] (body, first particle)
+    uint8_t* ovl = (uint8_t*)(slot_tab + kPoolMaxSlots);          // [64][64] bodies whose boxes come near
+    uint32_t* ovl_n = (uint32_t*)(ovl + kPoolMaxBodies * kPoolMaxBodies);   // [64]
+    uint32_t* misc = ovl_n + kPoolMaxBodies;                      // wave totals [16], flags
 
     const int slot = d.order[first + blockIdx.x];
     const PoolScene& sc = d.scenes[slot];
@@ -132,32 +146,52 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
     const int cap = c.nbr_cap;
     uint32_t* lists = d.nbr + (size_t)cap * p0;
 
-    // body records
+    // body records and the slot table (bodies wave-aligned, in order)
     for (int b = tid; b < nb; b += T) {
         float* r = bod + b * kPoolBodyFloats;
         r[kBM] = d.body_mass[b0 + b];
         for (int k = 0; k < 3; ++k) r[kBMq + k] = d.body_mq[3 * (size_t)(b0 + b) + k];
-        const int f = d.body_first[b0 + b];
-        const int e = b + 1 < nb ? d.body_first[b0 + b + 1] : n;
-        r[kBFirst] = __int_as_float(f);
-        r[kBEnd] = __int_as_float(e);
+        r[kBFirst] = __int_as_float(d.body_first[b0 + b]);
     }
     if (tid == 0) {
         misc[16] = 0u;   // error bits
         misc[17] = 0u;   // largest list
+        int s0 = 0;
+        for (int b = 0; b < nb; ++b) {
+            const int f = d.body_first[b0 + b];
+            const int e = b + 1 < nb ? d.body_first[b0 + b + 1] : n;
+            const int ns = (e - f + 63) >> 6;
+            float* r = bod + b * kPoolBodyFloats;
+            r[kBSlot0] = __int_as_float(s0);
+            r[kBSlots] = __int_as_float(ns);
+            for (int j = 0; j < ns && s0 + j < kPoolMaxSlots; ++j)
+                slot_tab[s0 + j] = make_int2(b | ((e - f - 64 * j < 64 ? e - f - 64 * j : 64) << 16), f + 64 * j);
+            s0 += ns;
+        }
+        misc[18] = (uint32_t)s0;   // slots in use
+    }
+    __syncthreads();
+    const int n_slots = (int)misc[18];
+    if (n_slots > W * S || n_slots > kPoolMaxSlots) {   // launch shape too small: never expected
+        if (tid == 0) atomicOr(&d.stats[slot].err, kErrInternal);
+        return;
     }
 
-    // per-lane particles: register set r holds particle ((r * W + wave) * 64 + lane)
+    // per-lane particles: register set r holds lane `lane` of slot r * W + wave
     float x0[S][3], V[S][3], del[S][3], q[S][3], m[S], Cd[S][3];
-    int bdy[S], lo[S];
+    int bdy[S], pid[S];
     uint32_t nn[S];
-    bool act[S];
+    bool act[S], live[S];
 #pragma unroll
     for (int r = 0; r < S; ++r) {
-        const int i = (r * W + wave) * 64 + lane;
-        act[r] = i < n;
+        const int sl = r * W + wave;
+        live[r] = sl < n_slots;                                   // uniform over the wave
+        const int2 st = live[r] ? slot_tab[sl] : make_int2(0, 0);
+        const int i = st.y + lane;
+        act[r] = live[r] && lane < (st.x >> 16);
+        pid[r] = act[r] ? i : 0;
         m[r] = 0.0f;
-        bdy[r] = 0;
+        bdy[r] = st.x & 0xffff;
         nn[r] = 0u;
         for (int k = 0; k < 3; ++k) x0[r][k] = V[r][k] = del[r][k] = q[r][k] = Cd[r][k] = 0.0f;
         if (act[r]) {
@@ -168,21 +202,14 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
                 q[r][k] = d.q[k * P + g];
             }
             m[r] = d.mass[g];
-            bdy[r] = d.pbody[g];
         }
-    }
-    __syncthreads();   // body records
-#pragma unroll
-    for (int r = 0; r < S; ++r) {
-        const int s = r * W + wave;
-        const int f = __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBFirst]);
-        lo[r] = act[r] ? (f > s * 64 ? f - s * 64 : 0) : lane;    // first lane of this particle's segment
     }
 
     for (int sub = 0; sub < total_subs; ++sub) {
         const bool last_sub = sub + 1 == total_subs;
         // ---- predict + key counts -------------------------------------------
         for (uint32_t k = tid; k <= Tc; k += T) tab[k] = 0u;
+        if (tid < kPoolMaxBodies) ovl_n[tid] = 0u;
         __syncthreads();
         uint32_t key[S], rank[S];
         float xt[S][3];
@@ -191,7 +218,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
             key[r] = 0u;
             rank[r] = 0u;
             if (!act[r]) continue;
-            const int i = (r * W + wave) * 64 + lane;
+            const int i = pid[r];
             const size_t g = (size_t)p0 + i;
             const float gg[3] = {gx, gy, gz};
             {
@@ -213,10 +240,41 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
             key[r] = morton(cell_axis(xt[r][0], c.origin[0], c.inv_cell), cell_axis(xt[r][1], c.origin[1], c.inv_cell),
                             cell_axis(xt[r][2], c.origin[2], c.inv_cell), mask);
             rank[r] = atomicAdd(&tab[key[r]], 1u);
-            if (i == __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBFirst]))   // body anchor: X_init of its first particle
+            if (i == __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBFirst]))   // anchor: X_init of the body's first particle
                 for (int k = 0; k < 3; ++k) bod[bdy[r] * kPoolBodyFloats + kBAnchor + k] = x0[r][k];
         }
+        // box of each slot's predicted positions (broad phase of the neighbour search)
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (!live[r]) continue;                                       // uniform over the wave
+            float bx[6];
+            for (int k = 0; k < 3; ++k) {
+                bx[k] = wave_min_to_63(act[r] ? xt[r][k] : INFINITY);
+                bx[3 + k] = wave_max_to_63(act[r] ? xt[r][k] : -INFINITY);
+            }
+            if (lane == 63)
+                for (int k = 0; k < 6; ++k) part[(r * W + wave) * kSums + k] = bx[k];
+        }
         __syncthreads();
+        // body boxes; bodies far from the origin skip the box test
+        for (int b = tid; b < nb; b += T) {
+            float* br = bod + b * kPoolBodyFloats;
+            const int s0 = __float_as_int(br[kBSlot0]), ns = __float_as_int(br[kBSlots]);
+            float bx[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+            for (int sl = s0; sl < s0 + ns; ++sl)
+                for (int k = 0; k < 3; ++k) {
+                    bx[k] = fminf(bx[k], part[sl * kSums + k]);
+                    bx[3 + k] = fmaxf(bx[3 + k], part[sl * kSums + 3 + k]);
+                }
+            const float lim = 1048576.0f * c.search_r;
+            bool far = false;
+            for (int k = 0; k < 3; ++k) {
+                br[kBLo + k] = bx[k];
+                br[kBHi + k] = bx[3 + k];
+                far = far || !(fabsf(bx[k]) < lim) || !(fabsf(bx[3 + k]) < lim);
+            }
+            br[kBFar] = __int_as_float(far ? 1 : 0);
+        }
         // ---- scan of the key counts ------------------------------------------
         {
             const uint32_t per = Tc > (uint32_t)T ? Tc / (uint32_t)T : 1u;
@@ -239,10 +297,24 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
 #pragma unroll
         for (int r = 0; r < S; ++r) {
             if (!act[r]) continue;
-            const int i = (r * W + wave) * 64 + lane;
+            const int i = pid[r];
             const uint32_t at = tab[key[r]] + rank[r];
             sid[at] = (uint32_t)i | ((uint32_t)bdy[r] << 16);
             d.sxt4[(size_t)p0 + at] = make_float4(xt[r][0], xt[r][1], xt[r][2], 0.0f);
+        }
+        // body pairs whose boxes, grown by 2 R_s, overlap
+        for (int t = tid; t < nb * nb; t += T) {
+            const int a = t / nb, b = t - a * nb;
+            if (a == b) continue;
+            const float* ba = bod + a * kPoolBodyFloats;
+            const float* bb = bod + b * kPoolBodyFloats;
+            bool near = __float_as_int(ba[kBFar]) || __float_as_int(bb[kBFar]);
+            if (!near) {
+                near = true;
+                for (int k = 0; k < 3; ++k)
+                    near = near && ba[kBLo + k] - c.box_margin <= bb[kBHi + k] && bb[kBLo + k] - c.box_margin <= ba[kBHi + k];
+            }
+            if (near) ovl[a * kPoolMaxBodies + atomicAdd(&ovl_n[a], 1u)] = (uint8_t)b;
         }
         __syncthreads();
         // ---- neighbour lists ---------------------------------------------------
@@ -250,12 +322,26 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
 #pragma unroll
         for (int r = 0; r < S; ++r) {
             if (!act[r]) continue;
-            const int i = (r * W + wave) * 64 + lane;
+            const int i = pid[r];
             const uint32_t cx = cell_axis(xt[r][0], c.origin[0], c.inv_cell);
             const uint32_t cy = cell_axis(xt[r][1], c.origin[1], c.inv_cell);
             const uint32_t cz = cell_axis(xt[r][2], c.origin[2], c.inv_cell);
             uint32_t cnt = 0;
-            for (int t = 0; t < 27; ++t) {
+            // a particle farther than 2 R_s (per axis) from every other body's box
+            // has no neighbours: every FP32 predicate with those bodies is false
+            bool near = false;
+            const uint32_t no = ovl_n[bdy[r]];
+            for (uint32_t j = 0; j < no && !near; ++j) {
+                const float* bo = bod + ovl[bdy[r] * kPoolMaxBodies + j] * kPoolBodyFloats;
+                bool in = __float_as_int(bo[kBFar]) != 0;
+                if (!in) {
+                    in = true;
+                    for (int k = 0; k < 3; ++k)
+                        in = in && xt[r][k] >= bo[kBLo + k] - c.box_margin && xt[r][k] <= bo[kBHi + k] + c.box_margin;
+                }
+                near = in;
+            }
+            for (int t = 0; t < (near ? 27 : 0); ++t) {
                 const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
                                           cz + (uint32_t)(t / 9 - 1), mask);
                 const uint32_t a = tab[k], e = tab[k + 1];
@@ -297,7 +383,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
             for (int r = 0; r < S; ++r) {
                 for (int k = 0; k < 3; ++k) Cd[r][k] = 0.0f;
                 const int s = r * W + wave;
-                const int i = s * 64 + lane;
+                const int i = pid[r];
                 if (act[r]) {
                     for (int pl = 0; pl < c.n_planes; ++pl) {
                         const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
@@ -356,24 +442,23 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
                 for (int k = 0; k < 3; ++k) Sv[k] = m[r] * y[k];
                 for (int a = 0; a < 3; ++a)
                     for (int k2 = 0; k2 < 3; ++k2) Sv[3 + 3 * a + k2] = m[r] * y[a] * q[r][k2];
-                for (int j = 0; j < 12; ++j) Sv[j] = seg_sum(Sv[j], lane, lo[r]);
-                if (act[r]) {
-                    const int bend = __float_as_int(bod[bdy[r] * kPoolBodyFloats + kBEnd]);
-                    if (lane == 63 || i + 1 == bend) {
-                        float* pp = part + (bdy[r] + s) * kSums;
-                        for (int j = 0; j < 12; ++j) pp[j] = Sv[j];
-                    }
+                if (live[r]) {
+                    for (int j = 0; j < 12; ++j) Sv[j] = wave_sum_to_63(Sv[j]);
+                    if (lane == 63)
+                        for (int j = 0; j < 3; ++j)
+                            *(float4*)(part + s * kSums + 4 * j) = make_float4(Sv[4 * j], Sv[4 * j + 1], Sv[4 * j + 2],
+                                                                             Sv[4 * j + 3]);
                 }
             }
             __syncthreads();
             // per body: centre, covariance, rotation
             for (int b = tid; b < nb; b += T) {
                 float* br = bod + b * kPoolBodyFloats;
-                const int f = __float_as_int(br[kBFirst]), e = __float_as_int(br[kBEnd]);
+                const int s0 = __float_as_int(br[kBSlot0]), ns = __float_as_int(br[kBSlots]);
                 float Tt[12];
                 for (int j = 0; j < 12; ++j) Tt[j] = 0.0f;
-                for (int s = f >> 6; s <= (e - 1) >> 6; ++s) {
-                    const float* pp = part + (b + s) * kSums;
+                for (int s = s0; s < s0 + ns; ++s) {
+                    const float* pp = part + s * kSums;
                     for (int j = 0; j < 12; ++j) Tt[j] += pp[j];
                 }
                 const float im = frcp(br[kBM]);
@@ -390,11 +475,10 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
 #pragma unroll
             for (int r = 0; r < S; ++r) {
                 const int s = r * W + wave;
-                const int i = s * 64 + lane;
                 const float* br = bod + bdy[r] * kPoolBodyFloats;
                 float rr[3], Dd[3];
                 goal_offsets(act[r], br, x0[r], del[r], q[r], rr, Dd);
-                float Sv[21], zb[3], za[3], vb[3], t3[3];
+                float Sv[24], zb[3], za[3], vb[3], t3[3];
                 for (int k = 0; k < 3; ++k) {
                     zb[k] = rr[k] + Cd[r][k];
                     za[k] = zb[k] + Dd[k];
@@ -413,24 +497,24 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
                 Sv[18] = -m[r] * za[0] * za[1];
                 Sv[19] = -m[r] * za[0] * za[2];
                 Sv[20] = -m[r] * za[1] * za[2];
-                for (int j = 0; j < 21; ++j) Sv[j] = seg_sum(Sv[j], lane, lo[r]);
-                if (act[r]) {
-                    const int bend = __float_as_int(br[kBEnd]);
-                    if (lane == 63 || i + 1 == bend) {
-                        float* pp = part + (bdy[r] + s) * kSums;
-                        for (int j = 0; j < 21; ++j) pp[j] = Sv[j];
-                    }
+                Sv[21] = Sv[22] = Sv[23] = 0.0f;
+                if (live[r]) {
+                    for (int j = 0; j < 21; ++j) Sv[j] = wave_sum_to_63(Sv[j]);
+                    if (lane == 63)
+                        for (int j = 0; j < 6; ++j)
+                            *(float4*)(part + s * kSums + 4 * j) = make_float4(Sv[4 * j], Sv[4 * j + 1], Sv[4 * j + 2],
+                                                                             Sv[4 * j + 3]);
                 }
             }
             __syncthreads();
             // per body: momentum conservation constraint, Eqs. (4)-(5)
             for (int b = tid; b < nb; b += T) {
                 float* br = bod + b * kPoolBodyFloats;
-                const int f = __float_as_int(br[kBFirst]), e = __float_as_int(br[kBEnd]);
+                const int s0 = __float_as_int(br[kBSlot0]), ns = __float_as_int(br[kBSlots]);
                 float Tt[21];
                 for (int j = 0; j < 21; ++j) Tt[j] = 0.0f;
-                for (int s = f >> 6; s <= (e - 1) >> 6; ++s) {
-                    const float* pp = part + (b + s) * kSums;
+                for (int s = s0; s < s0 + ns; ++s) {
+                    const float* pp = part + s * kSums;
                     for (int j = 0; j < 21; ++j) Tt[j] += pp[j];
                 }
                 const float Mb = br[kBM], im = frcp(Mb);
@@ -467,7 +551,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
 #pragma unroll
             for (int r = 0; r < S; ++r) {
                 if (!act[r]) continue;
-                const int i = (r * W + wave) * 64 + lane;
+                const int i = pid[r];
                 const size_t g = (size_t)p0 + i;
                 const float* br = bod + bdy[r] * kPoolBodyFloats;
                 float rr[3], Dd[3], ra[3], wr[3], w3[3];
@@ -509,7 +593,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
 #pragma unroll
     for (int r = 0; r < S; ++r) {
         if (!act[r]) continue;
-        const size_t g = (size_t)p0 + (r * W + wave) * 64 + lane;
+        const size_t g = (size_t)p0 + pid[r];
         for (int k = 0; k < 3; ++k) {
             d.x[k * P + g] = x0[r][k];
             d.v[k * P + g] = V[r][k];
@@ -528,8 +612,9 @@ size_t pool_lds_bytes(int cls)
 {
     const size_t bound = (size_t)pool_class_bound(cls);
     const size_t Tc = (size_t)1 << pool_class_key_bits(cls);
-    return 4 * ((Tc + 1 + 3) & ~(size_t)3) + 4 * bound + 4 * (kPoolMaxBodies + bound / 64) * kSums +
-           4 * kPoolMaxBodies * kPoolBodyFloats + 4 * 32;
+    return 4 * ((Tc + 1 + 3) & ~(size_t)3) + 4 * bound + 4 * kPoolMaxSlots * kSums +
+           4 * kPoolMaxBodies * kPoolBodyFloats + 8 * kPoolMaxSlots + kPoolMaxBodies * kPoolMaxBodies +
+           4 * kPoolMaxBodies + 4 * 32;
 }
 
 hipError_t pool_prepare(size_t max_lds)
