@@ -224,12 +224,15 @@ void pbdr_scene_destroy(pbdr_scene* scene);
  * Scene pools: many independent small scenes stepped together.
  *
  * A pool holds up to max_scenes scenes of at most PBDR_POOL_MAX_PARTICLES
- * particles, PBDR_POOL_MAX_BODIES bodies and 128 slots of 64 lanes (see
- * pbdr_pool_set_tuning) each, in arenas of max_particles
+ * particles and PBDR_POOL_MAX_BODIES bodies each, in arenas of max_particles
  * particles and max_bodies bodies, all inside one device workspace owned by
  * the caller (pbdr_pool_bytes).  Each scene is one workgroup that runs every
  * substep of a step call on its own (Alg. 1 as for a single scene), so a
- * call is a handful of launches however many scenes are resident.  Scenes
+ * call is a handful of launches however many scenes are resident.  Scenes of
+ * up to 8192 particles, 64 bodies and 128 slots of 64 lanes (see
+ * pbdr_pool_set_tuning) keep their particles in registers, in 7 size classes
+ * whose launch shape is tunable; larger ones run a kernel that keeps them in
+ * global memory.  Scenes
  * share the pool's pbdr_params (time step, substeps, iterations, radius,
  * planes, flags, nbr_cap; hash_bits and PBDR_FLAG_NO_GRAPH are ignored) and
  * bring their own gravity and friction coefficient.
@@ -240,9 +243,9 @@ void pbdr_scene_destroy(pbdr_scene* scene);
  * contiguous particle range or no body range is free; pbdr_pool_info reports
  * what is free.  Slots are reused after pbdr_pool_remove.
  * ------------------------------------------------------------------------ */
-#define PBDR_POOL_MAX_PARTICLES 8192
-#define PBDR_POOL_MAX_BODIES 64
-#define PBDR_POOL_CLASSES 7      /* size classes: class c holds scenes of n <= 128 << c */
+#define PBDR_POOL_MAX_PARTICLES 65535
+#define PBDR_POOL_MAX_BODIES 256
+#define PBDR_POOL_CLASSES 7      /* register-resident size classes: class c holds scenes of n <= 128 << c */
 
 typedef struct pbdr_pool pbdr_pool;
 
@@ -317,7 +320,7 @@ pbdr_status pbdr_pool_check(pbdr_pool* pool, int32_t slot, int32_t* max_neighbou
 pbdr_status pbdr_pool_get_tuning(const pbdr_pool* pool, int32_t* waves);
 pbdr_status pbdr_pool_set_tuning(pbdr_pool* pool, const int32_t* waves);
 
-/* Tuner: for every size class with resident scenes, times each admissible
+/* Tuner: for every register-resident size class with resident scenes, times each admissible
  * launch shape over n_frames frames of the class's scenes (best of `repeats`)
  * and keeps the fastest.  Scene states are restored afterwards; synchronises.
  * ms_out (may be NULL) receives [PBDR_POOL_CLASSES] the chosen shape's time. */

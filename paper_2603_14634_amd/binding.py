@@ -34,7 +34,7 @@ EXPORTED = [
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
     "pbdr_pool_info_get", "pbdr_pool_destroy",
 ]
-POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES = 8192, 64, 7
+POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES = 65535, 256, 7
 
 
 class Params(ctypes.Structure):

@@ -22,15 +22,21 @@ using pbdr::host::Resolved;
 
 namespace {
 
-constexpr int kClasses = pbdr::kPoolClasses;
+constexpr int kClasses = pbdr::kPoolClasses;          // tunable (register-resident) classes
+constexpr int kLaunchClasses = kClasses + 1;           // ... and the large scenes
+constexpr int kBig = pbdr::kPoolBigClass;
 static_assert(kClasses == PBDR_POOL_CLASSES, "class count");
-static_assert(pbdr::kPoolMaxParticles == PBDR_POOL_MAX_PARTICLES, "pool scene size");
-static_assert(pbdr::kPoolMaxBodies == PBDR_POOL_MAX_BODIES, "pool body count");
+static_assert(pbdr::kPoolBigMaxParticles == PBDR_POOL_MAX_PARTICLES, "pool scene size");
+static_assert(pbdr::kPoolBigMaxBodies == PBDR_POOL_MAX_BODIES, "pool body count");
 
 struct PoolLayout {
     size_t x, v, mass, q, pbody, dl, xt, sxt4, nbr_n, nbr, save_x, save_v, body_first, body_mass, body_mq, scenes,
-        stats, save_stats, order, total;
+        stats, save_stats, order, part, sid, rank, vel, cd, total;
 };
+
+// Slot-sum arena of the large scenes: every scene needs at most
+// n / 64 + 1 + n_bodies slots.
+size_t slot_arena(int32_t S, int32_t P, int32_t Bc) { return (size_t)P / 64 + (size_t)Bc + (size_t)S; }
 
 PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
 {
@@ -61,6 +67,11 @@ PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
     L.stats = take(sizeof(pbdr::PoolStat) * s);
     L.save_stats = take(sizeof(pbdr::PoolStat) * s);
     L.order = take(4 * s);
+    L.part = take(4 * 24 * slot_arena(S, P, Bc));
+    L.sid = take(4 * p);
+    L.rank = take(4 * p);
+    L.vel = take(12 * p);
+    L.cd = take(12 * p);
     L.total = off;
     return L;
 }
@@ -115,14 +126,18 @@ struct SlotInfo {
     bool used = false;
     int32_t p0 = 0, n = 0, b0 = 0, nb = 0, cls = 0;
     int32_t lanes_slots = 0;        // 64-lane slots of the wave-aligned bodies
+    int32_t s_base = -1;            // large scenes: range in the slot-sum arena
     float g[3] = {0.0f, 0.0f, 0.0f};
     float mu = 0.0f;
     std::vector<char> staging;    // host copy of the upload, kept until the slot is freed
     hipEvent_t uploaded = nullptr;  // recorded after the upload
 };
 
-int class_of(int32_t n)
+// Launch class of a scene: register-resident by size, or the large-scene kernel.
+int class_of(int32_t n, int32_t nb, int32_t lanes_slots, int max_cls)
 {
+    if (n > pbdr::pool_class_bound(max_cls) || nb > pbdr::kPoolMaxBodies || lanes_slots > pbdr::kPoolMaxSlots)
+        return kBig;
     int c = 0;
     while (c < kClasses - 1 && n > pbdr::pool_class_bound(c)) ++c;
     return c;
@@ -156,14 +171,15 @@ struct pbdr_pool {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    hipStream_t aux[kClasses] = {};
+    hipStream_t aux[kLaunchClasses] = {};
     hipEvent_t fork = nullptr;
-    hipEvent_t join[kClasses] = {};
+    hipEvent_t join[kLaunchClasses] = {};
     int32_t S = 0, P = 0, Bc = 0;
     int max_cls = 0;
+    bool big_ok = false;                 // the device holds the large-scene kernel's LDS
     std::vector<SlotInfo> slots;
     std::vector<int32_t> free_slots;
-    RangeAlloc parts, bodies;
+    RangeAlloc parts, bodies, slot_sums;
     int32_t used_particles = 0, used_bodies = 0, used_scenes = 0;
     int waves[kClasses];
     // double-buffered pinned launch plans (scene records + launch order)
@@ -179,7 +195,7 @@ void release_host(pbdr_pool* p)
 {
     for (SlotInfo& si : p->slots)
         if (si.uploaded) (void)hipEventDestroy(si.uploaded);
-    for (int c = 0; c < kClasses; ++c) {
+    for (int c = 0; c < kLaunchClasses; ++c) {
         if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
         if (p->join[c]) (void)hipEventDestroy(p->join[c]);
     }
@@ -209,8 +225,8 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
     HIP_TRY(hipEventSynchronize(p->uploaded[b]));       // the buffer's previous upload is done
     pbdr::PoolScene* hs = p->h_scenes[b];
     int32_t* ho = p->h_order[b];
-    std::vector<int32_t> by_class[kClasses];
-    int32_t nmax[kClasses] = {0};   // largest slot count per class
+    std::vector<int32_t> by_class[kLaunchClasses];
+    int32_t nmax[kLaunchClasses] = {0};   // largest slot count per class
     for (int32_t j = 0; j < p->S; ++j) {
         const SlotInfo& si = p->slots[(size_t)j];
         pbdr::PoolScene& r = hs[j];
@@ -221,6 +237,7 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
         r.b0 = si.b0;
         r.nb = si.nb;
         r.units = units[(size_t)j];
+        r.s_base = si.s_base;
         for (int k = 0; k < 3; ++k) r.g[k] = si.g[k];
         r.mu = si.mu;
         if (r.units > 0 && (only_class < 0 || si.cls == only_class)) {
@@ -230,8 +247,8 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
             r.units = 0;
         }
     }
-    int first[kClasses], count[kClasses], at = 0;
-    for (int c = 0; c < kClasses; ++c) {
+    int first[kLaunchClasses], count[kLaunchClasses], at = 0;
+    for (int c = 0; c < kLaunchClasses; ++c) {
         auto& v = by_class[c];
         // largest scenes first: they finish last, so they start first
         std::stable_sort(v.begin(), v.end(),
@@ -247,22 +264,22 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
     HIP_TRY(hipEventRecord(p->uploaded[b], p->stream));
     if (t0) HIP_TRY(hipEventRecord(t0, p->stream));
     int active = 0;
-    for (int c = 0; c < kClasses; ++c) active += count[c] > 0;
+    for (int c = 0; c < kLaunchClasses; ++c) active += count[c] > 0;
     if (active == 1) {          // one class: launch on the pool's stream
-        for (int c = 0; c < kClasses; ++c) {
+        for (int c = 0; c < kLaunchClasses; ++c) {
             if (!count[c]) continue;
-            const int w = width_for(nmax[c], p->waves[c]);
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, sets_for(nmax[c], w), first[c], count[c],
+            const int w = c == kBig ? 16 : width_for(nmax[c], p->waves[c]);
+            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, c == kBig ? 1 : sets_for(nmax[c], w), first[c], count[c],
                                                     subs_per_unit, p->stream);
             if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
         }
     } else {                    // classes run side by side on their own streams
         HIP_TRY(hipEventRecord(p->fork, p->stream));
-        for (int c = 0; c < kClasses; ++c) {
+        for (int c = 0; c < kLaunchClasses; ++c) {
             if (!count[c]) continue;
             HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork, 0));
-            const int w = width_for(nmax[c], p->waves[c]);
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, sets_for(nmax[c], w), first[c], count[c],
+            const int w = c == kBig ? 16 : width_for(nmax[c], p->waves[c]);
+            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, c == kBig ? 1 : sets_for(nmax[c], w), first[c], count[c],
                                                     subs_per_unit, p->aux[c]);
             if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
             HIP_TRY(hipEventRecord(p->join[c], p->aux[c]));
@@ -334,8 +351,10 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     for (int c = 0; c < kClasses; ++c)
         if (pbdr::pool_lds_bytes(c) <= (size_t)lds_max) max_cls = c;
     if (max_cls < 0) return fail(PBDR_ERR_DEVICE, "the device offers %d bytes of LDS per workgroup, too few for pools", lds_max);
+    const bool big_ok = pbdr::pool_lds_bytes(kBig) <= (size_t)lds_max;
     {
-        hipError_t e = pbdr::pool_prepare(pbdr::pool_lds_bytes(max_cls));
+        const size_t need = std::max(pbdr::pool_lds_bytes(max_cls), big_ok ? pbdr::pool_lds_bytes(kBig) : (size_t)0);
+        hipError_t e = pbdr::pool_prepare(need);
         if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool kernel set-up failed: %s", hipGetErrorString(e));
     }
 
@@ -350,10 +369,12 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     p->P = max_particles;
     p->Bc = max_bodies;
     p->max_cls = max_cls;
+    p->big_ok = big_ok;
     p->slots.resize((size_t)max_scenes);
     for (int32_t j = max_scenes - 1; j >= 0; --j) p->free_slots.push_back(j);
     p->parts.init(max_particles);
     p->bodies.init(max_bodies);
+    p->slot_sums.init((int32_t)slot_arena(max_scenes, max_particles, max_bodies));
     for (int c = 0; c < kClasses; ++c) p->waves[c] = std::min(16, std::max(1, pbdr::pool_class_bound(c) / 64));   // one set
 
     pbdr::PoolConsts& c = p->consts;
@@ -395,9 +416,14 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     d.scenes = (const pbdr::PoolScene*)(w + lay.scenes);
     d.stats = (pbdr::PoolStat*)(w + lay.stats);
     d.order = (const int32_t*)(w + lay.order);
+    d.part = (float*)(w + lay.part);
+    d.sid = (uint32_t*)(w + lay.sid);
+    d.rank = (uint32_t*)(w + lay.rank);
+    d.vel = (float*)(w + lay.vel);
+    d.cd = (float*)(w + lay.cd);
 
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kClasses && e == hipSuccess; ++k) {
+    for (int k = 0; k < kLaunchClasses && e == hipSuccess; ++k) {
         e = hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[k], hipEventDisableTiming);
     }
@@ -425,10 +451,11 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
     if (!desc || !slot_out) return fail(PBDR_ERR_INVALID_ARG, "desc and slot must not be NULL");
     *slot_out = -1;
     const int32_t n = desc->n_particles, nb = desc->n_bodies;
-    const int32_t nmax = pbdr::pool_class_bound(p->max_cls);
+    const int32_t nmax = p->big_ok ? pbdr::kPoolBigMaxParticles : pbdr::pool_class_bound(p->max_cls);
+    const int32_t bmax = p->big_ok ? pbdr::kPoolBigMaxBodies : pbdr::kPoolMaxBodies;
     if (n < 1 || n > nmax) return fail(PBDR_ERR_INVALID_ARG, "a pooled scene needs 1..%d particles, got %d", nmax, n);
-    if (nb < 1 || nb > PBDR_POOL_MAX_BODIES || nb > n)
-        return fail(PBDR_ERR_INVALID_ARG, "a pooled scene needs 1..%d bodies, got %d", PBDR_POOL_MAX_BODIES, nb);
+    if (nb < 1 || nb > bmax || nb > n)
+        return fail(PBDR_ERR_INVALID_ARG, "a pooled scene needs 1..%d bodies, got %d", bmax, nb);
     if (!desc->x || !desc->v || !desc->mass || !desc->body_start)
         return fail(PBDR_ERR_INVALID_ARG, "desc arrays must not be NULL");
     if (desc->body_start[0] != 0 || desc->body_start[nb] != n)
@@ -439,9 +466,10 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
         if (len < 1) return fail(PBDR_ERR_INVALID_ARG, "body %d is empty or body_start decreases", b);
         lanes_slots += (len + 63) / 64;
     }
-    if (lanes_slots > pbdr::kPoolMaxSlots)
+    const int cls = class_of(n, nb, lanes_slots, p->max_cls);
+    if (cls == kBig && !p->big_ok)
         return fail(PBDR_ERR_INVALID_ARG, "a pooled scene's bodies may fill at most %d slots of 64 lanes (one body per "
-                    "slot), this one needs %d", pbdr::kPoolMaxSlots, lanes_slots);
+                    "slot) on this device, this one needs %d", pbdr::kPoolMaxSlots, lanes_slots);
     for (int32_t i = 0; i < n; ++i)
         if (!(std::isfinite(desc->mass[i]) && desc->mass[i] > 0.0f))
             return fail(PBDR_ERR_INVALID_ARG, "mass[%d] must be finite and > 0", i);
@@ -459,6 +487,12 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
         p->parts.release(p0, n);
         return fail(PBDR_ERR_CAPACITY, "no free range of %d bodies", nb);
     }
+    const int32_t sb = cls == kBig ? p->slot_sums.alloc(lanes_slots) : -1;
+    if (cls == kBig && sb < 0) {          // cannot happen: the arena covers every admissible set of scenes
+        p->parts.release(p0, n);
+        p->bodies.release(b0, nb);
+        return fail(PBDR_ERR_CAPACITY, "no free range of %d slot sums", lanes_slots);
+    }
     const int32_t slot = p->free_slots.back();
     p->free_slots.pop_back();
     SlotInfo& si = p->slots[(size_t)slot];
@@ -467,8 +501,9 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
     si.n = n;
     si.b0 = b0;
     si.nb = nb;
-    si.cls = class_of(n);
+    si.cls = cls;
     si.lanes_slots = lanes_slots;
+    si.s_base = sb;
     for (int k = 0; k < 3; ++k) si.g[k] = (float)desc->gravity[k];
     si.mu = (float)desc->friction_mu;
 
@@ -548,6 +583,8 @@ pbdr_status pbdr_pool_remove(pbdr_pool* p, int32_t slot)
     SlotInfo& si = p->slots[(size_t)slot];
     p->parts.release(si.p0, si.n);
     p->bodies.release(si.b0, si.nb);
+    if (si.s_base >= 0) p->slot_sums.release(si.s_base, si.lanes_slots);
+    si.s_base = -1;
     p->used_particles -= si.n;
     p->used_bodies -= si.nb;
     p->used_scenes -= 1;
@@ -728,7 +765,7 @@ pbdr_status pbdr_pool_info_get(const pbdr_pool* p, pbdr_pool_info* out)
     out->max_bodies = p->Bc;
     out->bodies_used = p->used_bodies;
     out->largest_free_bodies = p->bodies.largest();
-    out->max_scene_particles = pbdr::pool_class_bound(p->max_cls);
+    out->max_scene_particles = p->big_ok ? pbdr::kPoolBigMaxParticles : pbdr::pool_class_bound(p->max_cls);
     out->workspace_bytes = p->lay.total;
     return PBDR_OK;
 }

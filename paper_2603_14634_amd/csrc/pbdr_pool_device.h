@@ -8,9 +8,14 @@
 
 namespace pbdr {
 
-constexpr int kPoolClasses = 7;            // size classes: n <= 128 << c
+constexpr int kPoolClasses = 7;            // register-resident size classes: n <= 128 << c
 constexpr int kPoolMaxParticles = 8192;    // 128 << (kPoolClasses - 1)
-constexpr int kPoolMaxBodies = 64;         // bodies per pooled scene
+constexpr int kPoolMaxBodies = 64;         // bodies of a register-resident scene
+constexpr int kPoolBigClass = kPoolClasses;   // launch class of the large scenes
+constexpr int kPoolBigMaxParticles = 65535;   // scene-local ids fit 16 bits
+constexpr int kPoolBigMaxBodies = 256;
+constexpr int kPoolBigMaxSlots = kPoolBigMaxParticles / 64 + 1 + kPoolBigMaxBodies;
+constexpr int kPoolBigKeyBits = 13;
 constexpr int kPoolMaxWaves = 16;          // waves per workgroup
 constexpr int kPoolBodyFloats = 48;        // per-body LDS record
 constexpr int kPoolMaxSlots = 128;         // 64-lane slots per scene (bodies wave-aligned) = 16 waves x 8
@@ -24,7 +29,8 @@ struct PoolScene {
     int32_t p0, n;      // first particle in the particle arena, particle count
     int32_t b0, nb;     // first body in the body arena, body count
     int32_t units;      // frames (or substeps) to advance in the current launch; 0 = skip
-    int32_t pad[3];
+    int32_t s_base;     // large scenes: first slot of its range in the slot-sum arena
+    int32_t pad[2];
     float g[3];         // gravity
     float mu;           // friction coefficient
 };
@@ -50,6 +56,11 @@ struct PoolDev {
     const int32_t* body_first; // [Bc] first particle of each body (scene-local)
     const float* body_mass;    // [Bc]
     const float* body_mq;      // [Bc][3] sum of m q over the body
+    float* part;               // large scenes: [slot arena][24] slot sums and boxes
+    uint32_t* sid;             // large scenes: [P] key-grouped (id | body << 16)
+    uint32_t* rank;            // large scenes: [P] slot within the key
+    float* vel;                // large scenes: [3][P] V_i while a substep runs
+    float* cd;                 // large scenes: [3][P] contact displacement of the iteration
     const PoolScene* scenes;   // [S]
     PoolStat* stats;           // [S]
     const int32_t* order;      // slots in launch order, grouped by size class
@@ -72,7 +83,7 @@ struct PoolConsts {
     int32_t iterations;
 };
 
-// Dynamic LDS bytes of the pool kernel for a size class.
+// Dynamic LDS bytes of the pool kernel for a size class (or kPoolBigClass).
 size_t pool_lds_bytes(int cls);
 
 // Allows every pool kernel variant up to max_lds bytes of dynamic LDS.

@@ -72,7 +72,8 @@ def _mixed_scenes():
     per-scene gravity and friction."""
     out = []
     for k, sizes in enumerate([[1], [1, 1, 1], [27, 64, 8], [100, 27], [255, 256, 257],
-                               [511, 513, 64, 1, 7], [700, 800, 900, 512], [1000] * 5]):
+                               [511, 513, 64, 1, 7], [700, 800, 900, 512], [1000] * 5,
+                               [27] * 80, [1000] * 12]):        # the last two run the large-scene kernel
         sc = touching_bodies(sizes, seed=10 + k)
         sc.gravity = (0.5 * k, -0.3, -5.0 - k)
         sc.mu = 0.1 * k
@@ -247,11 +248,41 @@ def test_capacity_overflow_and_non_finite_are_latched_per_scene():
 
 def test_pool_rejects_bad_scenes():
     sc = scenes.batch_scenes(6, n_scenes=1)[0]
-    pool = _new_pool([sc])
-    big = scenes.single_body(scenes.lattice_box(21, 21, 21, 0.02), radius=0.01)
+    big = scenes.single_body(scenes.lattice_box(41, 40, 40, 0.02), radius=0.01)
+    many = touching_bodies([1] * 257)
+    pool = B.Pool(_pool_params(sc), 4, big.n + sc.n, 400)
     with pytest.raises(B.PbdrError):
-        pool.add(big)                           # above the largest pooled scene
-    many = touching_bodies([1] * 65)
+        pool.add(big)                           # above the largest pooled scene (65535 particles)
     with pytest.raises(B.PbdrError):
-        pool.add(many)                          # more bodies than a pooled scene holds
+        pool.add(many)                          # more bodies than a pooled scene holds (256)
+    pool.add(sc)
+    pool.close()
+
+
+def test_large_scenes_alone_and_among_small_ones():
+    """Scenes above the register-resident limits (more than 8192 particles or
+    64 bodies) share a pool with small ones; each result is the same alone."""
+    big = touching_bodies([900] * 11, seed=7)           # 9900 particles
+    wide = touching_bodies([27] * 90, seed=8)           # 90 bodies
+    small = scenes.batch_scenes(9, n_scenes=10)
+    frames = 6
+    want = {}
+    for sc in (big, wide):
+        pool = _new_pool([sc])
+        s = pool.add(sc)
+        pool.step(frames)
+        want[id(sc)] = pool.read_state(s)
+        pool.close()
+    mix_list = small[:5] + [big] + small[5:] + [wide]
+    pool = _new_pool(mix_list)
+    slots = [pool.add(sc) for sc in mix_list]
+    for _ in range(frames):
+        pool.step(1)
+    for sc, sl in zip(mix_list, slots):
+        if id(sc) in want:
+            x, v = pool.read_state(sl)
+            np.testing.assert_array_equal(x, want[id(sc)][0])
+            np.testing.assert_array_equal(v, want[id(sc)][1])
+        else:
+            pool.check(sl)
     pool.close()
