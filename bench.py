@@ -1,7 +1,13 @@
 #!/usr/bin/env python3
 """Throughput of the PBD-R solver substep on one MI355X.
 
-Workload (default): ``cuboid_rain_1000`` -- 1000 randomly oriented cuboid
+Workloads: ``cuboid_rain_1000`` (default), ``drop_cubes_8x64`` and
+``dense_pile_20k`` run one scene through the single-scene solver;
+``batch_4096`` steps 4096 independent scenes (log-normal 100-5000 particles)
+in a scene pool; ``serving`` serves Poisson-arriving rollout requests with
+continuous batching and reports p50/p99 latency beside throughput.
+
+Default workload: ``cuboid_rain_1000`` -- 1000 randomly oriented cuboid
 lattices (per-axis sizes U{3..8}, about 171k particles, r = 0.01 m), ground
 plane, dt = 1/240 s, 4 substeps x 10 iterations per frame, seeded synthetic
 input.  A "step" is one frame: 4 full substeps (prediction, hash-grid
@@ -25,11 +31,14 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_14634_amd", "csrc", "pbdr_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_14634_amd", "csrc", f)
+               for f in ("pbdr_kernels.hip", "pbdr_math.h", "pbdr_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_cuboid_rain_1000_traffic.txt")
 
 
@@ -49,8 +58,12 @@ def iterate_bytes_per_body() -> float:
 
 
 def source_digest() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the single-scene kernel sources (the iteration kernel and what it includes)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(n_launch_bytes: float):
@@ -92,6 +105,149 @@ def cpu_baseline(sc, budget_s: float):
                       % (subs, sc.name, sc.n, sc.iterations, threads)}
 
 
+def pool_bytes_per_particle_substep(iterations: int, kbar: float) -> float:
+    """Algorithmic bytes of one particle-substep: the iteration's 84 + 4 k per
+    iteration (as for the single-scene iteration kernel) plus predict (x, v
+    read, X_init, delta, V written: 60) and the neighbour build (24 + 4 k)."""
+    return iterations * iterate_bytes_per_particle(kbar) + 60.0 + 24.0 + 4.0 * kbar
+
+
+def cpu_baseline_scenes(scs, budget_s: float, label: str):
+    """The FP64 reference over whole scenes, one substep each, until the budget is spent."""
+    from oracle import oracle as ref
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    done_n, used, count = 0, 0.0, 0
+    for sc in scs:
+        p = ref.params_for(sc, threads=threads)
+        rest = ref.Body(sc.x, sc.mass, sc.body_start)
+        t0 = time.perf_counter()
+        ref.substep(p, rest, sc.x, sc.v, n_substeps=1)
+        used += time.perf_counter() - t0
+        done_n += sc.n
+        count += 1
+        if used > budget_s:
+            break
+    return {"value": done_n / used, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": "one substep of each of the first %d scenes of %s (%d particles), FP64, %d OpenMP threads"
+                      % (count, label, done_n, threads)}
+
+
+def bench_pool(args):
+    import torch
+    from paper_2603_14634_amd import binding as B
+    from paper_2603_14634_amd import scenes
+
+    batch = scenes.batch_scenes(args.seed)
+    N = sum(sc.n for sc in batch)
+    NB = sum(sc.n_bodies for sc in batch)
+    S = batch[0].substeps
+    print("[bench] batch_4096: %d scenes, %d particles, %d bodies" % (len(batch), N, NB), file=sys.stderr, flush=True)
+    pool = B.Pool(B.params_for(batch[0]), len(batch), N, NB)
+    slots = [pool.add(sc) for sc in batch]
+    stream = pool.stream
+    tuned = pool.autotune(n_frames=2, repeats=1)
+    print("[bench] tuned waves per class %s (ms %s)" % (pool.tuning, ["%.2f" % t for t in tuned]), file=sys.stderr,
+          flush=True)
+    pool.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    pool.step(args.steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    mx = 0
+    for sl in slots:
+        mx = max(mx, pool.check(sl))
+    value = N * S * args.steps / (ms / 1e3)
+    # per-scene launches of the single-scene solver on a sample, for comparison
+    rng = np.random.default_rng(args.seed)
+    pick = rng.choice(len(batch), 16, replace=False)
+    tot_n, tot_ms = 0, 0.0
+    for j in pick:
+        sv = B.Solver.from_scene(batch[j])
+        sv.step(1)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(sv.stream)
+        sv.step(8)
+        e1.record(sv.stream)
+        torch.cuda.synchronize()
+        tot_ms += e0.elapsed_time(e1)
+        tot_n += batch[j].n
+        sv.close()
+    per_scene = tot_n * S * 8 / (tot_ms / 1e3)
+    print("[bench] %d frames in %.3f ms: %.4g particle-substeps/s (per-scene launches: %.4g)"
+          % (args.steps, ms, value, per_scene), file=sys.stderr, flush=True)
+    bpps = pool_bytes_per_particle_substep(batch[0].iterations, 0.0)
+    achieved = value * bpps / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_pool (one workgroup per scene, all substeps of the call)",
+            "avg_launch_us": round(ms * 1e3, 1), "bytes_per_particle_substep": bpps,
+            "note": "state stays on chip across iterations, so HBM carries far less than the algorithmic bytes"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_scenes(batch, args.cpu_budget_s, "batch_4096")
+    line = {
+        "metric": "particle-substeps/s at stated error vs FP64 oracle",
+        "value": round(value, 1), "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms / args.steps, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch_4096", "scenes": len(batch), "particles": N, "bodies": NB, "substeps": S,
+                   "iterations": batch[0].iterations, "seed": args.seed, "max_neighbours": mx,
+                   "per_scene_launch_rate": round(per_scene, 1), "tuned_waves": pool.tuning},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    pool.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(args):
+    from paper_2603_14634_amd import binding as B
+    from paper_2603_14634_amd import scenes
+    from paper_2603_14634_amd.serving import PoolBackend, ServingEngine, pool_for_budget
+
+    reqs = scenes.serving_trace(args.seed, rate_hz=args.rate, duration_s=args.window)
+    params = B.params_for(reqs[0].scene)
+    pool = pool_for_budget(params, args.budget_gib << 30, max_scenes=4096)
+    eng = ServingEngine(PoolBackend(pool), frames_per_tick=args.frames_per_tick, keep_results=False)
+    # warm-up: one tiny request compiles nothing new but touches every path once
+    eng.run([scenes.Request(0.0, reqs[0].scene, 1, -1)])
+    print("[bench] serving: %d requests at %.0f/s over %.2f s, pool of %d particles (%.1f GiB)"
+          % (len(reqs), args.rate, args.window, pool.info().max_particles, pool.info().workspace_bytes / 2 ** 30),
+          file=sys.stderr, flush=True)
+    out = eng.run(reqs)
+    print("[bench] served %d in %.2f s: p50 %.1f ms, p99 %.1f ms, %.4g particle-substeps/s, peak %d resident"
+          % (out["completed"], out["makespan_s"], out["p50_ms"], out["p99_ms"], out["throughput"],
+             out["peak_active"]), file=sys.stderr, flush=True)
+    bpps = pool_bytes_per_particle_substep(reqs[0].scene.iterations, 0.0)
+    busy_rate = out["particle_substeps"] / out["busy_s"] if out["busy_s"] > 0 else 0.0
+    achieved = busy_rate * bpps / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_pool / k_pool_big over the ticks (time the GPU was stepping)",
+            "bytes_per_particle_substep": bpps}
+    cpu = None if args.no_cpu_baseline else cpu_baseline_scenes([r.scene for r in reqs], args.cpu_budget_s,
+                                                                "the serving trace")
+    line = {
+        "metric": "particle-substeps/s at stated error vs FP64 oracle; p50/p99 rollout latency",
+        "value": round(out["throughput"], 1), "unit": "particle-substeps/s", "n_gpus": 1,
+        "steps": out["ticks"], "warmup": 1, "ms_per_step": round(out["busy_s"] * 1e3 / max(out["ticks"], 1), 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "latency_ms": {"p50": round(out["p50_ms"], 2), "p99": round(out["p99_ms"], 2),
+                       "mean_queue_wait": round(out["mean_wait_ms"], 2)},
+        "config": {"workload": "serving", "rate_hz": args.rate, "window_s": args.window, "requests": len(reqs),
+                   "completed": out["completed"], "rejected": len(out["rejected"]),
+                   "peak_resident": out["peak_active"], "frames_per_tick": args.frames_per_tick,
+                   "hbm_budget_gib": args.budget_gib, "makespan_s": round(out["makespan_s"], 3), "seed": args.seed},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    pool.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,7 +262,15 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (3 times), the "
                          "reference for scaling HBM byte counters")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: Poisson arrival rate (requests/s)")
+    ap.add_argument("--window", type=float, default=1.0, help="serving: seconds of arrivals")
+    ap.add_argument("--budget-gib", type=int, default=16, help="serving: HBM budget of the scene pool")
+    ap.add_argument("--frames-per-tick", type=int, default=2, help="serving: frames per scheduling tick")
     args = ap.parse_args()
+    if args.workload == "serving":
+        # the serving lanes and the pool's side-by-side classes use about a dozen
+        # streams; give each its own hardware queue (read when HIP starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
               "(scenes shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
@@ -119,6 +283,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "batch_4096":
+        return bench_pool(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     if args.calibrate_copy_mib > 0:
         nbytes = args.calibrate_copy_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

@@ -246,6 +246,7 @@ void pbdr_scene_destroy(pbdr_scene* scene);
 #define PBDR_POOL_MAX_PARTICLES 65535
 #define PBDR_POOL_MAX_BODIES 256
 #define PBDR_POOL_CLASSES 7      /* register-resident size classes: class c holds scenes of n <= 128 << c */
+#define PBDR_POOL_LANES 4        /* independent launch lanes (see pbdr_pool_step_slots_on) */
 
 typedef struct pbdr_pool pbdr_pool;
 
@@ -292,6 +293,22 @@ pbdr_status pbdr_pool_step(pbdr_pool* pool, int32_t n_frames);
 /* Advances the listed slots by frames[j] frames each (0 = stays); the others
  * stay.  For continuous batching, where scenes have different horizons. */
 pbdr_status pbdr_pool_step_slots(pbdr_pool* pool, int32_t count, const int32_t* slots, const int32_t* frames);
+
+/* As pbdr_pool_step_slots, but enqueued on hip_stream (a hipStream_t) through
+ * launch lane `lane` (0 .. PBDR_POOL_LANES-1).  Launches on different lanes
+ * may be in flight together; each lane's calls must be ordered on one stream.
+ * Lane 0 runs the size classes of a call side by side on internal streams,
+ * the other lanes run them one after another on hip_stream.
+ * The work waits for every pbdr_pool_add before the call.  Synchronise that
+ * stream before reading or removing the listed slots, and list no slot on two
+ * lanes at once.  The pool's own calls use lane 0. */
+pbdr_status pbdr_pool_step_slots_on(pbdr_pool* pool, int32_t lane, void* hip_stream, int32_t count,
+                                    const int32_t* slots, const int32_t* frames);
+
+/* Launch class of a resident scene: 0 .. PBDR_POOL_CLASSES-1 for the
+ * register-resident size classes, PBDR_POOL_CLASSES for the large-scene
+ * kernel. */
+pbdr_status pbdr_pool_slot_class(const pbdr_pool* pool, int32_t slot, int32_t* cls);
 
 /* Advances every resident scene by n_substeps substeps (for substep checks). */
 pbdr_status pbdr_pool_substep(pbdr_pool* pool, int32_t n_substeps);

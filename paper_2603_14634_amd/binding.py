@@ -32,9 +32,9 @@ EXPORTED = [
     "pbdr_pool_bytes", "pbdr_pool_create", "pbdr_pool_add", "pbdr_pool_remove", "pbdr_pool_step",
     "pbdr_pool_step_slots", "pbdr_pool_substep", "pbdr_pool_read_state", "pbdr_pool_read_debug",
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
-    "pbdr_pool_info_get", "pbdr_pool_destroy",
+    "pbdr_pool_info_get", "pbdr_pool_destroy", "pbdr_pool_step_slots_on", "pbdr_pool_slot_class",
 ]
-POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES = 65535, 256, 7
+POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES, POOL_LANES = 65535, 256, 7, 4
 
 
 class Params(ctypes.Structure):
@@ -161,7 +161,9 @@ def load_library(path: str = LIB_PATH):
                        ("pbdr_pool_read_debug", [vp, i32, i32, vp]), ("pbdr_pool_check", [vp, i32, pi32]),
                        ("pbdr_pool_get_tuning", [vp, vp]), ("pbdr_pool_set_tuning", [vp, vp]),
                        ("pbdr_pool_autotune", [vp, i32, i32, vp]),
-                       ("pbdr_pool_info_get", [vp, ctypes.POINTER(PoolInfo)])]:
+                       ("pbdr_pool_info_get", [vp, ctypes.POINTER(PoolInfo)]),
+                       ("pbdr_pool_step_slots_on", [vp, i32, vp, i32, vp, vp]),
+                       ("pbdr_pool_slot_class", [vp, i32, pi32])]:
         fn = getattr(lib, name)
         fn.restype = i32
         fn.argtypes = args
@@ -415,6 +417,20 @@ class Pool:
         if s.shape != f.shape:
             raise ValueError("slots and frames differ in length")
         _check(self._lib.pbdr_pool_step_slots(self._h, int(s.shape[0]), s.ctypes.data, f.ctypes.data))
+
+    def step_slots_on(self, lane: int, stream, slots, frames):
+        """Asynchronous launch of the listed slots on a torch stream through a launch lane."""
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        f = np.ascontiguousarray(frames, dtype=np.int32)
+        if s.shape != f.shape:
+            raise ValueError("slots and frames differ in length")
+        _check(self._lib.pbdr_pool_step_slots_on(self._h, lane, ctypes.c_void_p(stream.cuda_stream), int(s.shape[0]),
+                                                 s.ctypes.data, f.ctypes.data))
+
+    def slot_class(self, slot: int) -> int:
+        c = ctypes.c_int32()
+        _check(self._lib.pbdr_pool_slot_class(self._h, slot, ctypes.byref(c)))
+        return int(c.value)
 
     def substep(self, n_substeps: int = 1):
         _check(self._lib.pbdr_pool_substep(self._h, n_substeps))

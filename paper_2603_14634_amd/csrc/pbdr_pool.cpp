@@ -25,6 +25,7 @@ namespace {
 constexpr int kClasses = pbdr::kPoolClasses;          // tunable (register-resident) classes
 constexpr int kLaunchClasses = kClasses + 1;           // ... and the large scenes
 constexpr int kBig = pbdr::kPoolBigClass;
+constexpr int kLanes = PBDR_POOL_LANES;                // independent launch streams
 static_assert(kClasses == PBDR_POOL_CLASSES, "class count");
 static_assert(pbdr::kPoolBigMaxParticles == PBDR_POOL_MAX_PARTICLES, "pool scene size");
 static_assert(pbdr::kPoolBigMaxBodies == PBDR_POOL_MAX_BODIES, "pool body count");
@@ -66,7 +67,7 @@ PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
     L.scenes = take(sizeof(pbdr::PoolScene) * s);
     L.stats = take(sizeof(pbdr::PoolStat) * s);
     L.save_stats = take(sizeof(pbdr::PoolStat) * s);
-    L.order = take(4 * s);
+    L.order = take(8 * s * kLanes);
     L.part = take(4 * 24 * slot_arena(S, P, Bc));
     L.sid = take(4 * p);
     L.rank = take(4 * p);
@@ -129,6 +130,7 @@ struct SlotInfo {
     int32_t s_base = -1;            // large scenes: range in the slot-sum arena
     float g[3] = {0.0f, 0.0f, 0.0f};
     float mu = 0.0f;
+    pbdr::PoolScene rec = {};     // its device record, uploaded when added
     std::vector<char> staging;    // host copy of the upload, kept until the slot is freed
     hipEvent_t uploaded = nullptr;  // recorded after the upload
 };
@@ -171,9 +173,10 @@ struct pbdr_pool {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
-    hipStream_t aux[kLaunchClasses] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kLaunchClasses] = {};
+    hipStream_t aux[kLanes][kLaunchClasses] = {};
+    hipEvent_t fork[kLanes] = {};
+    hipEvent_t join[kLanes][kLaunchClasses] = {};
+    hipEvent_t added = nullptr;          // recorded after the latest upload of an added scene
     int32_t S = 0, P = 0, Bc = 0;
     int max_cls = 0;
     bool big_ok = false;                 // the device holds the large-scene kernel's LDS
@@ -182,11 +185,10 @@ struct pbdr_pool {
     RangeAlloc parts, bodies, slot_sums;
     int32_t used_particles = 0, used_bodies = 0, used_scenes = 0;
     int waves[kClasses];
-    // double-buffered pinned launch plans (scene records + launch order)
-    pbdr::PoolScene* h_scenes[2] = {nullptr, nullptr};
-    int32_t* h_order[2] = {nullptr, nullptr};
-    hipEvent_t uploaded[2] = {nullptr, nullptr};
-    int plan_buf = 0;
+    // per lane, double-buffered pinned launch lists of (slot, units)
+    int2* h_order[kLanes][2] = {};
+    hipEvent_t uploaded[kLanes][2] = {};
+    int plan_buf[kLanes] = {};
 };
 
 namespace {
@@ -195,16 +197,18 @@ void release_host(pbdr_pool* p)
 {
     for (SlotInfo& si : p->slots)
         if (si.uploaded) (void)hipEventDestroy(si.uploaded);
-    for (int c = 0; c < kLaunchClasses; ++c) {
-        if (p->aux[c]) (void)hipStreamDestroy(p->aux[c]);
-        if (p->join[c]) (void)hipEventDestroy(p->join[c]);
+    for (int l = 0; l < kLanes; ++l) {
+        for (int c = 0; c < kLaunchClasses; ++c) {
+            if (p->aux[l][c]) (void)hipStreamDestroy(p->aux[l][c]);
+            if (p->join[l][c]) (void)hipEventDestroy(p->join[l][c]);
+        }
+        if (p->fork[l]) (void)hipEventDestroy(p->fork[l]);
+        for (int b = 0; b < 2; ++b) {
+            if (p->uploaded[l][b]) (void)hipEventDestroy(p->uploaded[l][b]);
+            if (p->h_order[l][b]) (void)hipHostFree(p->h_order[l][b]);
+        }
     }
-    if (p->fork) (void)hipEventDestroy(p->fork);
-    for (int b = 0; b < 2; ++b) {
-        if (p->uploaded[b]) (void)hipEventDestroy(p->uploaded[b]);
-        if (p->h_scenes[b]) (void)hipHostFree(p->h_scenes[b]);
-        if (p->h_order[b]) (void)hipHostFree(p->h_order[b]);
-    }
+    if (p->added) (void)hipEventDestroy(p->added);
 }
 
 pbdr_status check_slot(const pbdr_pool* p, int32_t slot)
@@ -215,37 +219,24 @@ pbdr_status check_slot(const pbdr_pool* p, int32_t slot)
     return PBDR_OK;
 }
 
-// Uploads a launch plan in which slot j advances units[j] (0 = stays) and
-// launches every size class that has work.
-pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per_unit, int only_class = -1,
-                   hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
+// Launches, on `stream` and the aux streams of `lane`, every size class with
+// work: slot j advances units[j] units (0 = stays).  The launch list is
+// uploaded from the lane's pinned buffers, so launches on different lanes may
+// be in flight together.
+pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector<int32_t>& units, int subs_per_unit,
+                   int only_class = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
 {
-    const int b = p->plan_buf;
-    p->plan_buf ^= 1;
-    HIP_TRY(hipEventSynchronize(p->uploaded[b]));       // the buffer's previous upload is done
-    pbdr::PoolScene* hs = p->h_scenes[b];
-    int32_t* ho = p->h_order[b];
+    const int b = p->plan_buf[lane];
+    p->plan_buf[lane] ^= 1;
+    HIP_TRY(hipEventSynchronize(p->uploaded[lane][b]));       // the buffer's previous upload is done
+    int2* ho = p->h_order[lane][b];
     std::vector<int32_t> by_class[kLaunchClasses];
     int32_t nmax[kLaunchClasses] = {0};   // largest slot count per class
     for (int32_t j = 0; j < p->S; ++j) {
         const SlotInfo& si = p->slots[(size_t)j];
-        pbdr::PoolScene& r = hs[j];
-        std::memset(&r, 0, sizeof(r));
-        if (!si.used) continue;
-        r.p0 = si.p0;
-        r.n = si.n;
-        r.b0 = si.b0;
-        r.nb = si.nb;
-        r.units = units[(size_t)j];
-        r.s_base = si.s_base;
-        for (int k = 0; k < 3; ++k) r.g[k] = si.g[k];
-        r.mu = si.mu;
-        if (r.units > 0 && (only_class < 0 || si.cls == only_class)) {
-            by_class[si.cls].push_back(j);
-            nmax[si.cls] = std::max(nmax[si.cls], si.lanes_slots);
-        } else {
-            r.units = 0;
-        }
+        if (!si.used || units[(size_t)j] <= 0 || (only_class >= 0 && si.cls != only_class)) continue;
+        by_class[si.cls].push_back(j);
+        nmax[si.cls] = std::max(nmax[si.cls], si.lanes_slots);
     }
     int first[kLaunchClasses], count[kLaunchClasses], at = 0;
     for (int c = 0; c < kLaunchClasses; ++c) {
@@ -255,38 +246,40 @@ pbdr_status launch(pbdr_pool* p, const std::vector<int32_t>& units, int subs_per
                          [&](int32_t a, int32_t bb) { return p->slots[(size_t)a].n > p->slots[(size_t)bb].n; });
         first[c] = at;
         count[c] = (int)v.size();
-        for (int32_t j : v) ho[at++] = j;
+        for (int32_t j : v) ho[at++] = make_int2(j, units[(size_t)j]);
     }
     if (at == 0) return PBDR_OK;
-    HIP_TRY(hipMemcpyAsync(p->ws + p->lay.scenes, hs, sizeof(pbdr::PoolScene) * (size_t)p->S, hipMemcpyHostToDevice,
-                           p->stream));
-    HIP_TRY(hipMemcpyAsync(p->ws + p->lay.order, ho, 4 * (size_t)at, hipMemcpyHostToDevice, p->stream));
-    HIP_TRY(hipEventRecord(p->uploaded[b], p->stream));
-    if (t0) HIP_TRY(hipEventRecord(t0, p->stream));
+    HIP_TRY(hipStreamWaitEvent(stream, p->added, 0));          // scenes added on the pool's stream are in place
+    char* dev_order = p->ws + p->lay.order + 8 * (size_t)p->S * lane;
+    HIP_TRY(hipMemcpyAsync(dev_order, ho, 8 * (size_t)at, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(p->uploaded[lane][b], stream));
+    pbdr::PoolDev d = p->dev;
+    d.order = (const int2*)dev_order;
+    if (t0) HIP_TRY(hipEventRecord(t0, stream));
     int active = 0;
     for (int c = 0; c < kLaunchClasses; ++c) active += count[c] > 0;
-    if (active == 1) {          // one class: launch on the pool's stream
-        for (int c = 0; c < kLaunchClasses; ++c) {
-            if (!count[c]) continue;
-            const int w = c == kBig ? 16 : width_for(nmax[c], p->waves[c]);
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, c == kBig ? 1 : sets_for(nmax[c], w), first[c], count[c],
-                                                    subs_per_unit, p->stream);
-            if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
+    // Lane 0 runs several classes side by side on its aux streams; the other
+    // lanes run their classes one after another on their own stream (every
+    // stream shares a few hardware queues, so fewer streams keep the lanes apart).
+    if (lane != 0) active = 1;
+    if (active > 1) HIP_TRY(hipEventRecord(p->fork[lane], stream));
+    for (int c = 0; c < kLaunchClasses; ++c) {
+        if (!count[c]) continue;
+        hipStream_t s = stream;
+        if (active > 1) {       // classes run side by side on the lane's aux streams
+            s = p->aux[lane][c];
+            HIP_TRY(hipStreamWaitEvent(s, p->fork[lane], 0));
         }
-    } else {                    // classes run side by side on their own streams
-        HIP_TRY(hipEventRecord(p->fork, p->stream));
-        for (int c = 0; c < kLaunchClasses; ++c) {
-            if (!count[c]) continue;
-            HIP_TRY(hipStreamWaitEvent(p->aux[c], p->fork, 0));
-            const int w = c == kBig ? 16 : width_for(nmax[c], p->waves[c]);
-            hipError_t e = pbdr::enqueue_pool_class(p->dev, p->consts, c, w, c == kBig ? 1 : sets_for(nmax[c], w), first[c], count[c],
-                                                    subs_per_unit, p->aux[c]);
-            if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
-            HIP_TRY(hipEventRecord(p->join[c], p->aux[c]));
-            HIP_TRY(hipStreamWaitEvent(p->stream, p->join[c], 0));
-        }
+        const int w = c == kBig ? 16 : width_for(nmax[c], p->waves[c]);
+        hipError_t e = pbdr::enqueue_pool_class(d, p->consts, c, w, c == kBig ? 1 : sets_for(nmax[c], w), first[c],
+                                                count[c], subs_per_unit, s);
+        if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "pool launch failed: %s", hipGetErrorString(e));
+        if (active > 1) HIP_TRY(hipEventRecord(p->join[lane][c], s));
     }
-    if (t1) HIP_TRY(hipEventRecord(t1, p->stream));
+    if (active > 1)
+        for (int c = 0; c < kLaunchClasses; ++c)
+            if (count[c]) HIP_TRY(hipStreamWaitEvent(stream, p->join[lane][c], 0));
+    if (t1) HIP_TRY(hipEventRecord(t1, stream));
     return PBDR_OK;
 }
 
@@ -415,7 +408,7 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     d.body_mq = (const float*)(w + lay.body_mq);
     d.scenes = (const pbdr::PoolScene*)(w + lay.scenes);
     d.stats = (pbdr::PoolStat*)(w + lay.stats);
-    d.order = (const int32_t*)(w + lay.order);
+    d.order = (const int2*)(w + lay.order);
     d.part = (float*)(w + lay.part);
     d.sid = (uint32_t*)(w + lay.sid);
     d.rank = (uint32_t*)(w + lay.rank);
@@ -423,18 +416,21 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     d.cd = (float*)(w + lay.cd);
 
     hipError_t e = hipSuccess;
-    for (int k = 0; k < kLaunchClasses && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&p->aux[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[k], hipEventDisableTiming);
+    for (int l = 0; l < kLanes && e == hipSuccess; ++l) {
+        for (int k = 0; k < kLaunchClasses && e == hipSuccess && l == 0; ++k) {
+            e = hipStreamCreateWithFlags(&p->aux[l][k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[l][k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork[l], hipEventDisableTiming);
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+            e = hipEventCreateWithFlags(&p->uploaded[l][b], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_order[l][b], 8 * (size_t)max_scenes, 0);
+        }
     }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming);
-    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
-        e = hipEventCreateWithFlags(&p->uploaded[b], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_scenes[b], sizeof(pbdr::PoolScene) * (size_t)max_scenes, 0);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_order[b], 4 * (size_t)max_scenes, 0);
-    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p->added, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMemsetAsync(p->ws + lay.scenes, 0, sizeof(pbdr::PoolScene) * (size_t)max_scenes, p->stream);
     if (e == hipSuccess) e = hipMemsetAsync(p->ws + lay.stats, 0, sizeof(pbdr::PoolStat) * (size_t)max_scenes, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->added, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) {
         release_host(p);
@@ -562,8 +558,20 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
     if (e == hipSuccess)
         e = hipMemsetAsync(p->ws + p->lay.stats + sizeof(pbdr::PoolStat) * (size_t)slot, 0, sizeof(pbdr::PoolStat),
                            p->stream);
+    si.rec = pbdr::PoolScene{};
+    si.rec.p0 = p0;
+    si.rec.n = n;
+    si.rec.b0 = b0;
+    si.rec.nb = nb;
+    si.rec.s_base = sb;
+    for (int k = 0; k < 3; ++k) si.rec.g[k] = si.g[k];
+    si.rec.mu = si.mu;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->ws + p->lay.scenes + sizeof(pbdr::PoolScene) * (size_t)slot, &si.rec,
+                           sizeof(pbdr::PoolScene), hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess && !si.uploaded) e = hipEventCreateWithFlags(&si.uploaded, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(si.uploaded, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(p->added, p->stream);
     p->used_particles += n;
     p->used_bodies += nb;
     p->used_scenes += 1;
@@ -603,7 +611,7 @@ pbdr_status pbdr_pool_step(pbdr_pool* p, int32_t n_frames)
     if ((long long)n_frames * p->res.p.substeps > INT_MAX) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
     if (n_frames == 0) return PBDR_OK;
     std::vector<int32_t> units((size_t)p->S, n_frames);
-    return launch(p, units, p->res.p.substeps);
+    return launch(p, 0, p->stream, units, p->res.p.substeps);
 }
 
 pbdr_status pbdr_pool_step_slots(pbdr_pool* p, int32_t count, const int32_t* slots, const int32_t* frames)
@@ -618,7 +626,33 @@ pbdr_status pbdr_pool_step_slots(pbdr_pool* p, int32_t count, const int32_t* slo
             return fail(PBDR_ERR_INVALID_ARG, "frames[%d] out of range", j);
         units[(size_t)slots[j]] = frames[j];
     }
-    return launch(p, units, p->res.p.substeps);
+    return launch(p, 0, p->stream, units, p->res.p.substeps);
+}
+
+pbdr_status pbdr_pool_step_slots_on(pbdr_pool* p, int32_t lane, void* hip_stream, int32_t count, const int32_t* slots,
+                                    const int32_t* frames)
+{
+    if (!p) return fail(PBDR_ERR_INVALID_ARG, "pool is NULL");
+    if (lane < 0 || lane >= kLanes) return fail(PBDR_ERR_INVALID_ARG, "lane must be in [0, %d)", kLanes);
+    if (count < 0 || (count > 0 && (!slots || !frames))) return fail(PBDR_ERR_INVALID_ARG, "bad slot list");
+    std::vector<int32_t> units((size_t)p->S, 0);
+    for (int32_t j = 0; j < count; ++j) {
+        pbdr_status st = check_slot(p, slots[j]);
+        if (st != PBDR_OK) return st;
+        if (frames[j] < 0 || (long long)frames[j] * p->res.p.substeps > INT_MAX)
+            return fail(PBDR_ERR_INVALID_ARG, "frames[%d] out of range", j);
+        units[(size_t)slots[j]] = frames[j];
+    }
+    return launch(p, lane, (hipStream_t)hip_stream, units, p->res.p.substeps);
+}
+
+pbdr_status pbdr_pool_slot_class(const pbdr_pool* p, int32_t slot, int32_t* cls)
+{
+    pbdr_status st = check_slot(p, slot);
+    if (st != PBDR_OK) return st;
+    if (!cls) return fail(PBDR_ERR_INVALID_ARG, "cls is NULL");
+    *cls = p->slots[(size_t)slot].cls;
+    return PBDR_OK;
 }
 
 pbdr_status pbdr_pool_substep(pbdr_pool* p, int32_t n_substeps)
@@ -627,7 +661,7 @@ pbdr_status pbdr_pool_substep(pbdr_pool* p, int32_t n_substeps)
     if (n_substeps < 0) return fail(PBDR_ERR_INVALID_ARG, "n_substeps must be >= 0");
     if (n_substeps == 0) return PBDR_OK;
     std::vector<int32_t> units((size_t)p->S, n_substeps);
-    return launch(p, units, 1);
+    return launch(p, 0, p->stream, units, 1);
 }
 
 pbdr_status pbdr_pool_read_state(pbdr_pool* p, int32_t slot, float* x, float* v, int32_t on_device)
@@ -728,7 +762,7 @@ pbdr_status pbdr_pool_autotune(pbdr_pool* p, int32_t n_frames, int32_t repeats, 
             double t_best = 1e300;
             for (int r = 0; r < repeats && st == PBDR_OK; ++r) {
                 if ((st = restore()) != PBDR_OK) break;
-                if ((st = launch(p, units, p->res.p.substeps, c, t0, t1)) != PBDR_OK) break;
+                if ((st = launch(p, 0, p->stream, units, p->res.p.substeps, c, t0, t1)) != PBDR_OK) break;
                 hipError_t e = hipEventSynchronize(t1);
                 float ms = 0.0f;
                 if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);

@@ -24,13 +24,12 @@ inline int pool_class_bound(int cls) { return 128 << cls; }
 // key bits of a class's workgroup-local hash table (about one key per particle)
 inline int pool_class_key_bits(int cls) { return cls + 7 < 8 ? 8 : (cls + 7 > 13 ? 13 : cls + 7); }
 
-// One pooled scene (indexed by slot), written by the host.
+// One pooled scene (indexed by slot), written by the host when it is added.
 struct PoolScene {
     int32_t p0, n;      // first particle in the particle arena, particle count
     int32_t b0, nb;     // first body in the body arena, body count
-    int32_t units;      // frames (or substeps) to advance in the current launch; 0 = skip
     int32_t s_base;     // large scenes: first slot of its range in the slot-sum arena
-    int32_t pad[2];
+    int32_t pad[3];
     float g[3];         // gravity
     float mu;           // friction coefficient
 };
@@ -63,7 +62,7 @@ struct PoolDev {
     float* cd;                 // large scenes: [3][P] contact displacement of the iteration
     const PoolScene* scenes;   // [S]
     PoolStat* stats;           // [S]
-    const int32_t* order;      // slots in launch order, grouped by size class
+    const int2* order;         // per launch: (slot, frames or substeps), grouped by size class
 };
 
 // FP32 constants shared by every scene of a pool.
@@ -93,7 +92,7 @@ hipError_t pool_prepare(size_t max_lds);
 inline bool pool_slots_supported(int s) { return (s >= 1 && s <= 6) || s == 8; }
 
 // Launches the pool kernel over `count` scenes of class `cls` listed at
-// order[first ..]: each scene advances units * subs_per_unit substeps.
+// order[first ..]: each listed (slot, units) advances units * subs_per_unit substeps.
 // `waves` (1, 2, 4, 8 or 16) and `slots` (register sets per lane, see
 // pool_slots_supported) must satisfy waves * slots >= the largest slot count
 // (sum over bodies of ceil(n_b / 64)) of the listed scenes.

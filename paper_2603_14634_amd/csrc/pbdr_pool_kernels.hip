@@ -541,10 +541,11 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
     uint32_t* ovl_n = (uint32_t*)(ovl + kPoolMaxBodies * kPoolMaxBodies);   // [64]
     uint32_t* misc = ovl_n + kPoolMaxBodies;                      // wave totals [16], flags
 
-    const int slot = d.order[first + blockIdx.x];
+    const int2 job = d.order[first + blockIdx.x];                  // (slot, frames or substeps)
+    const int slot = job.x;
     const PoolScene& sc = d.scenes[slot];
     const int n = sc.n, nb = sc.nb, p0 = sc.p0, b0 = sc.b0;
-    const int units = sc.units;
+    const int units = job.y;
     if (units <= 0 || n <= 0) return;                              // uniform over the workgroup
     const int total_subs = units * subs_per_unit;
     const int T = blockDim.x, W = T >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
@@ -752,10 +753,11 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
     uint32_t* ovl = (uint32_t*)(slot_tab + kPoolBigMaxSlots);          // [256][8] bit sets of near bodies
     uint32_t* misc = ovl + kPoolBigMaxBodies * kBigWords;              // wave totals [16], flags
 
-    const int slot = d.order[first + blockIdx.x];
+    const int2 job = d.order[first + blockIdx.x];                       // (slot, frames or substeps)
+    const int slot = job.x;
     const PoolScene& sc = d.scenes[slot];
     const int n = sc.n, nb = sc.nb, p0 = sc.p0, b0 = sc.b0;
-    const int units = sc.units;
+    const int units = job.y;
     if (units <= 0 || n <= 0) return;                                   // uniform over the workgroup
     const int total_subs = units * subs_per_unit;
     const int T = blockDim.x, W = T >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;

@@ -263,16 +263,16 @@ def dense_pile(seed: int = 0, n_bodies: int = 20000, radius: float = 0.01,
 
 
 def small_scene(rng: np.random.Generator, n_target: int, radius: float = 0.01,
-                gravity_z: Optional[float] = None, mu: Optional[float] = None) -> Scene:
+                gravity_z: Optional[float] = None, mu: Optional[float] = None, max_bodies: int = 50) -> Scene:
     """A scene of cuboid bodies (as in ``cuboid_rain``) totalling about n_target particles.
 
-    Bodies are drawn until the target is reached (at least 1, at most 50); the
-    spawn box grows with the body count.  Gravity magnitude U(5, 15) along -z
-    and friction U(0, 1) unless given.
+    Bodies are drawn until the target is reached (at least 1, at most
+    ``max_bodies``); the spawn box grows with the body count.  Gravity magnitude
+    U(5, 15) along -z and friction U(0, 1) unless given.
     """
     offs, masses = [], []
     total = 0
-    while total < n_target and len(offs) < 50:
+    while total < n_target and len(offs) < max_bodies:
         o, mm = _cuboid_bodies(rng, 1, radius)
         offs += o
         masses += mm
@@ -310,11 +310,13 @@ class Request:
 
 
 def serving_trace(seed: int = 0, rate_hz: float = 200.0, duration_s: float = 2.0,
-                  lo: int = 200, hi: int = 50000, h_lo: int = 50, h_hi: int = 500) -> List[Request]:
+                  lo: int = 200, hi: int = 50000, h_lo: int = 50, h_hi: int = 500,
+                  max_bodies: int = 256) -> List[Request]:
     """Poisson arrivals of rollout requests.
 
-    Scene sizes log-uniform in [lo, hi] particles (built like ``small_scene``),
-    horizons uniform in {h_lo..h_hi} frames.
+    Target sizes log-uniform in [lo, hi] particles (built like ``small_scene``
+    with at most ``max_bodies`` bodies, so the largest scenes hold about 42k
+    particles), horizons uniform in {h_lo..h_hi} frames.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
@@ -324,7 +326,7 @@ def serving_trace(seed: int = 0, rate_hz: float = 200.0, duration_s: float = 2.0
         if t > duration_s:
             break
         n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
-        sc = small_scene(rng, n)
+        sc = small_scene(rng, n, max_bodies=max_bodies)
         out.append(Request(t, sc, int(rng.integers(h_lo, h_hi + 1)), len(out)))
     return out
 

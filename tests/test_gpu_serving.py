@@ -1,0 +1,72 @@
+"""Serving on the GPU: continuous batching over a scene pool.
+
+Each request's result (its scene's state after its horizon) must be the same,
+bit for bit, whether it is served alone or among others that arrive and leave
+while it runs, and admission must keep the resident scenes within the pool's
+HBM arena.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_14634_amd import binding as B
+from paper_2603_14634_amd import scenes
+from paper_2603_14634_amd.serving import PoolBackend, ServingEngine, pool_for_budget
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    B.load_library()
+
+
+def _trace(seed=0, rate=400.0, duration=0.06):
+    return scenes.serving_trace(seed, rate_hz=rate, duration_s=duration, lo=200, hi=20000, h_lo=4, h_hi=24)
+
+
+def _serve(reqs, budget=256 << 20, fpt=2):
+    params = B.params_for(reqs[0].scene)
+    pool = pool_for_budget(params, budget, max_scenes=64)
+    eng = ServingEngine(PoolBackend(pool), frames_per_tick=fpt)
+    out = eng.run(reqs)
+    info = pool.info()
+    pool.close()
+    return out, info
+
+
+def test_each_result_is_the_same_alone_and_in_the_mix():
+    reqs = _trace()
+    assert len(reqs) >= 10
+    sizes = np.array([r.scene.n for r in reqs])
+    picks = sorted({int(np.argmax(sizes)), int(np.argmin(sizes)), len(reqs) // 2})
+    mixed, _ = _serve(reqs, fpt=2)
+    assert mixed["completed"] == len(reqs) and not mixed["rejected"]
+    by_id = {o.request_id: o for o in mixed["outcomes"]}
+    print("[serve] %d requests, peak %d resident, p50 %.1f ms, p99 %.1f ms"
+          % (len(reqs), mixed["peak_active"], mixed["p50_ms"], mixed["p99_ms"]), flush=True)
+    assert mixed["peak_active"] >= 2                   # requests overlapped on the device
+    for j in picks:
+        r = reqs[j]
+        alone_req = scenes.Request(0.0, r.scene, r.frames, r.request_id)
+        alone, _ = _serve([alone_req], fpt=3)          # other tick sizes too
+        a = alone["outcomes"][0]
+        m = by_id[r.request_id]
+        print("[serve] request %d: %d particles, %d frames" % (j, r.scene.n, r.frames), flush=True)
+        np.testing.assert_array_equal(m.x, a.x)
+        np.testing.assert_array_equal(m.v, a.v)
+
+
+def test_admission_keeps_the_resident_scenes_within_the_budget():
+    reqs = _trace(seed=3, rate=1000.0, duration=0.03)
+    need = max(r.scene.n for r in reqs)
+    params = B.params_for(reqs[0].scene)
+    budget = B.pool_bytes(params, 64, 2 * need, max(1, 2 * need // 16))
+    out, info = _serve(reqs, budget=budget, fpt=4)
+    assert out["completed"] == len(reqs)
+    assert info.max_particles < sum(r.scene.n for r in reqs)   # not everything fits at once
+    assert out["mean_wait_ms"] > 0.0                            # so some requests queued
+    assert info.particles_used == 0 and info.scenes_used == 0   # everything left the pool
