@@ -131,6 +131,8 @@ typedef struct {
     int32_t waves_per_block;      /* iteration kernel: 64-lane waves per workgroup */
     int32_t iteration_blocks;     /* iteration kernel: workgroups per launch */
     int32_t max_body_particles;
+    int32_t iteration_kernel;     /* 0: register-rich variant; 1: 80-VGPR variant, taken
+                                     when the grid oversubscribes the GPU */
     size_t workspace_bytes;
 } pbdr_scene_info;
 

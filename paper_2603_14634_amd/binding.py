@@ -80,6 +80,7 @@ class SceneInfo(ctypes.Structure):
         ("waves_per_block", ctypes.c_int32),
         ("iteration_blocks", ctypes.c_int32),
         ("max_body_particles", ctypes.c_int32),
+        ("iteration_kernel", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 

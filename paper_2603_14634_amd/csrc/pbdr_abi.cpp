@@ -414,6 +414,12 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     }
     s->dev.waves_per_block = W;
     s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
+    {   // more workgroups than the GPU holds at once with 4 waves per SIMD (16 per
+        // CU, the ~100-VGPR kernel): take the 80-VGPR kernel, 6 waves per SIMD
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
+    }
     std::vector<int32_t> block_body(2 * (size_t)s->dev.n_iter_blocks);   // first body, body count
     for (int32_t blk = 0; blk < s->dev.n_iter_blocks; ++blk) {
         int32_t first = -1, last = -1;
@@ -643,6 +649,7 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->waves_per_block = s->dev.waves_per_block;
     out->iteration_blocks = s->dev.n_iter_blocks;
     out->max_body_particles = s->max_body;
+    out->iteration_kernel = s->dev.dense_iterate;
     out->workspace_bytes = s->lay.total;
     return PBDR_OK;
 }

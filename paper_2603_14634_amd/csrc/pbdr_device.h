@@ -71,6 +71,7 @@ struct Scene {
     const float* body_mq;     // [B][3] sum of m q over the body (rest frame, ~0)
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
+    int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (80-VGPR kernel)
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
     float* xt;                // [3][N] FP32 predicted positions

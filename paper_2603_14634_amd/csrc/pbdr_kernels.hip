@@ -330,7 +330,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 // wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
 // the substep: from the second iteration on, the rotation is refined from the
 // previous iteration's.
-__global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
+__device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it)
 {
     constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
     __shared__ float4 red_sm[kMaxWaves * NSM / 4];
@@ -589,6 +589,21 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
     }
 }
 
+// The iteration kernel in two register budgets: the compiler's choice (about
+// 100 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
+// (6 waves per SIMD) for grids that oversubscribe it, where two workgroups per
+// CU hide each other's per-body phases.
+__global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
+{
+    iterate_body(s, c, src, it);
+}
+
+__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
+k_iterate_dense(Scene s, StepConsts c, int src, int it)
+{
+    iterate_body(s, c, src, it);
+}
+
 // Canonical (key, id) order from the key grouping of the last substep: the
 // grouping keeps an arbitrary order inside a key (slots from atomic ranks);
 // particle i goes to its key's first slot plus the number of smaller ids
@@ -644,7 +659,11 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src, it);
+    if (s.dense_iterate)
+        hipLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src,
+                           it);
+    else
+        hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src, it);
 }
 
 }  // namespace

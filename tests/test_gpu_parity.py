@@ -146,12 +146,16 @@ def test_cuboid_rain_full_size(orc):
     sc = scenes.cuboid_rain(0)
     states = _oracle_states(orc, sc, [0, 12])
     for f, (x, v) in states.items():
-        check_substep(orc, sc, x, v, label="cuboid_rain frame %d" % f)
+        s = _gpu_solver(sc)
+        assert s.info().iteration_kernel == 0      # the grid fits the GPU at once
+        check_substep(orc, sc, x, v, solver=s, label="cuboid_rain frame %d" % f)
 
 
 def test_dense_pile_full_size(orc):
     sc = scenes.dense_pile(0, gap_frac=-0.05)
-    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, label="dense_pile 20k")
+    s = _gpu_solver(sc)
+    assert s.info().iteration_kernel == 1      # 20k bodies oversubscribe the GPU
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, solver=s, label="dense_pile 20k")
     assert c >= 1
 
 
