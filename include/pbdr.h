@@ -216,6 +216,17 @@ pbdr_status pbdr_scene_read_debug(pbdr_scene* scene, int32_t what, void* dst_hos
  * Requires at least one completed substep (else PBDR_ERR_STATE). */
 pbdr_status pbdr_scene_launch_iterations(pbdr_scene* scene, int32_t n_launches);
 
+/* Measurement aid: as pbdr_scene_launch_iterations, with a pair of HIP events
+ * bound to each launch's own dispatch (begin and end timestamps of the kernel,
+ * no marker packets in between); waits for the last launch and writes the
+ * duration of launch i, in microseconds, to out_us[i] (host array of
+ * n_launches floats, owned by the caller).  1 <= n_launches <=
+ * PBDR_MAX_TIMED_LAUNCHES, else PBDR_ERR_INVALID_ARG; PBDR_ERR_STATE before the
+ * first substep; PBDR_ERR_DEVICE if an event or a launch fails.  Blocks the
+ * calling thread until the launches have finished. */
+#define PBDR_MAX_TIMED_LAUNCHES 4096
+pbdr_status pbdr_scene_time_iterations(pbdr_scene* scene, int32_t n_launches, float* out_us);
+
 /* Resolved parameters and sizes. */
 pbdr_status pbdr_scene_info_get(const pbdr_scene* scene, pbdr_scene_info* out);
 

@@ -23,12 +23,14 @@ PP_AVG_MAX, PP_AVG_OWN, PP_AVG_NONE = 0, 1 << 8, 2 << 8
 DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3, 4, 5
 DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8
 MAX_PLANES = 8
+MAX_TIMED_LAUNCHES = 4096
 
 EXPORTED = [
     "pbdr_abi_version", "pbdr_last_error", "pbdr_scene_bytes", "pbdr_scene_create",
     "pbdr_scene_set_accel", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
     "pbdr_scene_read_state", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
-    "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations", "pbdr_scene_destroy",
+    "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations",
+    "pbdr_scene_time_iterations", "pbdr_scene_destroy",
     "pbdr_pool_bytes", "pbdr_pool_create", "pbdr_pool_add", "pbdr_pool_remove", "pbdr_pool_step",
     "pbdr_pool_step_slots", "pbdr_pool_substep", "pbdr_pool_read_state", "pbdr_pool_read_debug",
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
@@ -145,6 +147,7 @@ def load_library(path: str = LIB_PATH):
                        ("pbdr_scene_neighbour_stats", [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
                        ("pbdr_scene_read_debug", [vp, i32, vp]),
                        ("pbdr_scene_launch_iterations", [vp, i32]),
+                       ("pbdr_scene_time_iterations", [vp, i32, vp]),
                        ("pbdr_scene_info_get", [vp, ctypes.POINTER(SceneInfo)])]:
         fn = getattr(lib, name)
         fn.restype = i32
@@ -324,6 +327,13 @@ class Solver:
     def launch_iterations(self, n_launches: int):
         """Measurement aid: n back-to-back launches of the iteration kernel alone."""
         _check(self._lib.pbdr_scene_launch_iterations(self._h, n_launches))
+
+    def time_iterations(self, n_launches: int) -> np.ndarray:
+        """Measurement aid: n launches of the iteration kernel, each timed by HIP
+        events bound to its own dispatch; returns the durations in microseconds."""
+        out = np.zeros(n_launches, dtype=np.float32)
+        _check(self._lib.pbdr_scene_time_iterations(self._h, n_launches, out.ctypes.data))
+        return out
 
     def info(self) -> SceneInfo:
         out = SceneInfo()

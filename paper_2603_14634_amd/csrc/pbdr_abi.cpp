@@ -531,6 +531,38 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     return PBDR_OK;
 }
 
+pbdr_status pbdr_scene_time_iterations(pbdr_scene* s, int32_t n_launches, float* out_us)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    if (n_launches < 1 || n_launches > PBDR_MAX_TIMED_LAUNCHES)
+        return fail(PBDR_ERR_INVALID_ARG, "n_launches must be in [1, %d]", PBDR_MAX_TIMED_LAUNCHES);
+    if (!out_us) return fail(PBDR_ERR_INVALID_ARG, "out_us must not be NULL");
+    if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
+    if (s->dev.n == 0) {
+        for (int32_t i = 0; i < n_launches; ++i) out_us[i] = 0.0f;
+        return PBDR_OK;
+    }
+    std::vector<hipEvent_t> ev(2 * (size_t)n_launches, nullptr);
+    auto release = [&]() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    };
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess)
+        e = pbdr::enqueue_iterations_timed(s->dev, s->consts, n_launches, s->stream, ev.data(),
+                                           ev.data() + n_launches);
+    if (e == hipSuccess) e = hipEventSynchronize(ev.back());
+    for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[(size_t)i], ev[(size_t)n_launches + i]);
+        out_us[i] = 1e3f * ms;
+    }
+    release();
+    if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "timed iteration launches failed: %s", hipGetErrorString(e));
+    return PBDR_OK;
+}
+
 pbdr_status pbdr_scene_substep(pbdr_scene* s, int32_t n_substeps)
 {
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");

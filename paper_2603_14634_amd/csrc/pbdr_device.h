@@ -101,6 +101,10 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
 // but the first continue from the rotation of the launch before.
 hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream);
 
+// As enqueue_iterations, launch `it` bound to the events t0[it] and t1[it].
+hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int count, hipStream_t stream,
+                                    const hipEvent_t* t0, const hipEvent_t* t1);
+
 // Writes the canonical (key, id) order of the last substep into `sorted`.
 hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream);
 

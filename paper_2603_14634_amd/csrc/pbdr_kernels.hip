@@ -40,6 +40,8 @@
 #include "pbdr_device.h"
 #include "pbdr_math.h"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 
 namespace pbdr {
@@ -666,6 +668,19 @@ void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStr
         hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src, it);
 }
 
+// The same launch with a pair of events bound to the dispatch itself: their
+// timestamps are the kernel's own begin and end, with no marker packets between.
+void launch_iterate_timed(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream, hipEvent_t t0,
+                          hipEvent_t t1)
+{
+    if (s.dense_iterate)
+        hipExtLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1,
+                              0, s, c, src, it);
+    else
+        hipExtLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1, 0,
+                              s, c, src, it);
+}
+
 }  // namespace
 
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
@@ -695,6 +710,18 @@ hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hi
     int src = 0;
     for (int it = 0; it < count; ++it) {
         launch_iterate(s, c, src, it, stream);
+        src ^= 1;
+    }
+    return hipGetLastError();
+}
+
+hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int count, hipStream_t stream,
+                                    const hipEvent_t* t0, const hipEvent_t* t1)
+{
+    if (s.n <= 0 || count <= 0) return hipSuccess;
+    int src = 0;
+    for (int it = 0; it < count; ++it) {
+        launch_iterate_timed(s, c, src, it, stream, t0[it], t1[it]);
         src ^= 1;
     }
     return hipGetLastError();

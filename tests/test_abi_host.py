@@ -37,6 +37,8 @@ def test_header_compiles_as_c_and_struct_layout_matches_binding(tmp_path):
 #include <stddef.h>
 #include "pbdr.h"
 int main(void) {
+  printf("%zu %zu %d %d\n", offsetof(pbdr_scene_info, iteration_kernel), offsetof(pbdr_scene_info, max_body_particles),
+         PBDR_MAX_TIMED_LAUNCHES, PBDR_MAX_PLANES);
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pbdr_params), offsetof(pbdr_params, planes),
          offsetof(pbdr_params, flags), sizeof(pbdr_scene_desc), sizeof(pbdr_scene_info),
          offsetof(pbdr_scene_info, workspace_bytes), sizeof(pbdr_pool_scene_desc),
@@ -49,7 +51,8 @@ int main(void) {
                     "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     got = [int(t) for t in out]
-    want = [ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
+    want = [B.SceneInfo.iteration_kernel.offset, B.SceneInfo.max_body_particles.offset, B.MAX_TIMED_LAUNCHES,
+            B.MAX_PLANES, ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
             ctypes.sizeof(B.SceneInfo), B.SceneInfo.workspace_bytes.offset, ctypes.sizeof(B.PoolSceneDesc),
             B.PoolSceneDesc.gravity.offset, ctypes.sizeof(B.PoolInfo), B.PoolInfo.workspace_bytes.offset]
     assert got == want
@@ -155,6 +158,7 @@ def test_null_handles_are_rejected():
     assert lib.pbdr_scene_substep(None, 1) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_read_state(None, None, None, 0) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_launch_iterations(None, 1) == B.ERR_INVALID_ARG
+    assert lib.pbdr_scene_time_iterations(None, 1, None) == B.ERR_INVALID_ARG
     lib.pbdr_scene_destroy(None)
 
 

@@ -266,6 +266,27 @@ def test_bitwise_deterministic_and_graph_equals_direct_launches():
         np.testing.assert_array_equal(v, runs[0][1])
 
 
+def test_timed_iteration_launches_leave_the_state_and_next_substep_unchanged():
+    sc = scenes.drop_cubes(1)
+    runs = []
+    for timed in (False, True):
+        s = B.Solver(B.params_for(sc, flags=B.FLAG_NO_GRAPH), sc.x, sc.v, sc.mass, sc.body_start)
+        s.step(3)
+        before = s.read_state()
+        if timed:
+            us = s.time_iterations(7)
+            assert us.shape == (7,) and np.all(us > 0.0) and np.all(np.isfinite(us))
+            after = s.read_state()
+            np.testing.assert_array_equal(after[0], before[0])
+            np.testing.assert_array_equal(after[1], before[1])
+        s.step(2)
+        runs.append(s.read_state())
+    np.testing.assert_array_equal(runs[1][0], runs[0][0])
+    np.testing.assert_array_equal(runs[1][1], runs[0][1])
+    with pytest.raises(B.PbdrError):
+        s.time_iterations(B.MAX_TIMED_LAUNCHES + 1)
+
+
 def test_checkpoint_resume_is_bit_identical():
     sc = scenes.drop_cubes(2)
     a = B.Solver(B.params_for(sc), sc.x, sc.v, sc.mass, sc.body_start)
