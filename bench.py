@@ -207,27 +207,40 @@ def bench_pool(args):
 def bench_serving(args):
     from paper_2603_14634_amd import binding as B
     from paper_2603_14634_amd import scenes
-    from paper_2603_14634_amd.serving import PoolBackend, ServingEngine, pool_for_budget
+    from paper_2603_14634_amd.serving import HybridBackend, PoolBackend, ServingEngine, pool_for_budget
 
     reqs = scenes.serving_trace(args.seed, rate_hz=args.rate, duration_s=args.window)
     params = B.params_for(reqs[0].scene)
-    pool = pool_for_budget(params, args.budget_gib << 30, max_scenes=4096)
-    eng = ServingEngine(PoolBackend(pool), frames_per_tick=args.frames_per_tick, keep_results=False)
+    single = args.single_gib << 30 if args.serving_backend == "hybrid" else 0
+    pool = pool_for_budget(params, (args.budget_gib << 30) - single, max_scenes=4096)
+    backend = (HybridBackend(pool, single, single_lanes=args.single_lanes) if args.serving_backend == "hybrid"
+               else PoolBackend(pool))
+    eng = ServingEngine(backend, frames_per_tick=args.frames_per_tick, keep_results=False)
     # warm-up: one tiny request compiles nothing new but touches every path once
     eng.run([scenes.Request(0.0, reqs[0].scene, 1, -1)])
-    print("[bench] serving: %d requests at %.0f/s over %.2f s, pool of %d particles (%.1f GiB)"
-          % (len(reqs), args.rate, args.window, pool.info().max_particles, pool.info().workspace_bytes / 2 ** 30),
-          file=sys.stderr, flush=True)
+    print("[bench] serving: %d requests at %.0f/s over %.2f s, pool of %d particles (%.1f GiB), %s backend"
+          % (len(reqs), args.rate, args.window, pool.info().max_particles, pool.info().workspace_bytes / 2 ** 30,
+             args.serving_backend), file=sys.stderr, flush=True)
     out = eng.run(reqs)
     print("[bench] served %d in %.2f s: p50 %.1f ms, p99 %.1f ms, %.4g particle-substeps/s, peak %d resident"
           % (out["completed"], out["makespan_s"], out["p50_ms"], out["p99_ms"], out["throughput"],
              out["peak_active"]), file=sys.stderr, flush=True)
+    # latency by where the requests ran: the pool's register-resident classes,
+    # or the large-scene route (single scenes, or the pool's large-scene kernel)
+    by_id = {r.request_id: r for r in reqs}
+    split = {}
+    for o in out["outcomes"]:
+        big = pool.class_for(by_id[o.request_id].scene) == B.POOL_CLASSES
+        split.setdefault("large" if big else "small", []).append(o.latency_s * 1e3)
+    split = {k: {"requests": len(v), "p50": round(float(np.percentile(v, 50)), 2),
+                 "p99": round(float(np.percentile(v, 99)), 2)} for k, v in sorted(split.items())}
+    print("[bench] latency by route: %s" % split, file=sys.stderr, flush=True)
     bpps = pool_bytes_per_particle_substep(reqs[0].scene.iterations, 0.0)
     busy_rate = out["particle_substeps"] / out["busy_s"] if out["busy_s"] > 0 else 0.0
     achieved = busy_rate * bpps / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_pool / k_pool_big over the ticks (time the GPU was stepping)",
+            "kernel": "k_pool and the single-scene kernels over the ticks (time the GPU was stepping)",
             "bytes_per_particle_substep": bpps}
     cpu = None if args.no_cpu_baseline else cpu_baseline_scenes([r.scene for r in reqs], args.cpu_budget_s,
                                                                 "the serving trace")
@@ -237,11 +250,13 @@ def bench_serving(args):
         "steps": out["ticks"], "warmup": 1, "ms_per_step": round(out["busy_s"] * 1e3 / max(out["ticks"], 1), 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "latency_ms": {"p50": round(out["p50_ms"], 2), "p99": round(out["p99_ms"], 2),
-                       "mean_queue_wait": round(out["mean_wait_ms"], 2)},
+                       "mean_queue_wait": round(out["mean_wait_ms"], 2), "by_route": split},
         "config": {"workload": "serving", "rate_hz": args.rate, "window_s": args.window, "requests": len(reqs),
                    "completed": out["completed"], "rejected": len(out["rejected"]),
                    "peak_resident": out["peak_active"], "frames_per_tick": args.frames_per_tick,
-                   "hbm_budget_gib": args.budget_gib, "makespan_s": round(out["makespan_s"], 3), "seed": args.seed},
+                   "hbm_budget_gib": args.budget_gib, "backend": args.serving_backend,
+                   "single_scene_gib": args.single_gib if args.serving_backend == "hybrid" else 0,
+                   "makespan_s": round(out["makespan_s"], 3), "seed": args.seed},
         "roofline": roof, "cpu_baseline": cpu,
     }
     pool.close()
@@ -266,14 +281,18 @@ def main():
     ap.add_argument("--window", type=float, default=1.0, help="serving: seconds of arrivals")
     ap.add_argument("--budget-gib", type=int, default=16, help="serving: HBM budget of the scene pool")
     ap.add_argument("--frames-per-tick", type=int, default=2, help="serving: frames per scheduling tick")
+    ap.add_argument("--serving-backend", choices=("hybrid", "pool"), default="hybrid",
+                    help="serving: large scenes on the single-scene path (hybrid) or in the pool's large-scene kernel")
+    ap.add_argument("--single-gib", type=int, default=4, help="serving: HBM budget of the single-scene workspaces")
+    ap.add_argument("--single-lanes", type=int, default=4, help="serving: streams for single scenes")
     args = ap.parse_args()
     if args.workload == "serving":
         # the serving lanes and the pool's side-by-side classes use about a dozen
         # streams; give each its own hardware queue (read when HIP starts)
         os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     if args.gpus != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
-              "(scenes shard across GPUs without communication; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only; runs on several GPUs are not supported "
+              "(independent scenes would shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 
     import torch

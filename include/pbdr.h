@@ -161,6 +161,13 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
  * every substep until replaced, or NULL for none.  The caller keeps it alive. */
 pbdr_status pbdr_scene_set_accel(pbdr_scene* scene, const float* accel_dev);
 
+/* Moves the scene's work to another stream (hipStream_t or NULL for the
+ * default stream): waits for the work already enqueued on the current one,
+ * then enqueues every later call on hip_stream.  Lets a scene be created on a
+ * stream of its own (creation synchronises that stream) and then join a
+ * stream that other work keeps busy.  PBDR_ERR_DEVICE if the wait fails. */
+pbdr_status pbdr_scene_set_stream(pbdr_scene* scene, void* hip_stream);
+
 /* Advances n_frames frames of `substeps` substeps each (asynchronous). */
 pbdr_status pbdr_scene_step(pbdr_scene* scene, int32_t n_frames);
 
@@ -322,6 +329,13 @@ pbdr_status pbdr_pool_step_slots_on(pbdr_pool* pool, int32_t lane, void* hip_str
  * register-resident size classes, PBDR_POOL_CLASSES for the large-scene
  * kernel. */
 pbdr_status pbdr_pool_slot_class(const pbdr_pool* pool, int32_t slot, int32_t* cls);
+
+/* Launch class, as pbdr_pool_slot_class reports it, that a scene of this shape
+ * would get in this pool, without adding it (host only: body_start [B+1] in
+ * host memory).  PBDR_ERR_INVALID_ARG if the shape is malformed or could
+ * never be added to this pool. */
+pbdr_status pbdr_pool_class_for(const pbdr_pool* pool, int32_t n_particles, int32_t n_bodies,
+                                const int32_t* body_start, int32_t* cls);
 
 /* Advances every resident scene by n_substeps substeps (for substep checks). */
 pbdr_status pbdr_pool_substep(pbdr_pool* pool, int32_t n_substeps);

@@ -27,7 +27,7 @@ MAX_TIMED_LAUNCHES = 4096
 
 EXPORTED = [
     "pbdr_abi_version", "pbdr_last_error", "pbdr_scene_bytes", "pbdr_scene_create",
-    "pbdr_scene_set_accel", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
+    "pbdr_scene_set_accel", "pbdr_scene_set_stream", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
     "pbdr_scene_read_state", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
     "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations",
     "pbdr_scene_time_iterations", "pbdr_scene_destroy",
@@ -35,6 +35,7 @@ EXPORTED = [
     "pbdr_pool_step_slots", "pbdr_pool_substep", "pbdr_pool_read_state", "pbdr_pool_read_debug",
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
     "pbdr_pool_info_get", "pbdr_pool_destroy", "pbdr_pool_step_slots_on", "pbdr_pool_slot_class",
+    "pbdr_pool_class_for",
 ]
 POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES, POOL_LANES = 65535, 256, 7, 4
 
@@ -140,7 +141,8 @@ def load_library(path: str = LIB_PATH):
     lib.pbdr_scene_create.restype = i32
     lib.pbdr_scene_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(SceneDesc), vp, sz, vp,
                                       ctypes.POINTER(vp)]
-    for name, args in [("pbdr_scene_set_accel", [vp, vp]), ("pbdr_scene_step", [vp, i32]),
+    for name, args in [("pbdr_scene_set_accel", [vp, vp]), ("pbdr_scene_set_stream", [vp, vp]),
+                       ("pbdr_scene_step", [vp, i32]),
                        ("pbdr_scene_substep", [vp, i32]), ("pbdr_scene_set_state", [vp, vp, vp, i32]),
                        ("pbdr_scene_read_state", [vp, vp, vp, i32]), ("pbdr_scene_read_rest", [vp, vp]),
                        ("pbdr_scene_check", [vp, ctypes.POINTER(i32)]),
@@ -167,7 +169,8 @@ def load_library(path: str = LIB_PATH):
                        ("pbdr_pool_autotune", [vp, i32, i32, vp]),
                        ("pbdr_pool_info_get", [vp, ctypes.POINTER(PoolInfo)]),
                        ("pbdr_pool_step_slots_on", [vp, i32, vp, i32, vp, vp]),
-                       ("pbdr_pool_slot_class", [vp, i32, pi32])]:
+                       ("pbdr_pool_slot_class", [vp, i32, pi32]),
+                       ("pbdr_pool_class_for", [vp, i32, i32, vp, pi32])]:
         fn = getattr(lib, name)
         fn.restype = i32
         fn.argtypes = args
@@ -274,6 +277,11 @@ class Solver:
 
     def substep(self, n_substeps: int = 1):
         _check(self._lib.pbdr_scene_substep(self._h, n_substeps))
+
+    def set_stream(self, stream):
+        """Moves later work to ``stream`` (a torch stream) after the current one drains."""
+        _check(self._lib.pbdr_scene_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def set_accel(self, accel):
         """accel: torch float32 device tensor [3, N] (kept alive here) or None."""
@@ -441,6 +449,14 @@ class Pool:
     def slot_class(self, slot: int) -> int:
         c = ctypes.c_int32()
         _check(self._lib.pbdr_pool_slot_class(self._h, slot, ctypes.byref(c)))
+        return int(c.value)
+
+    def class_for(self, scene) -> int:
+        """Launch class the scene would get here (POOL_CLASSES = the large-scene kernel)."""
+        bs = np.ascontiguousarray(scene.body_start, dtype=np.int32)
+        c = ctypes.c_int32()
+        _check(self._lib.pbdr_pool_class_for(self._h, int(scene.n), int(bs.shape[0] - 1), bs.ctypes.data,
+                                             ctypes.byref(c)))
         return int(c.value)
 
     def substep(self, n_substeps: int = 1):

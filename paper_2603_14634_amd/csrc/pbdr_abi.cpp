@@ -496,6 +496,14 @@ pbdr_status pbdr_scene_set_accel(pbdr_scene* s, const float* accel_dev)
     return PBDR_OK;
 }
 
+pbdr_status pbdr_scene_set_stream(pbdr_scene* s, void* hip_stream)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->stream = (hipStream_t)hip_stream;
+    return PBDR_OK;
+}
+
 pbdr_status pbdr_scene_step(pbdr_scene* s, int32_t n_frames)
 {
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");

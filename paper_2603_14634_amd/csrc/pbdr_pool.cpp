@@ -655,6 +655,33 @@ pbdr_status pbdr_pool_slot_class(const pbdr_pool* p, int32_t slot, int32_t* cls)
     return PBDR_OK;
 }
 
+pbdr_status pbdr_pool_class_for(const pbdr_pool* p, int32_t n_particles, int32_t n_bodies, const int32_t* body_start,
+                                int32_t* cls)
+{
+    if (!p) return fail(PBDR_ERR_INVALID_ARG, "pool is NULL");
+    if (!body_start || !cls) return fail(PBDR_ERR_INVALID_ARG, "body_start and cls must not be NULL");
+    *cls = -1;
+    if (n_particles < 1 || n_bodies < 1 || n_bodies > n_particles)
+        return fail(PBDR_ERR_INVALID_ARG, "a scene needs n_particles >= n_bodies >= 1, got %d and %d", n_particles,
+                    n_bodies);
+    if (body_start[0] != 0 || body_start[n_bodies] != n_particles)
+        return fail(PBDR_ERR_INVALID_ARG, "body_start must begin at 0 and end at n_particles");
+    int64_t lanes_slots = 0;
+    for (int32_t b = 0; b < n_bodies; ++b) {
+        const int32_t len = body_start[b + 1] - body_start[b];
+        if (len < 1) return fail(PBDR_ERR_INVALID_ARG, "body %d is empty or body_start decreases", b);
+        lanes_slots += (len + 63) / 64;
+    }
+    const int c = class_of(n_particles, n_bodies, (int32_t)std::min<int64_t>(lanes_slots, INT32_MAX), p->max_cls);
+    const int32_t nmax = p->big_ok ? pbdr::kPoolBigMaxParticles : pbdr::pool_class_bound(p->max_cls);
+    const int32_t bmax = p->big_ok ? pbdr::kPoolBigMaxBodies : pbdr::kPoolMaxBodies;
+    if ((c == kBig && !p->big_ok) || n_particles > nmax || n_bodies > bmax)
+        return fail(PBDR_ERR_INVALID_ARG, "a scene of %d particles and %d bodies does not fit this pool", n_particles,
+                    n_bodies);
+    *cls = c;
+    return PBDR_OK;
+}
+
 pbdr_status pbdr_pool_substep(pbdr_pool* p, int32_t n_substeps)
 {
     if (!p) return fail(PBDR_ERR_INVALID_ARG, "pool is NULL");
