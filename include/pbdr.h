@@ -182,6 +182,19 @@ pbdr_status pbdr_scene_set_state(pbdr_scene* scene, const float* x, const float*
  * synchronises; returns any latched device condition. */
 pbdr_status pbdr_scene_read_state(pbdr_scene* scene, float* x, float* v, int32_t on_device);
 
+/* Per-body state of the current x, v, to HOST arrays (any may be NULL; B =
+ * n_bodies), computed on the device with FP64 sums over each body:
+ *   com  [B][3]  centre of mass c = sum m x / M;
+ *   rot9 [B][9]  row-major rotation of shape matching for this pose (Sec.
+ *                III-C): the proper rotation maximising tr(R^T A) with
+ *                A = sum m (x - c) q^T against the rest offsets q, so that
+ *                x - c ~ R q (evaluated in FP32 from the normalised A;
+ *                identity for A = 0, unspecified for bodies on a line);
+ *   P    [B][3]  linear momentum sum m v;
+ *   L    [B][3]  angular momentum about the centre, sum m (x - c) x v.
+ * Synchronises; returns any latched device condition. */
+pbdr_status pbdr_scene_read_bodies(pbdr_scene* scene, double* com, double* rot9, double* P, double* L);
+
 /* Rest offsets q [3][N] (host), for checkpoints: a scene created from a saved
  * state with these offsets continues identically. */
 pbdr_status pbdr_scene_read_rest(pbdr_scene* scene, float* rest_q);

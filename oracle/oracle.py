@@ -150,6 +150,16 @@ def substep(p: OrcParams, rest: Body, x: np.ndarray, v: np.ndarray, accel=None, 
     return xx, vv, int(mx)
 
 
+def body_state(rest: Body, x: np.ndarray, v: np.ndarray):
+    """Per-body (com [B,3], R [B,3,3], P [B,3], L [B,3]) of the state (x, v), FP64."""
+    lib = load()
+    B = rest.nb
+    com, rot, P, L = np.zeros((B, 3)), np.zeros((B, 3, 3)), np.zeros((B, 3)), np.zeros((B, 3))
+    lib.orc_body_state(ctypes.c_int32(rest.n), ctypes.c_int32(B), _p(rest.body_start), _p(rest.mass),
+                       _p(rest.q), _p(_f64(x)), _p(_f64(v)), _p(com), _p(rot), _p(P), _p(L))
+    return com, rot, P, L
+
+
 def predict32(p: OrcParams, x, v, accel=None) -> np.ndarray:
     lib = load()
     x32, v32 = _f32(x), _f32(v)

@@ -690,3 +690,41 @@ int32_t orc_run(const orc_params* p, int32_t n, int32_t nb, const int32_t* body_
     }
     return mx;
 }
+
+/* Per-body state of (x, v): centre of mass, the rotation of shape matching for
+ * this pose (Sec. III-C: the least-squares rotation from the rest offsets q,
+ * i.e. the polar rotation of A = sum m (x - c) q^T), linear momentum and
+ * angular momentum about the centre (the quantities of Sec. III-C, Eqs.
+ * (4)-(5)).  Plain definitions, FP64, ascending particle order. */
+void orc_body_state(int32_t n, int32_t nb, const int32_t* body_start, const double* mass, const double* q,
+                    const double* x, const double* v, double* com, double* rot9, double* P, double* L)
+{
+    for (int32_t b = 0; b < nb; ++b) {
+        double M = 0.0, c[3] = {0.0, 0.0, 0.0};
+        for (int32_t i = body_start[b]; i < body_start[b + 1]; ++i) {
+            M += mass[i];
+            c[0] += mass[i] * X_(x, n, i);
+            c[1] += mass[i] * Y_(x, n, i);
+            c[2] += mass[i] * Z_(x, n, i);
+        }
+        for (int a = 0; a < 3; ++a) c[a] /= M;
+        double A[9] = {0}, Pb[3] = {0}, Lb[3] = {0};
+        for (int32_t i = body_start[b]; i < body_start[b + 1]; ++i) {
+            const double r[3] = {X_(x, n, i) - c[0], Y_(x, n, i) - c[1], Z_(x, n, i) - c[2]};
+            const double qi[3] = {X_(q, n, i), Y_(q, n, i), Z_(q, n, i)};
+            const double vi[3] = {X_(v, n, i), Y_(v, n, i), Z_(v, n, i)};
+            for (int a = 0; a < 3; ++a)
+                for (int k = 0; k < 3; ++k) A[3 * a + k] += mass[i] * r[a] * qi[k];
+            for (int a = 0; a < 3; ++a) Pb[a] += mass[i] * vi[a];
+            Lb[0] += mass[i] * (r[1] * vi[2] - r[2] * vi[1]);
+            Lb[1] += mass[i] * (r[2] * vi[0] - r[0] * vi[2]);
+            Lb[2] += mass[i] * (r[0] * vi[1] - r[1] * vi[0]);
+        }
+        for (int a = 0; a < 3; ++a) {
+            com[3 * (size_t)b + a] = c[a];
+            P[3 * (size_t)b + a] = Pb[a];
+            L[3 * (size_t)b + a] = Lb[a];
+        }
+        orc_polar(A, rot9 + 9 * (size_t)b);
+    }
+}

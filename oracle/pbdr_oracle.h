@@ -83,6 +83,12 @@ int32_t orc_substep(const orc_params* p, int32_t n, int32_t nb, const int32_t* b
                     const double* mass, const double* body_mass, const double* q,
                     const double* accel, double* x, double* v);
 
+/* Per-body state of (x, v) (SoA [3][n]): centre of mass com [nb][3], rotation
+ * of shape matching rot9 [nb][9] (row-major, x - c ~ R q), linear momentum
+ * P [nb][3] and angular momentum about the centre L [nb][3]. */
+void orc_body_state(int32_t n, int32_t nb, const int32_t* body_start, const double* mass, const double* q,
+                    const double* x, const double* v, double* com, double* rot9, double* P, double* L);
+
 /* n_substeps consecutive substeps; returns the largest neighbour count seen. */
 int32_t orc_run(const orc_params* p, int32_t n, int32_t nb, const int32_t* body_start,
                 const double* mass, const double* body_mass, const double* q,

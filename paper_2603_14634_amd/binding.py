@@ -28,7 +28,7 @@ MAX_TIMED_LAUNCHES = 4096
 EXPORTED = [
     "pbdr_abi_version", "pbdr_last_error", "pbdr_scene_bytes", "pbdr_scene_create",
     "pbdr_scene_set_accel", "pbdr_scene_set_stream", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
-    "pbdr_scene_read_state", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
+    "pbdr_scene_read_state", "pbdr_scene_read_bodies", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
     "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations",
     "pbdr_scene_time_iterations", "pbdr_scene_destroy",
     "pbdr_pool_bytes", "pbdr_pool_create", "pbdr_pool_add", "pbdr_pool_remove", "pbdr_pool_step",
@@ -145,6 +145,7 @@ def load_library(path: str = LIB_PATH):
                        ("pbdr_scene_step", [vp, i32]),
                        ("pbdr_scene_substep", [vp, i32]), ("pbdr_scene_set_state", [vp, vp, vp, i32]),
                        ("pbdr_scene_read_state", [vp, vp, vp, i32]), ("pbdr_scene_read_rest", [vp, vp]),
+                       ("pbdr_scene_read_bodies", [vp, vp, vp, vp, vp]),
                        ("pbdr_scene_check", [vp, ctypes.POINTER(i32)]),
                        ("pbdr_scene_neighbour_stats", [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
                        ("pbdr_scene_read_debug", [vp, i32, vp]),
@@ -312,6 +313,14 @@ class Solver:
     def read_state_device(self, x, v):
         _check(self._lib.pbdr_scene_read_state(self._h, ctypes.c_void_p(x.data_ptr()),
                                                ctypes.c_void_p(v.data_ptr()), 1))
+
+    def read_bodies(self):
+        """Per-body (com [B,3], R [B,3,3], P [B,3], L [B,3]) of the current state, FP64."""
+        B = self.n_bodies
+        com, rot, P, L = np.zeros((B, 3)), np.zeros((B, 3, 3)), np.zeros((B, 3)), np.zeros((B, 3))
+        _check(self._lib.pbdr_scene_read_bodies(self._h, com.ctypes.data, rot.ctypes.data, P.ctypes.data,
+                                                L.ctypes.data))
+        return com, rot, P, L
 
     def read_rest(self):
         q = np.empty((3, self.n), dtype=np.float32)

@@ -15,6 +15,7 @@
 
 #include "pbdr_device.h"
 #include "pbdr_host.h"
+#include "pbdr_state.h"
 
 namespace pbdr {
 namespace host {
@@ -91,7 +92,7 @@ using pbdr::host::g_err;
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
         sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
-        body_wave0, block_body, body_mq, total;
+        body_wave0, block_body, body_mq, body_out, total;
 };
 
 // Upper bound on the padded wave count of the iteration kernel's body packing:
@@ -143,6 +144,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.body_wave0 = take(4 * B);
     L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 1));
     L.body_mq = take(12 * B);
+    L.body_out = take(18 * sizeof(double) * B);
     L.total = off;
     return L;
 }
@@ -605,6 +607,30 @@ pbdr_status pbdr_scene_read_state(pbdr_scene* s, float* x, float* v, int32_t on_
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (bytes && x) HIP_TRY(hipMemcpyAsync(x, s->ws + s->lay.x, bytes, kind, s->stream));
     if (bytes && v) HIP_TRY(hipMemcpyAsync(v, s->ws + s->lay.v, bytes, kind, s->stream));
+    return latched(s);
+}
+
+pbdr_status pbdr_scene_read_bodies(pbdr_scene* s, double* com, double* rot9, double* P, double* L)
+{
+    if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
+    const size_t B = (size_t)s->dev.nb;
+    if (B == 0) return latched(s);
+    double* dev_out = reinterpret_cast<double*>(s->ws + s->lay.body_out);
+    hipError_t e = pbdr::enqueue_body_state(s->dev, dev_out, s->stream);
+    if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    std::vector<double> h(18 * B);
+    HIP_TRY(hipMemcpyAsync(h.data(), dev_out, h.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (size_t b = 0; b < B; ++b) {
+        const double* o = h.data() + 18 * b;
+        for (int k = 0; k < 3; ++k) {
+            if (com) com[3 * b + k] = o[k];
+            if (P) P[3 * b + k] = o[12 + k];
+            if (L) L[3 * b + k] = o[15 + k];
+        }
+        if (rot9)
+            for (int k = 0; k < 9; ++k) rot9[9 * b + k] = o[3 + k];
+    }
     return latched(s);
 }
 

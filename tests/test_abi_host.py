@@ -161,6 +161,7 @@ def test_null_handles_are_rejected():
     assert lib.pbdr_scene_time_iterations(None, 1, None) == B.ERR_INVALID_ARG
     assert lib.pbdr_pool_class_for(None, 1, 1, None, None) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_set_stream(None, None) == B.ERR_INVALID_ARG
+    assert lib.pbdr_scene_read_bodies(None, None, None, None, None) == B.ERR_INVALID_ARG
     lib.pbdr_scene_destroy(None)
 
 

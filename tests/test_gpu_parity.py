@@ -183,6 +183,50 @@ def test_empty_scene():
     s.step(3)
     x, v = s.read_state()
     assert x.shape == (3, 0)
+    com, rot, P, L = s.read_bodies()
+    assert com.shape == (0, 3) and rot.shape == (0, 3, 3)
+
+
+def test_read_bodies_matches_reference(orc):
+    # two states the reference produces: drop_cubes after 40 substeps, and
+    # every body of it moved rigidly (random rotation, translation, spin)
+    sc = scenes.drop_cubes(0)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    xo, vo, _ = orc.substep(_orc_params(orc, sc), rest, sc.x, sc.v, n_substeps=40)
+    rng = np.random.default_rng(5)
+    xr, vr = np.zeros_like(xo), np.zeros_like(vo)
+    rots = []
+    for b in range(sc.n_bodies):
+        sl = slice(sc.body_start[b], sc.body_start[b + 1])
+        R0 = scenes.random_rotation(rng)
+        r = R0 @ rest.q[:, sl]
+        xr[:, sl] = rng.uniform(-1.0, 1.0, size=(3, 1)) + r
+        vr[:, sl] = rng.normal(size=(3, 1)) + np.cross(rng.normal(size=3), r.T).T
+        rots.append(R0)
+    s = _gpu_solver(sc)
+    for label, (x, v) in (("after 40 substeps", (xo, vo)), ("rigid motions", (xr, vr))):
+        x32, v32 = x.astype(np.float32), v.astype(np.float32)
+        s.set_state(x32, v32)
+        got = s.read_bodies()
+        want = orc.body_state(rest, x32, v32)
+        print("[bodies] %s: %d bodies" % (label, sc.n_bodies), flush=True)
+        np.testing.assert_allclose(got[0], want[0], rtol=0, atol=1e-12)        # FP64 sums of the same FP32 state
+        np.testing.assert_allclose(got[1], want[1], rtol=0, atol=2e-5)         # rotation evaluated in FP32
+        # FP64 sums of FP32 products differ only in order: bound by the size of
+        # the terms, sum m |v| and sum m |x - c| |v|
+        m, xd, vd = sc.mass.astype(np.float64), x32.astype(np.float64), v32.astype(np.float64)
+        speed = np.linalg.norm(vd, axis=0)
+        for b in range(sc.n_bodies):
+            sl = slice(sc.body_start[b], sc.body_start[b + 1])
+            arm = np.linalg.norm(xd[:, sl] - want[0][b][:, None], axis=0)
+            np.testing.assert_allclose(got[2][b], want[2][b], rtol=0, atol=1e-13 * (m[sl] * speed[sl]).sum())
+            np.testing.assert_allclose(got[3][b], want[3][b], rtol=0,
+                                       atol=1e-13 * (m[sl] * arm * speed[sl]).sum())
+        for R in got[1]:
+            np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-5)
+            assert abs(np.linalg.det(R) - 1.0) < 1e-5
+    for b, R0 in enumerate(rots):
+        np.testing.assert_allclose(got[1][b], R0, atol=2e-5)
 
 
 @pytest.mark.parametrize("flags", [B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN, B.PP_AVG_NONE])

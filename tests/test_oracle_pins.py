@@ -192,6 +192,34 @@ def test_polar_recovers_the_rotation_of_a_rigid_motion(orc):
         np.testing.assert_allclose(orc.polar(A), R0, atol=1e-13)
 
 
+def test_body_state_of_rigid_motions(orc):
+    # x = t + R0 q, v = V + w x (R0 q) for every body: the centre is t, the
+    # rotation R0, P = M V and L = I w with I = sum m (|r|^2 1 - r r^T)
+    rng = np.random.default_rng(11)
+    parts = [scenes.lattice_box(3, 4, 5, 0.1), scenes.lattice_box(2, 2, 6, 0.1), scenes.lattice_box(4, 4, 4, 0.1)]
+    x0 = np.concatenate(parts, axis=1)
+    bs = np.concatenate([[0], np.cumsum([q.shape[1] for q in parts])]).astype(np.int32)
+    m = rng.uniform(0.5, 2.0, size=x0.shape[1])
+    rest = orc.Body(x0, m, bs)
+    x, v = np.zeros_like(x0), np.zeros_like(x0)
+    want = []
+    for b in range(3):
+        sl = slice(bs[b], bs[b + 1])
+        R0, t, V, w = scenes.random_rotation(rng), rng.normal(size=3), rng.normal(size=3), rng.normal(size=3)
+        r = R0 @ rest.q[:, sl]
+        x[:, sl] = t[:, None] + r
+        v[:, sl] = V[:, None] + np.cross(w, r.T).T
+        mb = m[sl]
+        inertia = sum(mi * (ri @ ri * np.eye(3) - np.outer(ri, ri)) for mi, ri in zip(mb, r.T))
+        want.append((t, R0, mb.sum() * V, inertia @ w))
+    com, rot, P, L = orc.body_state(rest, x, v)
+    for b, (t, R0, Pw, Lw) in enumerate(want):
+        np.testing.assert_allclose(com[b], t, atol=1e-13)
+        np.testing.assert_allclose(rot[b], R0, atol=1e-12)
+        np.testing.assert_allclose(P[b], Pw, rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(L[b], Lw, rtol=1e-11, atol=1e-12)
+
+
 def test_polar_matches_newton_polar_and_library_svd(orc):
     rng = np.random.default_rng(4)
     for _ in range(200):
