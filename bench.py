@@ -39,7 +39,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_14634_amd", "csrc", f)
                for f in ("pbdr_kernels.hip", "pbdr_math.h", "pbdr_device.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_iterate_cuboid_rain_1000_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def iterate_bytes_per_particle(kbar: float) -> float:
@@ -66,12 +66,13 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(n_launch_bytes: float):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on a different kernel source."""
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the iteration kernel on this workload from the
+    committed rocprofv3 counter summary, or None when there is none or it was
+    taken on a different kernel source."""
     try:
         vals = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(os.path.join(PROFILES, "k_iterate_%s_traffic.txt" % workload)) as f:
             for line in f:
                 if ":" in line:
                     k, v = line.split(":", 1)
@@ -187,7 +188,7 @@ def bench_pool(args):
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_pool (one workgroup per scene, all substeps of the call)",
-            "avg_launch_us": round(ms * 1e3, 1), "bytes_per_particle_substep": bpps,
+            "us_per_call": round(ms * 1e3 / args.steps, 1), "bytes_per_particle_substep": bpps,
             "note": "state stays on chip across iterations, so HBM carries far less than the algorithmic bytes"}
     cpu = None if args.no_cpu_baseline else cpu_baseline_scenes(batch, args.cpu_budget_s, "batch_4096")
     line = {
@@ -284,12 +285,16 @@ def main():
     ap.add_argument("--serving-backend", choices=("hybrid", "pool"), default="hybrid",
                     help="serving: large scenes on the single-scene path (hybrid) or in the pool's large-scene kernel")
     ap.add_argument("--single-gib", type=int, default=4, help="serving: HBM budget of the single-scene workspaces")
-    ap.add_argument("--single-lanes", type=int, default=4, help="serving: streams for single scenes")
+    ap.add_argument("--single-lanes", type=int, default=8, help="serving: streams for single scenes")
+    ap.add_argument("--settle", type=int, default=None,
+                    help="untimed frames before the warm-up (default: 240 for dense_pile_20k, so the pile has "
+                         "settled into contact, else 0)")
     args = ap.parse_args()
     if args.workload == "serving":
-        # the serving lanes and the pool's side-by-side classes use about a dozen
-        # streams; give each its own hardware queue (read when HIP starts)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+        # the serving lanes, the single-scene lanes and the pool's side-by-side
+        # classes use about 18 streams; give each its own hardware queue (read
+        # when HIP starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "24")
     if args.gpus != 1:
         print("bench.py measures one GPU only; runs on several GPUs are not supported "
               "(independent scenes would shard across GPUs without communication)", file=sys.stderr)
@@ -321,6 +326,10 @@ def main():
           flush=True)
     solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits)
     stream = solver.stream
+    settle = args.settle if args.settle is not None else (240 if args.workload == "dense_pile_20k" else 0)
+    if settle:
+        print("[bench] settling %d frames (untimed)" % settle, file=sys.stderr, flush=True)
+        solver.step(settle)
     solver.step(args.warmup)
     torch.cuda.synchronize()
     solver.check()
@@ -360,7 +369,7 @@ def main():
     interval_ms = k0.elapsed_time(k1) / n_it
     bytes_launch = sc.n * iterate_bytes_per_particle(kbar) + sc.n_bodies * iterate_bytes_per_body()
     achieved = bytes_launch / (it_ms / 1e3) / 1e9
-    traffic = measured_traffic(bytes_launch)
+    traffic = measured_traffic(sc.name)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_iterate (one Jacobi iteration, all bodies)",
@@ -389,7 +398,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "particles": sc.n, "bodies": sc.n_bodies, "substeps": sc.substeps,
                    "iterations": sc.iterations, "dt_frame": sc.dt_frame, "radius": sc.radius, "seed": args.seed,
-                   "max_neighbours": max_nbr, "accuracy": "per substep |dX - dX_ref| <= 1e-5 r (tests)"},
+                   "max_neighbours": max_nbr, "settled_frames": settle,
+                   "accuracy": "per substep |dX - dX_ref| <= 1e-5 r (tests)"},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
