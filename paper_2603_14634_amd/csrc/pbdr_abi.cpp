@@ -95,13 +95,17 @@ struct Layout {
         body_wave0, block_body, body_mq, body_out, total;
 };
 
-// Upper bound on the padded wave count of the iteration kernel's body packing:
-// each body needs ceil(n_b / 64) <= n_b / 64 + 1 waves; greedy packing into
-// workgroups of W waves wastes less than half of every closed workgroup, and
-// the last workgroup is padded by at most W - 1 waves.
+// Upper bound on the padded wave count of the iteration kernel's body packing
+// (both launches together): each body needs ceil(n_b / 64) <= n_b / 64 + 1
+// waves.  Greedy packing into workgroups of W waves wastes less than half of
+// every workgroup it closes for lack of room.  When bodies of more than 4
+// waves get their own launch, each of them (>= 5 waves) may sit alone in a
+// workgroup of at most 16 waves and force one early close (<= 3 waves) in
+// the 4-wave packing: at most 19 < 4 x 5 waves.  The last workgroup of each
+// launch is padded by at most W - 1 waves.
 size_t max_iteration_waves(int32_t n, int32_t nb)
 {
-    return 2 * ((size_t)n / 64 + (size_t)nb + 1) + pbdr::kMaxWaves;
+    return 4 * ((size_t)n / 64 + (size_t)nb + 2) + 2 * pbdr::kMaxWaves;
 }
 
 Layout make_layout(int32_t n, int32_t nb, int k, int cap)
@@ -142,7 +146,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.nbr_stats = take(sizeof(pbdr::NbrStats) * ((N + pbdr::kBlock - 1) / pbdr::kBlock));
     L.wave_body = take(4 * max_iteration_waves(n, nb));
     L.body_wave0 = take(4 * B);
-    L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 1));
+    L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 2));
     L.body_mq = take(12 * B);
     L.body_out = take(18 * sizeof(double) * B);
     L.total = off;
@@ -155,6 +159,8 @@ struct pbdr_scene {
     Resolved res;
     Layout lay;
     pbdr::Scene dev;
+    pbdr::Scene dev2;                    // second iteration launch (bodies of more than 4 waves) if split
+    bool split = false;
     pbdr::StepConsts consts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -173,6 +179,9 @@ namespace {
 // Frames per graph for long step() calls: replaying one graph per frame
 // leaves the GPU waiting on the host between graphs.
 constexpr int kGraphFrames = 8;
+
+// The second iteration launch of a split packing, or NULL.
+const pbdr::Scene* second_launch(const pbdr_scene* s) { return s->split ? &s->dev2 : nullptr; }
 
 void drop_graph(pbdr_scene* s)
 {
@@ -304,7 +313,8 @@ pbdr_status check_host_finite(const float* a, size_t count, const char* what)
 
 pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
 {
-    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, substeps_total, s->stream);
+    hipError_t e = pbdr::enqueue_substeps(s->dev, second_launch(s), s->consts, s->res.p.iterations, substeps_total,
+                                          s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     s->stepped = true;
     return PBDR_OK;
@@ -319,7 +329,8 @@ pbdr_status capture(pbdr_scene* s, int frames, hipGraph_t* graph, hipGraphExec_t
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     for (int f = 0; f < frames && e == hipSuccess; ++f)
-        e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->res.p.substeps, s->cap_stream);
+        e = pbdr::enqueue_substeps(s->dev, second_launch(s), s->consts, s->res.p.iterations, s->res.p.substeps,
+                                   s->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -399,44 +410,79 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     fill_consts(s);
 
     // iteration-kernel packing: each body takes ceil(n_b / 64) consecutive
-    // waves; bodies are packed greedily, in order, into workgroups of W waves
-    const int W = std::max(4, (max_body + 63) / 64);
-    std::vector<int32_t> wave_body, body_wave0((size_t)nb);
-    for (int32_t b = 0; b < nb; ++b) {
-        const int need = (desc->body_start[b + 1] - desc->body_start[b] + 63) / 64;
-        const int used = (int)(wave_body.size() % (size_t)W);
-        if (used + need > W) wave_body.resize(wave_body.size() + (size_t)(W - used), -1);
-        body_wave0[(size_t)b] = (int32_t)wave_body.size();
-        wave_body.resize(wave_body.size() + (size_t)need, b);
+    // waves; bodies are packed greedily, in order, into workgroups of W waves,
+    // and a workgroup holds consecutive bodies only (its body-lane slots are
+    // body ids from its first).  Returns the padded wave table and fills the
+    // first wave of every packed body and each workgroup's (first body, count).
+    auto pack = [&](int W, int min_need, int max_need, std::vector<int32_t>& waves, std::vector<int32_t>& blocks,
+                    std::vector<int32_t>& body_wave0) {
+        int32_t prev = -2;
+        for (int32_t b = 0; b < nb; ++b) {
+            const int need = (desc->body_start[b + 1] - desc->body_start[b] + 63) / 64;
+            if (need < min_need || need > max_need) continue;
+            const int used = (int)(waves.size() % (size_t)W);
+            if (used > 0 && (used + need > W || b != prev + 1))
+                waves.resize(waves.size() + (size_t)(W - used), -1);
+            body_wave0[(size_t)b] = (int32_t)waves.size();
+            waves.resize(waves.size() + (size_t)need, b);
+            prev = b;
+        }
+        if (waves.size() % (size_t)W) waves.resize(waves.size() + (size_t)W - waves.size() % (size_t)W, -1);
+        const size_t nblk = waves.size() / (size_t)W;
+        blocks.assign(2 * nblk, 0);
+        for (size_t blk = 0; blk < nblk; ++blk) {
+            int32_t first = -1, last = -1;
+            for (int w = 0; w < W; ++w) {
+                const int32_t bb = waves[blk * W + w];
+                if (bb < 0) continue;
+                if (first < 0) first = bb;
+                last = bb;
+            }
+            blocks[2 * blk] = first < 0 ? 0 : first;
+            blocks[2 * blk + 1] = first < 0 ? 0 : last - first + 1;
+        }
+    };
+    int cus = 256;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     }
-    if (wave_body.size() % (size_t)W) wave_body.resize(wave_body.size() + (size_t)W - wave_body.size() % (size_t)W, -1);
-    if (wave_body.size() > max_iteration_waves(n, nb)) {
+    const int W = std::max(4, (max_body + 63) / 64);
+    std::vector<int32_t> wave_body, block_body, body_wave0((size_t)nb), wave_body2, block_body2;
+    pack(W, 0, W, wave_body, block_body, body_wave0);
+    s->dev.waves_per_block = W;
+    s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
+    // More workgroups than the GPU holds at once with 4 waves per SIMD (16 per
+    // CU, the ~100-VGPR kernel): take the 80-VGPR kernel (6 waves per SIMD),
+    // and if the largest bodies need wider workgroups than the others, give
+    // the bodies of up to 4 waves workgroups of 4 waves (so that more of them
+    // share a CU) and the larger ones a second launch of W-wave workgroups.
+    s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
+    s->split = false;
+    if (s->dev.dense_iterate && W > 4) {
+        wave_body.clear();
+        pack(4, 0, 4, wave_body, block_body, body_wave0);
+        pack(W, 5, W, wave_body2, block_body2, body_wave0);     // bodies of more than 4 waves
+        s->split = !wave_body2.empty();
+        s->dev.waves_per_block = 4;
+        s->dev.n_iter_blocks = (int32_t)(wave_body.size() / 4);
+        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * 4 ? 1 : 0;
+    }
+    const size_t waves_total = wave_body.size() + wave_body2.size();
+    const size_t blocks_total = (block_body.size() + block_body2.size()) / 2;
+    if (waves_total > max_iteration_waves(n, nb) || blocks_total > max_iteration_waves(n, nb) / 4 + 2) {
         delete s;
         return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
     }
-    s->dev.waves_per_block = W;
-    s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
-    {   // more workgroups than the GPU holds at once with 4 waves per SIMD (16 per
-        // CU, the ~100-VGPR kernel): take the 80-VGPR kernel, 6 waves per SIMD
-        int dev = 0, cus = 256;
-        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
-    }
-    std::vector<int32_t> block_body(2 * (size_t)s->dev.n_iter_blocks);   // first body, body count
-    for (int32_t blk = 0; blk < s->dev.n_iter_blocks; ++blk) {
-        int32_t first = -1, last = -1;
-        for (int w = 0; w < W; ++w) {
-            const int32_t bb = wave_body[(size_t)blk * W + w];
-            if (bb < 0) continue;
-            if (first < 0) first = bb;
-            last = bb;
-        }
-        block_body[2 * (size_t)blk] = first < 0 ? 0 : first;
-        block_body[2 * (size_t)blk + 1] = first < 0 ? 0 : last - first + 1;
-    }
-    if ((size_t)s->dev.n_iter_blocks > max_iteration_waves(n, nb) / 4 + 1) {   // W >= 4
-        delete s;
-        return fail(PBDR_ERR_INVALID_ARG, "internal: block table exceeds its bound");
+    s->dev2 = s->dev;
+    if (s->split) {
+        s->dev2.wave_body = s->dev.wave_body + wave_body.size();
+        s->dev2.block_body = s->dev.block_body + block_body.size();
+        s->dev2.waves_per_block = W;
+        s->dev2.n_iter_blocks = (int32_t)(wave_body2.size() / (size_t)W);
+        s->dev2.dense_iterate = s->dev2.n_iter_blocks > cus * (16 / W) ? 1 : 0;
+        wave_body.insert(wave_body.end(), wave_body2.begin(), wave_body2.end());
+        block_body.insert(block_body.end(), block_body2.begin(), block_body2.end());
     }
 
     // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
@@ -495,6 +541,7 @@ pbdr_status pbdr_scene_set_accel(pbdr_scene* s, const float* accel_dev)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (s->dev.accel != accel_dev) drop_graph(s);
     s->dev.accel = accel_dev;
+    s->dev2.accel = accel_dev;
     return PBDR_OK;
 }
 
@@ -536,7 +583,7 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
     if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
-    hipError_t e = pbdr::enqueue_iterations(s->dev, s->consts, n_launches, s->stream);
+    hipError_t e = pbdr::enqueue_iterations(s->dev, second_launch(s), s->consts, n_launches, s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return PBDR_OK;
 }
@@ -560,7 +607,7 @@ pbdr_status pbdr_scene_time_iterations(pbdr_scene* s, int32_t n_launches, float*
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     if (e == hipSuccess)
-        e = pbdr::enqueue_iterations_timed(s->dev, s->consts, n_launches, s->stream, ev.data(),
+        e = pbdr::enqueue_iterations_timed(s->dev, second_launch(s), s->consts, n_launches, s->stream, ev.data(),
                                            ev.data() + n_launches);
     if (e == hipSuccess) e = hipEventSynchronize(ev.back());
     for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) {
@@ -713,7 +760,7 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->search_radius = s->res.rs;
     out->cell_size = s->res.a;
     out->waves_per_block = s->dev.waves_per_block;
-    out->iteration_blocks = s->dev.n_iter_blocks;
+    out->iteration_blocks = s->dev.n_iter_blocks + (s->split ? s->dev2.n_iter_blocks : 0);
     out->max_body_particles = s->max_body;
     out->iteration_kernel = s->dev.dense_iterate;
     out->workspace_bytes = s->lay.total;

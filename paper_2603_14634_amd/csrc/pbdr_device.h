@@ -94,16 +94,21 @@ struct Scene {
     const float* accel;       // [3][N] external acceleration or nullptr
 };
 
-// Enqueues `count` substeps of K = iterations solver iterations.
-hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream);
+// Enqueues `count` substeps of K = iterations solver iterations.  s2 (or
+// NULL) is the same scene with the wave tables of a second iteration launch
+// (bodies of more than 4 waves, when s packs the others into 4-wave
+// workgroups); both launches make one Jacobi iteration.
+hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+                            hipStream_t stream);
 
-// Enqueues `count` launches of the iteration kernel alone (measurement); all
-// but the first continue from the rotation of the launch before.
-hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream);
+// Enqueues `count` iterations of the iteration kernel(s) alone (measurement);
+// all but the first continue from the rotation of the iteration before.
+hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int count, hipStream_t stream);
 
-// As enqueue_iterations, launch `it` bound to the events t0[it] and t1[it].
-hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int count, hipStream_t stream,
-                                    const hipEvent_t* t0, const hipEvent_t* t1);
+// As enqueue_iterations, iteration `it` bound to the events t0[it] (begin of
+// its first launch) and t1[it] (end of its last).
+hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int count,
+                                    hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1);
 
 // Writes the canonical (key, id) order of the last substep into `sorted`.
 hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream);

@@ -704,30 +704,37 @@ hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int count, hipStream_t stream)
+hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int count, hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     int src = 0;
     for (int it = 0; it < count; ++it) {
         launch_iterate(s, c, src, it, stream);
+        if (s2) launch_iterate(*s2, c, src, it, stream);
         src ^= 1;
     }
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int count, hipStream_t stream,
-                                    const hipEvent_t* t0, const hipEvent_t* t1)
+hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int count,
+                                    hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        launch_iterate_timed(s, c, src, it, stream, t0[it], t1[it]);
+        if (s2) {       // one iteration = both launches: begin of the first, end of the second
+            launch_iterate_timed(s, c, src, it, stream, t0[it], nullptr);
+            launch_iterate_timed(*s2, c, src, it, stream, nullptr, t1[it]);
+        } else {
+            launch_iterate_timed(s, c, src, it, stream, t0[it], t1[it]);
+        }
         src ^= 1;
     }
     return hipGetLastError();
 }
 
-hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream)
+hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+                            hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     const unsigned nb = blocks_for((size_t)s.n);
@@ -742,6 +749,7 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
         int src = 0;
         for (int it = 0; it < iterations; ++it) {
             launch_iterate(s, c, src, it, stream);
+            if (s2) launch_iterate(*s2, c, src, it, stream);
             src ^= 1;
         }
     }

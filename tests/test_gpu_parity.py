@@ -185,7 +185,10 @@ def test_cuboid_rain_full_size(orc):
 def test_dense_pile_full_size(orc):
     sc = scenes.dense_pile(0, gap_frac=-0.05)
     s = _gpu_solver(sc)
-    assert s.info().iteration_kernel == 1      # 20k bodies oversubscribe the GPU
+    info = s.info()
+    assert info.iteration_kernel == 1          # 20k bodies oversubscribe the GPU
+    assert info.waves_per_block == 4           # bodies of up to 4 waves in 4-wave workgroups, the rest apart
+    assert int(np.diff(sc.body_start).max()) > 256
     _, _, _, c = check_substep(orc, sc, sc.x, sc.v, solver=s, label="dense_pile 20k")
     assert c >= 1
 
@@ -360,6 +363,23 @@ def test_timed_iteration_launches_leave_the_state_and_next_substep_unchanged():
     np.testing.assert_array_equal(runs[1][1], runs[0][1])
     with pytest.raises(B.PbdrError):
         s.time_iterations(B.MAX_TIMED_LAUNCHES + 1)
+
+
+def test_split_iteration_launches_graph_equals_direct_launches():
+    # 20k bodies: bodies of up to 4 waves and the larger ones in two launches
+    # per iteration, captured in the graph or enqueued directly: both agree
+    # bitwise
+    sc = scenes.dense_pile(0)
+    runs = []
+    for flags in (B.FLAG_NO_GRAPH, 0):
+        s = B.Solver(B.params_for(sc, flags=flags), sc.x, sc.v, sc.mass, sc.body_start)
+        assert s.info().waves_per_block == 4
+        s.step(2)
+        runs.append(s.read_state())
+        s.close()
+        del s
+    np.testing.assert_array_equal(runs[1][0], runs[0][0])
+    np.testing.assert_array_equal(runs[1][1], runs[0][1])
 
 
 def test_checkpoint_resume_is_bit_identical():
