@@ -208,14 +208,15 @@ def bench_pool(args):
 def bench_serving(args):
     from paper_2603_14634_amd import binding as B
     from paper_2603_14634_amd import scenes
-    from paper_2603_14634_amd.serving import HybridBackend, PoolBackend, ServingEngine, pool_for_budget
+    from paper_2603_14634_amd.serving import (HybridBackend, PoolBackend, ServingEngine, batch_for_budget,
+                                              pool_for_budget)
 
     reqs = scenes.serving_trace(args.seed, rate_hz=args.rate, duration_s=args.window)
     params = B.params_for(reqs[0].scene)
-    single = args.single_gib << 30 if args.serving_backend == "hybrid" else 0
-    pool = pool_for_budget(params, (args.budget_gib << 30) - single, max_scenes=4096)
-    backend = (HybridBackend(pool, single, single_lanes=args.single_lanes) if args.serving_backend == "hybrid"
-               else PoolBackend(pool))
+    large = args.large_gib << 30 if args.serving_backend == "hybrid" else 0
+    pool = pool_for_budget(params, (args.budget_gib << 30) - large, max_scenes=4096)
+    batch = batch_for_budget(params, large) if large else None
+    backend = HybridBackend(pool, batch) if batch is not None else PoolBackend(pool)
     eng = ServingEngine(backend, frames_per_tick=args.frames_per_tick, keep_results=False)
     # warm-up: one tiny request compiles nothing new but touches every path once
     eng.run([scenes.Request(0.0, reqs[0].scene, 1, -1)])
@@ -227,7 +228,7 @@ def bench_serving(args):
           % (out["completed"], out["makespan_s"], out["p50_ms"], out["p99_ms"], out["throughput"],
              out["peak_active"]), file=sys.stderr, flush=True)
     # latency by where the requests ran: the pool's register-resident classes,
-    # or the large-scene route (single scenes, or the pool's large-scene kernel)
+    # or the large-scene route (the scene batch, or the pool's large-scene kernel)
     by_id = {r.request_id: r for r in reqs}
     split = {}
     for o in out["outcomes"]:
@@ -241,7 +242,7 @@ def bench_serving(args):
     achieved = busy_rate * bpps / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_pool and the single-scene kernels over the ticks (time the GPU was stepping)",
+            "kernel": "k_pool and the batch's multi-workgroup kernels over the ticks (time the GPU was stepping)",
             "bytes_per_particle_substep": bpps}
     cpu = None if args.no_cpu_baseline else cpu_baseline_scenes([r.scene for r in reqs], args.cpu_budget_s,
                                                                 "the serving trace")
@@ -256,7 +257,7 @@ def bench_serving(args):
                    "completed": out["completed"], "rejected": len(out["rejected"]),
                    "peak_resident": out["peak_active"], "frames_per_tick": args.frames_per_tick,
                    "hbm_budget_gib": args.budget_gib, "backend": args.serving_backend,
-                   "single_scene_gib": args.single_gib if args.serving_backend == "hybrid" else 0,
+                   "large_scene_gib": args.large_gib if args.serving_backend == "hybrid" else 0,
                    "makespan_s": round(out["makespan_s"], 3), "seed": args.seed},
         "roofline": roof, "cpu_baseline": cpu,
     }
@@ -283,18 +284,17 @@ def main():
     ap.add_argument("--budget-gib", type=int, default=16, help="serving: HBM budget of the scene pool")
     ap.add_argument("--frames-per-tick", type=int, default=2, help="serving: frames per scheduling tick")
     ap.add_argument("--serving-backend", choices=("hybrid", "pool"), default="hybrid",
-                    help="serving: large scenes on the single-scene path (hybrid) or in the pool's large-scene kernel")
-    ap.add_argument("--single-gib", type=int, default=4, help="serving: HBM budget of the single-scene workspaces")
-    ap.add_argument("--single-lanes", type=int, default=8, help="serving: streams for single scenes")
+                    help="serving: large scenes in a scene batch (hybrid) or in the pool's large-scene kernel")
+    ap.add_argument("--large-gib", type=int, default=4, help="serving: HBM budget of the scene batch")
     ap.add_argument("--settle", type=int, default=None,
                     help="untimed frames before the warm-up (default: 240 for dense_pile_20k, so the pile has "
                          "settled into contact, else 0)")
     args = ap.parse_args()
     if args.workload == "serving":
-        # the serving lanes, the single-scene lanes and the pool's side-by-side
-        # classes use about 18 streams; give each its own hardware queue (read
-        # when HIP starts)
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", "24")
+        # the serving lanes (pool and batch) and the pool's side-by-side classes
+        # use about a dozen streams; give each its own hardware queue (read when
+        # HIP starts)
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
     if args.gpus != 1:
         print("bench.py measures one GPU only; runs on several GPUs are not supported "
               "(independent scenes would shard across GPUs without communication)", file=sys.stderr)

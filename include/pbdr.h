@@ -388,6 +388,87 @@ pbdr_status pbdr_pool_info_get(const pbdr_pool* pool, pbdr_pool_info* out);
 /* Frees the host handle; the workspace is untouched. */
 void pbdr_pool_destroy(pbdr_pool* pool);
 
+/* ------------------------------------------------------------------------
+ * Scene batches: many independent scenes stepped together by the kernels of
+ * the single-scene path, every substep of Alg. 1 spread over the whole GPU.
+ * For scenes too large for a pool's register-resident classes: a call is one
+ * set of launches per frame for all the scenes it steps, where stepping them
+ * one by one pays the launches of every scene.
+ *
+ * The batch holds up to max_scenes scenes, max_particles particles and
+ * max_bodies bodies (bodies of at most 1024 particles) in one device
+ * workspace owned by the caller (pbdr_batch_bytes).  Each scene has its own
+ * hash table in the batch's key arena (4 to 8 keys per particle), so scenes
+ * never interact; they share the batch's pbdr_params (time step, substeps,
+ * iterations, radius, planes, flags, nbr_cap; gravity, friction_mu and
+ * hash_bits are ignored) and bring their own gravity and friction
+ * coefficient.  A scene's result depends only on the scene: it is bitwise
+ * the same alone or among others.  Calls are enqueued on the batch's stream
+ * (asynchronous) and stepped with direct launches (no graph).  Device
+ * conditions (capacity, non-finite state) are latched for the whole batch.
+ * ------------------------------------------------------------------------ */
+typedef struct pbdr_batch pbdr_batch;
+
+typedef struct {
+    int32_t max_scenes, scenes_used;
+    int32_t max_particles, particles_used, largest_free_particles;
+    int32_t max_bodies, bodies_used;
+    int32_t max_keys, largest_free_keys;
+    size_t workspace_bytes;
+} pbdr_batch_info;
+
+/* Device workspace bytes of a batch; 0 if invalid (1 <= max_bodies <=
+ * max_particles <= 2^24, 1 <= max_scenes <= 65536, valid params). */
+size_t pbdr_batch_bytes(const pbdr_params* params, int32_t max_scenes, int32_t max_particles, int32_t max_bodies);
+
+/* Creates an empty batch in dev_workspace (256-byte aligned, >=
+ * pbdr_batch_bytes) working on hip_stream (hipStream_t or NULL); synchronises it. */
+pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int32_t max_particles,
+                              int32_t max_bodies, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                              pbdr_batch** out);
+
+/* Adds a scene (desc in host memory, as for pools); *slot receives its slot.
+ * Uploads on a stream of the batch's own (waits only for that upload); the
+ * next call waits for it.  PBDR_ERR_CAPACITY if no slot, particle, body or
+ * key range is free now; PBDR_ERR_INVALID_ARG for a malformed scene or a body
+ * of more than 1024 particles. */
+pbdr_status pbdr_batch_add(pbdr_batch* batch, const pbdr_pool_scene_desc* desc, int32_t* slot);
+
+/* Frees a slot and its ranges (enqueued after the work already on the
+ * stream).  Synchronise before removing a scene a pending call steps. */
+pbdr_status pbdr_batch_remove(pbdr_batch* batch, int32_t slot);
+
+/* Advances every resident scene by n_frames frames (asynchronous). */
+pbdr_status pbdr_batch_step(pbdr_batch* batch, int32_t n_frames);
+
+/* Advances the listed slots by frames[j] frames each (0 = stays; each slot
+ * listed at most once); the others stay.  Scenes with equal remaining frames
+ * are stepped together, in as many launch sequences as there are distinct
+ * frame counts. */
+pbdr_status pbdr_batch_step_slots(pbdr_batch* batch, int32_t count, const int32_t* slots, const int32_t* frames);
+
+/* Advances every resident scene by n_substeps substeps (for substep checks). */
+pbdr_status pbdr_batch_substep(pbdr_batch* batch, int32_t n_substeps);
+
+/* Copies a scene's positions and velocities ([3][N] each; host or device
+ * pointers; either may be NULL), synchronises, and returns the batch's
+ * latched device condition, if any. */
+pbdr_status pbdr_batch_read_state(pbdr_batch* batch, int32_t slot, float* x, float* v, int32_t on_device);
+
+/* Debug buffers of a scene's last substep to HOST memory (synchronises):
+ * PBDR_DEBUG_XT, PBDR_DEBUG_NBR_COUNT, PBDR_DEBUG_NBR ([nbr_cap][N], scene-local
+ * ids ascending) and PBDR_DEBUG_DELTA, with the layouts of pbdr_scene_read_debug. */
+pbdr_status pbdr_batch_read_debug(pbdr_batch* batch, int32_t slot, int32_t what, void* dst_host);
+
+/* Synchronises; returns the latched device condition and (if not NULL) the
+ * largest neighbour count of the last substep's stepped particles. */
+pbdr_status pbdr_batch_check(pbdr_batch* batch, int32_t* max_neighbours);
+
+pbdr_status pbdr_batch_info_get(const pbdr_batch* batch, pbdr_batch_info* out);
+
+/* Synchronises the batch's stream and frees the host handle; the workspace is untouched. */
+void pbdr_batch_destroy(pbdr_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,9 @@ EXPORTED = [
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
     "pbdr_pool_info_get", "pbdr_pool_destroy", "pbdr_pool_step_slots_on", "pbdr_pool_slot_class",
     "pbdr_pool_class_for",
+    "pbdr_batch_bytes", "pbdr_batch_create", "pbdr_batch_add", "pbdr_batch_remove", "pbdr_batch_step",
+    "pbdr_batch_step_slots", "pbdr_batch_substep", "pbdr_batch_read_state", "pbdr_batch_read_debug",
+    "pbdr_batch_check", "pbdr_batch_info_get", "pbdr_batch_destroy",
 ]
 POOL_MAX_PARTICLES, POOL_MAX_BODIES, POOL_CLASSES, POOL_LANES = 65535, 256, 7, 4
 
@@ -112,6 +115,17 @@ class PoolInfo(ctypes.Structure):
     ]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("max_scenes", ctypes.c_int32), ("scenes_used", ctypes.c_int32),
+        ("max_particles", ctypes.c_int32), ("particles_used", ctypes.c_int32),
+        ("largest_free_particles", ctypes.c_int32),
+        ("max_bodies", ctypes.c_int32), ("bodies_used", ctypes.c_int32),
+        ("max_keys", ctypes.c_int32), ("largest_free_keys", ctypes.c_int32),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
 class PbdrError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("pbdr status %d: %s" % (status, message))
@@ -177,6 +191,21 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     lib.pbdr_pool_destroy.restype = None
     lib.pbdr_pool_destroy.argtypes = [vp]
+    lib.pbdr_batch_bytes.restype = sz
+    lib.pbdr_batch_bytes.argtypes = [ctypes.POINTER(Params), i32, i32, i32]
+    lib.pbdr_batch_create.restype = i32
+    lib.pbdr_batch_create.argtypes = [ctypes.POINTER(Params), i32, i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    for name, args in [("pbdr_batch_add", [vp, ctypes.POINTER(PoolSceneDesc), pi32]),
+                       ("pbdr_batch_remove", [vp, i32]), ("pbdr_batch_step", [vp, i32]),
+                       ("pbdr_batch_step_slots", [vp, i32, vp, vp]), ("pbdr_batch_substep", [vp, i32]),
+                       ("pbdr_batch_read_state", [vp, i32, vp, vp, i32]),
+                       ("pbdr_batch_read_debug", [vp, i32, i32, vp]), ("pbdr_batch_check", [vp, pi32]),
+                       ("pbdr_batch_info_get", [vp, ctypes.POINTER(BatchInfo)])]:
+        fn = getattr(lib, name)
+        fn.restype = i32
+        fn.argtypes = args
+    lib.pbdr_batch_destroy.restype = None
+    lib.pbdr_batch_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -523,6 +552,121 @@ class Pool:
     def close(self):
         if getattr(self, "_h", None):
             self._lib.pbdr_pool_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_bytes(params: Params, max_scenes: int, max_particles: int, max_bodies: int) -> int:
+    return int(load_library().pbdr_batch_bytes(ctypes.byref(params), max_scenes, max_particles, max_bodies))
+
+
+def _pool_desc(scene):
+    """A pool/batch scene descriptor and the host arrays it points to."""
+    x = _host_f32(scene.x, (3, scene.n))
+    v = _host_f32(scene.v, (3, scene.n))
+    m = _host_f32(scene.mass, (scene.n,))
+    bs = np.ascontiguousarray(scene.body_start, dtype=np.int32)
+    desc = PoolSceneDesc(scene.n, scene.n_bodies, x.ctypes.data, v.ctypes.data, m.ctypes.data, bs.ctypes.data)
+    desc.gravity[:] = [float(g) for g in scene.gravity]
+    desc.friction_mu = float(scene.mu)
+    return desc, (x, v, m, bs)
+
+
+class Batch:
+    """Many large scenes stepped together by the multi-workgroup kernels
+    (include/pbdr.h, scene batches)."""
+
+    def __init__(self, params: Params, max_scenes: int, max_particles: int, max_bodies: int,
+                 device: str = "cuda:0", stream=None):
+        import torch
+
+        self._lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP GPU is required")
+        self.device = torch.device(device)
+        self.params = params
+        nbytes = self._lib.pbdr_batch_bytes(ctypes.byref(params), max_scenes, max_particles, max_bodies)
+        if nbytes == 0:
+            raise PbdrError(ERR_INVALID_ARG, "invalid batch capacities or parameters")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = ctypes.c_void_p()
+        _check(self._lib.pbdr_batch_create(ctypes.byref(params), max_scenes, max_particles, max_bodies,
+                                           self.workspace.data_ptr(), int(nbytes),
+                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
+        self._h = handle
+        self.sizes = {}
+
+    def try_add(self, scene):
+        """Adds a ``scenes.Scene``; returns its slot, or None if it does not fit now."""
+        desc, keep = _pool_desc(scene)
+        slot = ctypes.c_int32(-1)
+        st = self._lib.pbdr_batch_add(self._h, ctypes.byref(desc), ctypes.byref(slot))
+        del keep
+        if st == ERR_CAPACITY:
+            return None
+        _check(st)
+        self.sizes[int(slot.value)] = scene.n
+        return int(slot.value)
+
+    def add(self, scene) -> int:
+        slot = self.try_add(scene)
+        if slot is None:
+            raise PbdrError(ERR_CAPACITY, last_error())
+        return slot
+
+    def remove(self, slot: int):
+        _check(self._lib.pbdr_batch_remove(self._h, slot))
+        self.sizes.pop(slot, None)
+
+    def step(self, n_frames: int = 1):
+        _check(self._lib.pbdr_batch_step(self._h, n_frames))
+
+    def step_slots(self, slots, frames):
+        s = np.ascontiguousarray(slots, dtype=np.int32)
+        f = np.ascontiguousarray(frames, dtype=np.int32)
+        if s.shape != f.shape:
+            raise ValueError("slots and frames differ in length")
+        _check(self._lib.pbdr_batch_step_slots(self._h, int(s.shape[0]), s.ctypes.data, f.ctypes.data))
+
+    def substep(self, n_substeps: int = 1):
+        _check(self._lib.pbdr_batch_substep(self._h, n_substeps))
+
+    def read_state(self, slot: int):
+        n = self.sizes[slot]
+        x = np.empty((3, n), dtype=np.float32)
+        v = np.empty((3, n), dtype=np.float32)
+        _check(self._lib.pbdr_batch_read_state(self._h, slot, x.ctypes.data, v.ctypes.data, 0))
+        return x, v
+
+    def check(self) -> int:
+        mx = ctypes.c_int32()
+        _check(self._lib.pbdr_batch_check(self._h, ctypes.byref(mx)))
+        return int(mx.value)
+
+    def read_debug(self, slot: int, what: int) -> np.ndarray:
+        n = self.sizes[slot]
+        cap = self.params.nbr_cap or 32
+        shapes = {DEBUG_XT: ((3, n), np.float32), DEBUG_NBR_COUNT: ((n,), np.uint32),
+                  DEBUG_NBR: ((cap, n), np.uint32), DEBUG_DELTA: ((3, n), np.float32)}
+        shape, dt = shapes[what]
+        out = np.empty(shape, dtype=dt)
+        _check(self._lib.pbdr_batch_read_debug(self._h, slot, what, out.ctypes.data))
+        return out
+
+    def info(self) -> BatchInfo:
+        out = BatchInfo()
+        _check(self._lib.pbdr_batch_info_get(self._h, ctypes.byref(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pbdr_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

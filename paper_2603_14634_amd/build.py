@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbdr.so")
-SOURCES = ["pbdr_kernels.hip", "pbdr_pool_kernels.hip", "pbdr_state.hip", "pbdr_abi.cpp", "pbdr_pool.cpp"]
+SOURCES = ["pbdr_kernels.hip", "pbdr_pool_kernels.hip", "pbdr_state.hip", "pbdr_abi.cpp", "pbdr_pool.cpp",
+           "pbdr_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # The pool kernel is instantiated for several launch shapes; contraction only

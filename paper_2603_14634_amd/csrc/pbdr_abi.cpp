@@ -237,10 +237,13 @@ pbdr_status latched(pbdr_scene* s)
     return PBDR_OK;
 }
 
-void fill_consts(pbdr_scene* s)
+void fill_consts(pbdr_scene* s) { pbdr::host::fill_step_consts(s->res, &s->consts); }
+
+}  // namespace
+
+void pbdr::host::fill_step_consts(const Resolved& r, pbdr::StepConsts* out)
 {
-    const Resolved& r = s->res;
-    pbdr::StepConsts& c = s->consts;
+    pbdr::StepConsts& c = *out;
     std::memset(&c, 0, sizeof(c));
     c.h = (float)r.h;
     c.inv_h = (float)(1.0 / r.h);
@@ -262,6 +265,8 @@ void fill_consts(pbdr_scene* s)
         c.plane_d[j] = (float)r.p.planes[j][3];
     }
 }
+
+namespace {
 
 void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
 {
@@ -301,6 +306,8 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.body_wave0 = (const int32_t*)(w + L.body_wave0);
     d.block_body = (const int32_t*)(w + L.block_body);
     d.body_mq = (const float*)(w + L.body_mq);
+    d.pscene = nullptr;                   // one scene
+    d.mscene = nullptr;
     d.accel = nullptr;
 }
 

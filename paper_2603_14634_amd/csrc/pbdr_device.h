@@ -53,6 +53,18 @@ struct StepConsts {
     float plane_d[kMaxPlanes];
 };
 
+// Several independent scenes stepped as one (multi-scene mode): per scene,
+// its gravity, friction coefficient, hash-table range and whether it takes
+// part in the current launches.
+struct MultiScene {
+    float g[3];
+    float mu;
+    uint32_t key_base;        // first key of the scene's table
+    uint32_t key_mask;        // table size - 1 (power of two)
+    uint32_t active;          // 1: stepped by the current launches
+    uint32_t pad;
+};
+
 // Device pointers into a scene's workspace.
 struct Scene {
     int32_t n, nb;
@@ -92,6 +104,11 @@ struct Scene {
     Counters* counters;
     NbrStats* nbr_stats;      // [ceil(N / kBlock)]
     const float* accel;       // [3][N] external acceleration or nullptr
+    // multi-scene mode (nullptr otherwise): scene slot of each particle (-1:
+    // none) and the scenes.  Particles of scenes not stepped take no key, so
+    // the key grouping holds the stepped particles only (cells[T].x of them).
+    const int32_t* pscene;    // [N]
+    const MultiScene* mscene; // [S]
 };
 
 // Enqueues `count` substeps of K = iterations solver iterations.  s2 (or

@@ -4,15 +4,73 @@
 #pragma once
 #include <stdint.h>
 
+#include <algorithm>
+#include <iterator>
+#include <map>
+
 #include "pbdr.h"
 
 namespace pbdr {
+struct StepConsts;
 namespace host {
 
 constexpr uint32_t kKnownFlags = PBDR_FLAG_STD_VELOCITY | PBDR_FLAG_NO_LIN_MOM | PBDR_FLAG_NO_ANG_MOM |
                                  PBDR_FLAG_NO_GRAPH | PBDR_PP_AVG_MASK;
 constexpr int32_t kMaxParticles = 1 << 28;
 constexpr int kMinHashBits = 6, kMaxHashBits = 28;
+
+// First-fit allocator of integer ranges [start, start + len) (arena admission).
+class RangeAlloc {
+public:
+    void init(int32_t capacity)
+    {
+        free_.clear();
+        if (capacity > 0) free_[0] = capacity;
+    }
+    int32_t alloc(int32_t len)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < len) continue;
+            const int32_t start = it->first, rest = it->second - len;
+            free_.erase(it);
+            if (rest > 0) free_[start + len] = rest;
+            return start;
+        }
+        return -1;
+    }
+    void release(int32_t start, int32_t len)
+    {
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && start + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                prev->second += len;
+                return;
+            }
+        }
+        free_[start] = len;
+    }
+    // end of the highest range in use (0 if none) for an allocator of `capacity`
+    int32_t high_water(int32_t capacity) const
+    {
+        if (free_.empty()) return capacity;
+        const auto last = std::prev(free_.end());
+        return last->first + last->second == capacity ? last->first : capacity;
+    }
+    int32_t largest() const
+    {
+        int32_t m = 0;
+        for (const auto& e : free_) m = std::max(m, e.second);
+        return m;
+    }
+
+private:
+    std::map<int32_t, int32_t> free_;
+};
 
 // Parameters with defaults filled in.
 struct Resolved {
@@ -27,6 +85,8 @@ void clear_error();
 bool finite3(const double* v);
 // Validates params for a scene of n particles and resolves the defaults.
 pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out);
+// FP32 constants of one substep from resolved parameters.
+void fill_step_consts(const Resolved& r, StepConsts* out);
 
 }  // namespace host
 }  // namespace pbdr

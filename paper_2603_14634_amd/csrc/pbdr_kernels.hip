@@ -62,6 +62,13 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
     if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
+    const MultiScene* ms = nullptr;
+    if (s.pscene) {                    // multi-scene mode: this particle's scene, if stepped
+        const int32_t sc = s.pscene[i];
+        if (sc < 0 || !s.mscene[sc].active) return;
+        ms = &s.mscene[sc];
+    }
+    const float* g = ms ? ms->g : c.g;
     float xt[3];
     bool finite = true;
     for (int k = 0; k < 3; ++k) {
@@ -74,7 +81,7 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
             s.v[j] = v;
             finite = finite && isfinite(x) && isfinite(v);
         }
-        const float a = c.g[k] + (s.accel ? s.accel[j] : 0.0f);
+        const float a = g[k] + (s.accel ? s.accel[j] : 0.0f);
         const float dv = c.h * a;
         const float vt = v + dv;
         const float dx = c.h * vt;
@@ -84,9 +91,10 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
         s.vel[0][j] = vt;     // V_0 = V~
     }
     if (!finite) atomicOr(&s.counters->err, kErrNonFinite);
-    const uint32_t key = morton(cell_axis(xt[0], c.origin[0], c.inv_cell),
-                                cell_axis(xt[1], c.origin[1], c.inv_cell),
-                                cell_axis(xt[2], c.origin[2], c.inv_cell), c.key_mask);
+    const uint32_t key = (ms ? ms->key_base : 0u) + morton(cell_axis(xt[0], c.origin[0], c.inv_cell),
+                                                           cell_axis(xt[1], c.origin[1], c.inv_cell),
+                                                           cell_axis(xt[2], c.origin[2], c.inv_cell),
+                                                           ms ? ms->key_mask : c.key_mask);
     s.key[i] = key;
     s.rank[i] = atomicAdd(&s.cell_count[key], 1u);
 }
@@ -202,12 +210,19 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
         }
         run_chunk += chunk_tot[ch];
     }
+    // end sentinel: the number of particles grouped (all of them, or in
+    // multi-scene mode those stepped)
+    if (tile == gridDim.x - 1 && threadIdx.x == 0) s.cells[s.T] = make_uint2(s_prefix + total, 0xffffffffu);
 }
 
 __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
+    if (s.pscene) {                    // multi-scene mode: stepped particles only
+        const int32_t sc = s.pscene[i];
+        if (sc < 0 || !s.mscene[sc].active) return;
+    }
     const size_t n = (size_t)s.n;
     const uint32_t key = s.key[i];
     const uint32_t slot = s.cells[key].x + s.rank[i];
@@ -228,13 +243,20 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 {
     extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
     const int j = blockIdx.x * kBlock + threadIdx.x;   // position in key order
-    const bool live = j < s.n;
+    // multi-scene mode: the key order holds the stepped particles only
+    bool live = j < (s.pscene ? (int)s.cells[s.T].x : s.n);
     const size_t n = (size_t)s.n;
     const int cap = c.nbr_cap;
     const int tid = threadIdx.x;
     uint32_t count = 0;
+    uint32_t i = live ? s.sorted_raw[j] : 0u;
+    uint32_t key_base = 0u, key_mask = c.key_mask;
+    if (live && s.pscene) {             // multi-scene mode: the particle's own scene table
+        const int32_t sc = s.pscene[i];
+        key_base = s.mscene[sc].key_base;
+        key_mask = s.mscene[sc].key_mask;
+    }
     if (live) {
-        const uint32_t i = s.sorted_raw[j];
         const float4 me = s.sxt4[j];
         const float px = me.x, py = me.y, pz = me.z;
         const int32_t pb = __float_as_int(me.w);
@@ -244,8 +266,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
         uint32_t lo[27], hi[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
-            const uint32_t k = morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
-                                      cz + (uint32_t)(t / 9 - 1), c.key_mask);
+            const uint32_t k = key_base + morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
+                                                 cz + (uint32_t)(t / 9 - 1), key_mask);
             const uint2 e = s.cells[k];
             const uint32_t end = s.cells[k + 1].x;
             lo[t] = e.x;
@@ -389,6 +411,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     // contacts, from X_i (Jacobi): planes (constraint (1)) and particles of
     // other bodies (constraint (2)); friction from the displacement since X_init
     if (act) {
+        const float mu = s.pscene ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
         for (int pl = 0; pl < c.n_planes; ++pl) {
             const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
             const float un = nx * del[0] + ny * del[1] + nz * del[2];
@@ -397,7 +420,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
             const float pen = c.radius - e;
             const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
             const float ut2 = ux * ux + uy * uy + uz * uz;
-            const float f = ut2 > 0.0f ? fminf(1.0f, c.mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+            const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
             Cd[0] += pen * nx - f * ux;
             Cd[1] += pen * ny - f * uy;
             Cd[2] += pen * nz - f * uz;
@@ -423,7 +446,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
             const float un = u[0] * nx + u[1] * ny + u[2] * nz;
             const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
             const float ut2 = ux * ux + uy * uy + uz * uz;
-            const float f = ut2 > 0.0f ? fminf(1.0f, c.mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+            const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
             float wgt = 1.0f;
             if (avg == 0u) {
                 const uint32_t nq = s.nbr_n[jq];
@@ -626,6 +649,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
+    if (s.pscene) {
+        const int32_t sc = s.pscene[i];
+        if (sc < 0 || !s.mscene[sc].active) return;
+    }
     const size_t n = (size_t)s.n;
     bool finite = true;
     for (int k = 0; k < 3; ++k) {

@@ -18,6 +18,7 @@
 #include "pbdr_pool_device.h"
 
 using pbdr::host::fail;
+using pbdr::host::RangeAlloc;
 using pbdr::host::Resolved;
 
 namespace {
@@ -78,51 +79,6 @@ PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
 }
 
 // First-fit allocator of index ranges in [0, capacity), coalescing on release.
-class RangeAlloc {
-public:
-    void init(int32_t capacity)
-    {
-        free_.clear();
-        if (capacity > 0) free_[0] = capacity;
-    }
-    int32_t alloc(int32_t len)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < len) continue;
-            const int32_t start = it->first, rest = it->second - len;
-            free_.erase(it);
-            if (rest > 0) free_[start + len] = rest;
-            return start;
-        }
-        return -1;
-    }
-    void release(int32_t start, int32_t len)
-    {
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && start + len == next->first) {
-            len += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                prev->second += len;
-                return;
-            }
-        }
-        free_[start] = len;
-    }
-    int32_t largest() const
-    {
-        int32_t m = 0;
-        for (const auto& e : free_) m = std::max(m, e.second);
-        return m;
-    }
-
-private:
-    std::map<int32_t, int32_t> free_;
-};
-
 struct SlotInfo {
     bool used = false;
     int32_t p0 = 0, n = 0, b0 = 0, nb = 0, cls = 0;

@@ -213,110 +213,95 @@ class PoolBackend:
 class HybridBackend(PoolBackend):
     """The pool for the scenes its register-resident classes hold; every scene
     the pool would give to its large-scene kernel (one workgroup walking tens of
-    thousands of particles, tens of milliseconds per frame) runs instead as a
-    scene of its own on the multi-workgroup path (``binding.Solver``), whose
-    substeps spread over the whole GPU.
+    thousands of particles, tens of milliseconds per frame) goes instead to a
+    scene batch (``binding.Batch``): all of them are stepped together by the
+    multi-workgroup kernels, one set of launches per frame for the whole batch,
+    on a lane of its own beside the pool's.  The batch's HBM arena admits them
+    as the pool's admits the small ones.  A scene's result depends only on the
+    scene: it is routed by its shape alone, and neither the pool nor the batch
+    lets scenes interact."""
 
-    Each such scene holds a workspace of its own, admitted while the resident
-    ones stay within ``single_budget_bytes``, and joins the extra lane (one
-    stream each) with the fewest resident particles; a lane's scenes step one
-    after another on its stream, and the lanes run side by side with each other
-    and with the pool's lanes.  A scene's result depends only on the scene: it
-    is routed by its shape alone, and each single scene is stepped alone."""
+    FIRST_BATCH = 1 << 20          # slot numbers of batch scenes start here
 
-    FIRST_SINGLE = 1 << 20          # slot numbers of single scenes start here
-
-    def __init__(self, pool, single_budget_bytes: int, single_lanes: int = 4, solver_factory=None):
+    def __init__(self, pool, batch):
         super().__init__(pool)
-        import torch
-
-        if single_lanes < 1:
-            raise ValueError("single_lanes must be >= 1")
+        self.batch = batch
         self.pool_lanes = self.lanes
-        self.lanes = self.pool_lanes + single_lanes
-        self.streams += [torch.cuda.Stream(device=pool.device) for _ in range(single_lanes)]
-        self.events += [None] * single_lanes
-        self.budget = int(single_budget_bytes)
-        self.used_bytes = 0
-        self.singles = {}           # slot -> (solver, bytes, lane, particles)
-        self.lane_particles = [0] * self.lanes
-        self._next = self.FIRST_SINGLE
-        self._factory = solver_factory or self._solver
-        self._admit_stream = torch.cuda.Stream(device=pool.device)
+        self.batch_lane = self.lanes
+        self.lanes += 1
+        self.streams.append(batch.stream)
+        self.events.append(None)
 
-    def _solver(self, scene, stream):
-        from . import binding as B
-
-        # created on a stream of its own (creation waits for its stream), then
-        # moved to the lane, whose stream may be busy with other scenes' frames
-        s = B.Solver(B.params_for(scene), scene.x, scene.v, scene.mass, scene.body_start,
-                     device=self.pool.device, stream=self._admit_stream)
-        s.set_stream(stream)
-        return s
-
-    def routes_single(self, scene) -> bool:
+    def routes_to_batch(self, scene) -> bool:
         from . import binding as B
 
         return self.pool.class_for(scene) == B.POOL_CLASSES
 
     def try_add(self, scene):
-        from . import binding as B
-
-        if not self.routes_single(scene):
+        if not self.routes_to_batch(scene):
             return self.pool.try_add(scene)
-        nbytes = B.scene_bytes(B.params_for(scene), scene.n, scene.n_bodies)
-        if self.used_bytes + nbytes > self.budget:
-            return None
-        lane = min(range(self.pool_lanes, self.lanes), key=lambda ln: (self.lane_particles[ln], ln))
-        solver = self._factory(scene, self.streams[lane])
-        slot = self._next
-        self._next += 1
-        self.singles[slot] = (solver, nbytes, lane, scene.n)
-        self.used_bytes += nbytes
-        self.lane_particles[lane] += scene.n
-        return slot
+        slot = self.batch.try_add(scene)
+        return None if slot is None else self.FIRST_BATCH + slot
 
     def fits_ever(self, scene) -> bool:
         """Whether the scene could be admitted into an empty backend."""
-        from . import binding as B
-
-        if self.routes_single(scene):
-            return B.scene_bytes(B.params_for(scene), scene.n, scene.n_bodies) <= self.budget
+        if self.routes_to_batch(scene):
+            info = self.batch.info()
+            return scene.n <= info.max_particles and scene.n_bodies <= info.max_bodies
         return scene.n <= self.pool.info().max_particles
 
     def lane_of(self, slot):
-        if slot in self.singles:
-            return self.singles[slot][2]
-        return super().lane_of(slot)
+        return self.batch_lane if slot >= self.FIRST_BATCH else super().lane_of(slot)
 
     def launch(self, lane, slots, frames):
-        if lane < self.pool_lanes:
+        if lane != self.batch_lane:
             return super().launch(lane, slots, frames)
         import torch
 
-        for s, f in zip(slots, frames):
-            self.singles[s][0].step(f)
+        self.batch.step_slots([s - self.FIRST_BATCH for s in slots], frames)
         ev = torch.cuda.Event()
-        ev.record(self.streams[lane])
+        ev.record(self.batch.stream)
         self.events[lane] = ev
 
     def read_state(self, slot):
-        if slot in self.singles:
-            return self.singles[slot][0].read_state()
+        if slot >= self.FIRST_BATCH:
+            return self.batch.read_state(slot - self.FIRST_BATCH)
         return super().read_state(slot)
 
     def check(self, slot):
-        if slot in self.singles:
-            return self.singles[slot][0].check()
+        if slot >= self.FIRST_BATCH:
+            return self.batch.check()
         return super().check(slot)
 
     def remove(self, slot):
-        if slot not in self.singles:
-            return super().remove(slot)
-        solver, nbytes, lane, n = self.singles.pop(slot)
-        solver.close()
-        self.used_bytes -= nbytes
-        self.lane_particles[lane] -= n
+        if slot >= self.FIRST_BATCH:
+            return self.batch.remove(slot - self.FIRST_BATCH)
+        return super().remove(slot)
+
+
+def batch_for_budget(params, budget_bytes: int, max_scenes: int = 1024, particles_per_body: int = 16,
+                     device="cuda:0"):
+    """The largest scene batch (in particles) whose workspace fits the HBM budget,
+    on a stream of its own."""
+    import torch
+
+    from . import binding as B
+
+    def size(n):
+        return B.batch_bytes(params, max_scenes, n, max(1, n // particles_per_body))
+
+    lo, hi = 1, 1 << 24
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        b = size(mid)
+        if 0 < b <= budget_bytes:
+            lo = mid
+        else:
+            hi = mid - 1
+    if not 0 < size(lo) <= budget_bytes:
+        raise ValueError("budget too small for a scene batch")
+    return B.Batch(params, max_scenes, lo, max(1, lo // particles_per_body), device=device,
+                   stream=torch.cuda.Stream(device=device))
 
 
 def pool_for_budget(params, budget_bytes: int, max_scenes: int = 4096, particles_per_body: int = 16, device="cuda:0"):

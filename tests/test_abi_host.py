@@ -37,8 +37,9 @@ def test_header_compiles_as_c_and_struct_layout_matches_binding(tmp_path):
 #include <stddef.h>
 #include "pbdr.h"
 int main(void) {
-  printf("%zu %zu %d %d\n", offsetof(pbdr_scene_info, iteration_kernel), offsetof(pbdr_scene_info, max_body_particles),
-         PBDR_MAX_TIMED_LAUNCHES, PBDR_MAX_PLANES);
+  printf("%zu %zu %d %d %zu %zu\n", offsetof(pbdr_scene_info, iteration_kernel),
+         offsetof(pbdr_scene_info, max_body_particles), PBDR_MAX_TIMED_LAUNCHES, PBDR_MAX_PLANES,
+         sizeof(pbdr_batch_info), offsetof(pbdr_batch_info, workspace_bytes));
   printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(pbdr_params), offsetof(pbdr_params, planes),
          offsetof(pbdr_params, flags), sizeof(pbdr_scene_desc), sizeof(pbdr_scene_info),
          offsetof(pbdr_scene_info, workspace_bytes), sizeof(pbdr_pool_scene_desc),
@@ -52,7 +53,7 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()
     got = [int(t) for t in out]
     want = [B.SceneInfo.iteration_kernel.offset, B.SceneInfo.max_body_particles.offset, B.MAX_TIMED_LAUNCHES,
-            B.MAX_PLANES, ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
+            B.MAX_PLANES, ctypes.sizeof(B.BatchInfo), B.BatchInfo.workspace_bytes.offset, ctypes.sizeof(B.Params), B.Params.planes.offset, B.Params.flags.offset, ctypes.sizeof(B.SceneDesc),
             ctypes.sizeof(B.SceneInfo), B.SceneInfo.workspace_bytes.offset, ctypes.sizeof(B.PoolSceneDesc),
             B.PoolSceneDesc.gravity.offset, ctypes.sizeof(B.PoolInfo), B.PoolInfo.workspace_bytes.offset]
     assert got == want
@@ -162,6 +163,13 @@ def test_null_handles_are_rejected():
     assert lib.pbdr_pool_class_for(None, 1, 1, None, None) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_set_stream(None, None) == B.ERR_INVALID_ARG
     assert lib.pbdr_scene_read_bodies(None, None, None, None, None) == B.ERR_INVALID_ARG
+    for name, args in (("pbdr_batch_add", (None, None, None)), ("pbdr_batch_remove", (None, 0)),
+                       ("pbdr_batch_step", (None, 1)), ("pbdr_batch_step_slots", (None, 0, None, None)),
+                       ("pbdr_batch_substep", (None, 1)), ("pbdr_batch_read_state", (None, 0, None, None, 0)),
+                       ("pbdr_batch_read_debug", (None, 0, 0, None)), ("pbdr_batch_check", (None, None)),
+                       ("pbdr_batch_info_get", (None, None))):
+        assert getattr(lib, name)(*args) == B.ERR_INVALID_ARG, name
+    lib.pbdr_batch_destroy(None)
     lib.pbdr_scene_destroy(None)
 
 

@@ -10,7 +10,8 @@ import pytest
 
 from paper_2603_14634_amd import binding as B
 from paper_2603_14634_amd import scenes
-from paper_2603_14634_amd.serving import HybridBackend, PoolBackend, ServingEngine, pool_for_budget
+from paper_2603_14634_amd.serving import (HybridBackend, PoolBackend, ServingEngine, batch_for_budget,
+                                          pool_for_budget)
 
 pytestmark = pytest.mark.gpu
 
@@ -72,55 +73,62 @@ def test_admission_keeps_the_resident_scenes_within_the_budget():
     assert info.particles_used == 0 and info.scenes_used == 0   # everything left the pool
 
 
-def _serve_hybrid(reqs, budget=256 << 20, single_budget=256 << 20, fpt=2, single_lanes=2):
+def _serve_hybrid(reqs, budget=256 << 20, batch_budget=256 << 20, fpt=2):
     params = B.params_for(reqs[0].scene)
     pool = pool_for_budget(params, budget, max_scenes=64)
-    backend = HybridBackend(pool, single_budget, single_lanes=single_lanes)
+    batch = batch_for_budget(params, batch_budget, max_scenes=64)
+    backend = HybridBackend(pool, batch)
     out = ServingEngine(backend, frames_per_tick=fpt).run(reqs)
-    state = (pool.info(), backend.used_bytes, len(backend.singles))
+    state = (pool.info(), batch.info())
     pool.close()
+    batch.close()
     return out, backend, state
 
 
-def test_hybrid_routes_large_scenes_to_the_single_scene_path_with_the_same_results():
-    reqs = _trace(seed=5, rate=400.0, duration=0.06)
+def _large_and_small(reqs):
     params = B.params_for(reqs[0].scene)
     probe = pool_for_budget(params, 64 << 20, max_scenes=8)
     big = [j for j, r in enumerate(reqs) if probe.class_for(r.scene) == B.POOL_CLASSES]
     small = [j for j, r in enumerate(reqs) if probe.class_for(r.scene) < B.POOL_CLASSES]
     probe.close()
+    return big, small
+
+
+def test_hybrid_serves_large_scenes_in_a_batch_with_the_same_results():
+    reqs = _trace(seed=5, rate=400.0, duration=0.06)
+    big, small = _large_and_small(reqs)
     assert big and small
-    print("[serve] hybrid: %d requests, %d on the single-scene path" % (len(reqs), len(big)), flush=True)
-    mixed, _, (info, used, left) = _serve_hybrid(reqs)
+    print("[serve] hybrid: %d requests, %d in the scene batch" % (len(reqs), len(big)), flush=True)
+    mixed, _, (pinfo, binfo) = _serve_hybrid(reqs)
     assert mixed["completed"] == len(reqs) and not mixed["rejected"]
-    assert info.scenes_used == 0 and used == 0 and left == 0      # everything left both arenas
+    assert pinfo.scenes_used == 0 and binfo.scenes_used == 0      # everything left both arenas
     by_id = {o.request_id: o for o in mixed["outcomes"]}
     for j in (big[0], big[-1]):
         r = reqs[j]
-        # a single-scene request gives what the plain solver gives for its horizon
+        # a batch request gives what the single-scene solver gives for its horizon
         s = B.Solver(B.params_for(r.scene), r.scene.x, r.scene.v, r.scene.mass, r.scene.body_start)
         s.step(r.frames)
         x, v = s.read_state()
         s.close()
-        print("[serve] single request %d: %d particles, %d frames" % (j, r.scene.n, r.frames), flush=True)
+        print("[serve] batch request %d: %d particles, %d frames" % (j, r.scene.n, r.frames), flush=True)
         np.testing.assert_array_equal(by_id[r.request_id].x, x)
         np.testing.assert_array_equal(by_id[r.request_id].v, v)
     for j in (small[0], small[-1], big[len(big) // 2]):
         r = reqs[j]
-        alone, _, _ = _serve_hybrid([scenes.Request(0.0, r.scene, r.frames, r.request_id)], fpt=3, single_lanes=1)
+        alone, _, _ = _serve_hybrid([scenes.Request(0.0, r.scene, r.frames, r.request_id)], fpt=3)
         np.testing.assert_array_equal(by_id[r.request_id].x, alone["outcomes"][0].x)
         np.testing.assert_array_equal(by_id[r.request_id].v, alone["outcomes"][0].v)
 
 
-def test_hybrid_admission_keeps_single_scenes_within_their_budget():
+def test_hybrid_admission_keeps_the_batch_within_its_arena():
     reqs = _trace(seed=5, rate=1000.0, duration=0.03)
-    params = B.params_for(reqs[0].scene)
-    probe = pool_for_budget(params, 64 << 20, max_scenes=8)
-    big = [r for r in reqs if probe.class_for(r.scene) == B.POOL_CLASSES]
-    probe.close()
+    big, _ = _large_and_small(reqs)
     assert len(big) >= 2
-    need = max(B.scene_bytes(B.params_for(r.scene), r.scene.n, r.scene.n_bodies) for r in big)
-    out, backend, (_, used, left) = _serve_hybrid(reqs, single_budget=need)   # the largest single scene fits only alone
+    need = max(reqs[j].scene.n for j in big)
+    params = B.params_for(reqs[0].scene)
+    # a batch that holds the largest large scene but not all of them at once
+    budget = B.batch_bytes(params, 64, need + need // 2, max(1, (need + need // 2) // 16))
+    out, _, (_, binfo) = _serve_hybrid(reqs, batch_budget=budget)
     assert out["completed"] == len(reqs) and not out["rejected"]
-    assert used == 0 and left == 0
-    assert backend.used_bytes == 0
+    assert binfo.max_particles < sum(reqs[j].scene.n for j in big)
+    assert binfo.scenes_used == 0 and binfo.particles_used == 0
