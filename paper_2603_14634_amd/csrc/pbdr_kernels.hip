@@ -55,6 +55,9 @@ constexpr int kWaves = kBlock / 64;
 // integration step + keys + counting pass
 // ---------------------------------------------------------------------------
 
+// MULTI: multi-scene mode (Scene::pscene set); a separate instance, so that
+// the single-scene kernels carry none of its checks.
+template <bool MULTI>
 __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, int fold_src)
 {
 #pragma clang fp contract(off)
@@ -63,7 +66,7 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     const MultiScene* ms = nullptr;
-    if (s.pscene) {                    // multi-scene mode: this particle's scene, if stepped
+    if (MULTI) {                       // this particle's scene, if stepped
         const int32_t sc = s.pscene[i];
         if (sc < 0 || !s.mscene[sc].active) return;
         ms = &s.mscene[sc];
@@ -215,11 +218,12 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
     if (tile == gridDim.x - 1 && threadIdx.x == 0) s.cells[s.T] = make_uint2(s_prefix + total, 0xffffffffu);
 }
 
+template <bool MULTI>
 __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
-    if (s.pscene) {                    // multi-scene mode: stepped particles only
+    if (MULTI) {                       // stepped particles only
         const int32_t sc = s.pscene[i];
         if (sc < 0 || !s.mscene[sc].active) return;
     }
@@ -239,19 +243,20 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
 // neighbour lists, one thread per particle in key order
 // ---------------------------------------------------------------------------
 
+template <bool MULTI>
 __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 {
     extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
     const int j = blockIdx.x * kBlock + threadIdx.x;   // position in key order
     // multi-scene mode: the key order holds the stepped particles only
-    bool live = j < (s.pscene ? (int)s.cells[s.T].x : s.n);
+    bool live = j < (MULTI ? (int)s.cells[s.T].x : s.n);
     const size_t n = (size_t)s.n;
     const int cap = c.nbr_cap;
     const int tid = threadIdx.x;
     uint32_t count = 0;
     uint32_t i = live ? s.sorted_raw[j] : 0u;
     uint32_t key_base = 0u, key_mask = c.key_mask;
-    if (live && s.pscene) {             // multi-scene mode: the particle's own scene table
+    if (MULTI && live) {                // multi-scene mode: the particle's own scene table
         const int32_t sc = s.pscene[i];
         key_base = s.mscene[sc].key_base;
         key_mask = s.mscene[sc].key_mask;
@@ -354,6 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 // wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
 // the substep: from the second iteration on, the rotation is refined from the
 // previous iteration's.
+template <bool MULTI>
 __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it)
 {
     constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
@@ -411,7 +417,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     // contacts, from X_i (Jacobi): planes (constraint (1)) and particles of
     // other bodies (constraint (2)); friction from the displacement since X_init
     if (act) {
-        const float mu = s.pscene ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
+        const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
         for (int pl = 0; pl < c.n_planes; ++pl) {
             const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
             const float un = nx * del[0] + ny * del[1] + nz * del[2];
@@ -618,15 +624,16 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 // 100 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
 // (6 waves per SIMD) for grids that oversubscribe it, where two workgroups per
 // CU hide each other's per-body phases.
+template <bool MULTI>
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body(s, c, src, it);
+    iterate_body<MULTI>(s, c, src, it);
 }
 
 __global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body(s, c, src, it);
+    iterate_body<false>(s, c, src, it);
 }
 
 // Canonical (key, id) order from the key grouping of the last substep: the
@@ -645,11 +652,12 @@ __global__ void __launch_bounds__(kBlock) k_canonical(Scene s)
     s.sorted[b0 + below] = i;
 }
 
+template <bool MULTI>
 __global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
-    if (s.pscene) {
+    if (MULTI) {
         const int32_t sc = s.pscene[i];
         if (sc < 0 || !s.mscene[sc].active) return;
     }
@@ -688,11 +696,15 @@ inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlo
 
 void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream)
 {
-    if (s.dense_iterate)
+    if (s.pscene)           // multi-scene mode: one variant for every mix
+        hipLaunchKernelGGL(k_iterate<true>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src,
+                           it);
+    else if (s.dense_iterate)
         hipLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src,
                            it);
     else
-        hipLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src, it);
+        hipLaunchKernelGGL(k_iterate<false>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c,
+                           src, it);
 }
 
 // The same launch with a pair of events bound to the dispatch itself: their
@@ -704,7 +716,7 @@ void launch_iterate_timed(const Scene& s, const StepConsts& c, int src, int it, 
         hipExtLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1,
                               0, s, c, src, it);
     else
-        hipExtLaunchKernelGGL(k_iterate, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1, 0,
+        hipExtLaunchKernelGGL(k_iterate<false>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1, 0,
                               s, c, src, it);
 }
 
@@ -768,11 +780,20 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
     const unsigned nb_pred = blocks_for((size_t)s.n > (size_t)s.n_scan_tiles ? (size_t)s.n : (size_t)s.n_scan_tiles);
     const size_t nbr_lds = (size_t)c.nbr_cap * kBlock * sizeof(uint32_t);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
+    const bool multi = s.pscene != nullptr;
     for (int sub = 0; sub < count; ++sub) {
-        hipLaunchKernelGGL(k_predict_keys, dim3(nb_pred), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
-        hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, stream, s);
-        hipLaunchKernelGGL(k_neighbours, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+        if (multi) {
+            hipLaunchKernelGGL(k_predict_keys<true>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
+            hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
+            hipLaunchKernelGGL(k_scatter<true>, dim3(nb), dim3(kBlock), 0, stream, s);
+            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+        } else {
+            hipLaunchKernelGGL(k_predict_keys<false>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c,
+                               sub == 0 ? -1 : last);
+            hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
+            hipLaunchKernelGGL(k_scatter<false>, dim3(nb), dim3(kBlock), 0, stream, s);
+            hipLaunchKernelGGL(k_neighbours<false>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+        }
         int src = 0;
         for (int it = 0; it < iterations; ++it) {
             launch_iterate(s, c, src, it, stream);
@@ -780,7 +801,10 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
             src ^= 1;
         }
     }
-    hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kBlock), 0, stream, s, last);
+    if (multi)
+        hipLaunchKernelGGL(k_finalize<true>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+    else
+        hipLaunchKernelGGL(k_finalize<false>, dim3(nb), dim3(kBlock), 0, stream, s, last);
     return hipGetLastError();
 }
 
