@@ -51,6 +51,18 @@ using namespace dev;
 
 constexpr int kWaves = kBlock / 64;
 
+// Workgroup i of a launch runs on XCD i % 8 (each XCD has its own L2).  This
+// gives XCD x the contiguous range of logical workgroups x*q + min(x, r) ..
+// (q + [x < r] of them, q = n / 8, r = n % 8), a bijection of [0, n): work that
+// is adjacent in the logical order (neighbouring bodies, which share cache
+// lines at their ends and read each other's positions; neighbouring keys)
+// then meets in one L2.
+__device__ inline int xcd_block()
+{
+    const uint32_t nb = gridDim.x, q = nb / 8u, r = nb % 8u, x = blockIdx.x % 8u;
+    return (int)(x * q + (x < r ? x : r) + blockIdx.x / 8u);
+}
+
 // ---------------------------------------------------------------------------
 // integration step + keys + counting pass
 // ---------------------------------------------------------------------------
@@ -247,7 +259,8 @@ template <bool MULTI>
 __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 {
     extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
-    const int j = blockIdx.x * kBlock + threadIdx.x;   // position in key order
+    const int blk = xcd_block();
+    const int j = blk * kBlock + threadIdx.x;  // position in key order
     // multi-scene mode: the key order holds the stepped particles only
     bool live = j < (MULTI ? (int)s.cells[s.T].x : s.n);
     const size_t n = (size_t)s.n;
@@ -340,8 +353,8 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
             bm = max(bm, st_max[w]);
             bs += st_sum[w];
         }
-        const int rows = min(kBlock, s.n - (int)(blockIdx.x * kBlock));
-        NbrStats& slot = s.nbr_stats[blockIdx.x];
+        const int rows = min(kBlock, s.n - blk * kBlock);
+        NbrStats& slot = s.nbr_stats[blk];
         slot.max_nbr = max(slot.max_nbr, bm);
         slot.sum += bs;
         slot.rows += (unsigned long long)rows;
@@ -369,14 +382,15 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
 
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int g = blockIdx.x * s.waves_per_block + wave;
+    const int blk = xcd_block();
+    const int g = blk * s.waves_per_block + wave;
     const int b = s.wave_body[g];                 // -1: idle wave
-    const int blk_b0 = s.block_body[2 * blockIdx.x], blk_nb = s.block_body[2 * blockIdx.x + 1];
+    const int blk_b0 = s.block_body[2 * blk], blk_nb = s.block_body[2 * blk + 1];
     int s0 = 0, e0 = 0, lw0 = wave;
     if (b >= 0) {
         s0 = s.body_start[b];
         e0 = s.body_start[b + 1];
-        lw0 = s.body_wave0[b] - blockIdx.x * s.waves_per_block;
+        lw0 = s.body_wave0[b] - blk * s.waves_per_block;
     }
     const int lb = b >= blk_b0 ? b - blk_b0 : 0;  // body slot within the workgroup
     const int i = s0 + (wave - lw0) * 64 + lane;  // this lane's particle
@@ -395,7 +409,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     int bl_w0 = 0, bl_nw = 0;
     float bl_M = 1.0f, Rprev[9];
     if (body_lane) {
-        bl_w0 = s.body_wave0[bb] - blockIdx.x * s.waves_per_block;
+        bl_w0 = s.body_wave0[bb] - blk * s.waves_per_block;
         bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
         bl_M = s.body_mass[bb];
         if (it > 0)
