@@ -255,8 +255,11 @@ __global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
 // neighbour lists, one thread per particle in key order
 // ---------------------------------------------------------------------------
 
+// At most 128 VGPRs (4 waves per SIMD, no spill): the 27 key ranges and 9
+// candidates in flight otherwise take ~156 and leave 3 waves per SIMD.
 template <bool MULTI>
-__global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
+k_neighbours(Scene s, StepConsts c)
 {
     extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
     const int blk = xcd_block();
