@@ -434,8 +434,9 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
  * of more than 1024 particles. */
 pbdr_status pbdr_batch_add(pbdr_batch* batch, const pbdr_pool_scene_desc* desc, int32_t* slot);
 
-/* Frees a slot and its ranges (enqueued after the work already on the
- * stream).  Synchronise before removing a scene a pending call steps. */
+/* Frees a slot and its ranges; later calls no longer step it, and a scene
+ * added later may reuse the ranges.  Synchronise the batch's stream before
+ * removing a scene that a pending call steps. */
 pbdr_status pbdr_batch_remove(pbdr_batch* batch, int32_t slot);
 
 /* Advances every resident scene by n_frames frames (asynchronous). */

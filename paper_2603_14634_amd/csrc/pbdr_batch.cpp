@@ -494,8 +494,12 @@ pbdr_status pbdr_batch_remove(pbdr_batch* b, int32_t slot)
     pbdr_status st = bcheck_slot(b, slot);
     if (st != PBDR_OK) return st;
     BSlot& sl = b->slots[(size_t)slot];
-    // its particles belong to no scene from the next launch on
-    HIP_TRY(hipMemsetAsync(b->ws + b->lay.pscene + 4 * (size_t)sl.p0, 0xff, 4 * (size_t)sl.n, b->stream));
+    // its particles belong to no scene from the next launch on; cleared on the
+    // upload stream, so that a scene added into the same range later is
+    // uploaded after the clear (the next launch waits for both)
+    HIP_TRY(hipMemsetAsync(b->ws + b->lay.pscene + 4 * (size_t)sl.p0, 0xff, 4 * (size_t)sl.n, b->upload));
+    HIP_TRY(hipEventRecord(b->uploaded, b->upload));
+    b->upload_pending = true;
     for (int32_t bb = sl.b0; bb <= sl.b0 + sl.nb; ++bb) b->body_need[(size_t)bb] = 0;
     b->keys.release(sl.k0, 1 << sl.kbits);
     b->bodies.release(sl.b0, sl.nb + 1);
