@@ -154,3 +154,100 @@ def test_large_scenes_tick_on_their_own_lane():
 def test_engine_rejects_bad_settings():
     with pytest.raises(ValueError):
         ServingEngine(object(), frames_per_tick=0)
+
+
+class _Stream:
+    """Stands in for a torch stream (no GPU)."""
+
+
+class _FakeRoutedPool:
+    """The pool side of HybridBackend: launch classes by size, POOL_CLASSES above `big`."""
+
+    def __init__(self, big):
+        self.big = big
+        self.resident = {}
+        self.device = "cpu"
+        self.launched = []
+
+    def class_for(self, scene):
+        from paper_2603_14634_amd import binding as B
+
+        return B.POOL_CLASSES if scene.n > self.big else 0
+
+    def slot_class(self, slot):
+        return 0
+
+    def try_add(self, scene):
+        slot = len(self.resident)
+        self.resident[slot] = scene
+        return slot
+
+    def step_slots_on(self, lane, stream, slots, frames):
+        self.launched.append((lane, list(slots), list(frames)))
+
+    def read_state(self, slot):
+        return ("pool", slot)
+
+    def check(self, slot):
+        return 0
+
+    def remove(self, slot):
+        del self.resident[slot]
+
+
+class _FakeBatch(_FakeRoutedPool):
+    def __init__(self, capacity):
+        super().__init__(big=0)
+        self.capacity = capacity
+        self.stream = _Stream()
+        self.steps = []
+
+    def info(self):
+        return type("Info", (), {"max_particles": self.capacity, "max_bodies": self.capacity // 16})()
+
+    def try_add(self, scene):
+        if sum(s.n for s in self.resident.values()) + scene.n > self.capacity:
+            return None
+        return super().try_add(scene)
+
+    def step_slots(self, slots, frames):
+        self.steps.append((list(slots), list(frames)))
+
+    def read_state(self, slot):
+        return ("batch", slot)
+
+
+def test_hybrid_backend_routes_by_shape_and_keeps_slot_spaces_apart(monkeypatch):
+    import torch
+
+    from paper_2603_14634_amd import serving
+
+    class _Event:
+        def record(self, stream):
+            pass
+
+        def query(self):
+            return True
+
+    monkeypatch.setattr(torch.cuda, "Stream", lambda device=None: _Stream())
+    monkeypatch.setattr(torch.cuda, "Event", _Event)
+    pool, batch = _FakeRoutedPool(big=1000), _FakeBatch(capacity=5000)
+    hb = serving.HybridBackend(pool, batch)
+    assert hb.lanes == 4 and hb.batch_lane == 3
+    def scene(n, tag):
+        sc = _Scene(n, tag)
+        sc.n_bodies = max(1, n // 100)
+        return sc
+
+    small, large, huge = scene(500, 0), scene(3000, 1), scene(4000, 2)
+    s_small, s_large = hb.try_add(small), hb.try_add(large)
+    assert s_small < hb.FIRST_BATCH <= s_large
+    assert hb.try_add(huge) is None                          # the batch arena is full for now
+    assert hb.lane_of(s_small) < hb.pool_lanes and hb.lane_of(s_large) == hb.batch_lane
+    hb.launch(hb.batch_lane, [s_large], [2])
+    assert batch.steps == [([s_large - hb.FIRST_BATCH], [2])] and hb.done(hb.batch_lane)
+    assert hb.read_state(s_large) == ("batch", s_large - hb.FIRST_BATCH)
+    assert hb.read_state(s_small) == ("pool", s_small)
+    assert hb.fits_ever(huge) is True and hb.fits_ever(scene(6000, 3)) is False
+    hb.remove(s_large)
+    assert not batch.resident and hb.try_add(huge) is not None
