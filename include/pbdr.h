@@ -462,7 +462,7 @@ pbdr_status pbdr_batch_read_state(pbdr_batch* batch, int32_t slot, float* x, flo
 pbdr_status pbdr_batch_read_debug(pbdr_batch* batch, int32_t slot, int32_t what, void* dst_host);
 
 /* Synchronises; returns the latched device condition and (if not NULL) the
- * largest neighbour count of the last substep's stepped particles. */
+ * largest neighbour count seen since the batch was created. */
 pbdr_status pbdr_batch_check(pbdr_batch* batch, int32_t* max_neighbours);
 
 pbdr_status pbdr_batch_info_get(const pbdr_batch* batch, pbdr_batch_info* out);

@@ -308,6 +308,8 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.body_mq = (const float*)(w + L.body_mq);
     d.pscene = nullptr;                   // one scene
     d.mscene = nullptr;
+    d.n_extent = n;
+    d.n_active = n;
     d.accel = nullptr;
 }
 

@@ -204,6 +204,7 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
     auto* blocks = (int32_t*)(hp + L.block_off);
     auto* wave0 = (int32_t*)(hp + L.wave0_off);
     size_t nw = 0;
+    int32_t b_lo = b->BC, b_hi = 0;       // body ids with a first wave in this plan
     auto close_block = [&]() {           // pad the open workgroup with idle waves
         while (nw % (size_t)W) waves[nw++] = -1;
     };
@@ -219,6 +220,8 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
         m.active = active[(size_t)s] ? 1u : 0u;
         if (!m.active) continue;
         close_block();                     // a workgroup holds bodies of one scene (consecutive ids)
+        b_lo = std::min(b_lo, sl.b0);
+        b_hi = std::max(b_hi, sl.b0 + sl.nb);
         for (int32_t bb = sl.b0; bb < sl.b0 + sl.nb; ++bb) {
             const int need = b->body_need[(size_t)bb];
             if (nw + 2 * (size_t)W > L.max_waves) return fail(PBDR_ERR_INVALID_ARG, "internal: packing bound");
@@ -246,7 +249,15 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
         HIP_TRY(hipStreamWaitEvent(b->stream, b->uploaded, 0));
         b->upload_pending = false;
     }
-    HIP_TRY(hipMemcpyAsync(b->ws + L.plan, hp, L.plan_bytes, hipMemcpyHostToDevice, b->stream));
+    // only the parts in use: scene constants, the waves and workgroups of
+    // this plan, and the first waves of the bodies it packs
+    auto up = [&](size_t off, size_t bytes) {
+        return hipMemcpyAsync(b->ws + L.plan + off, hp + off, bytes, hipMemcpyHostToDevice, b->stream);
+    };
+    HIP_TRY(up(L.mscene_off, sizeof(pbdr::MultiScene) * (size_t)b->S));
+    HIP_TRY(up(L.wave_off, 4 * nw));
+    HIP_TRY(up(L.block_off, 8 * nblk));
+    HIP_TRY(up(L.wave0_off + 4 * (size_t)b_lo, 4 * (size_t)(b_hi - b_lo)));
     HIP_TRY(hipEventRecord(b->plan_done[k], b->stream));
     pbdr::Scene d = b->dev;
     const uint32_t khi = (uint32_t)b->keys.high_water((int32_t)b->K);
@@ -254,6 +265,10 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
     d.n_scan_tiles = (uint32_t)(((size_t)d.T + pbdr::kScanTile - 1) / pbdr::kScanTile);
     d.waves_per_block = W;
     d.n_iter_blocks = (int32_t)nblk;
+    d.n_extent = b->parts.high_water(b->P);
+    d.n_active = 0;
+    for (int32_t s = 0; s < b->S; ++s)
+        if (b->slots[(size_t)s].used && active[(size_t)s]) d.n_active += b->slots[(size_t)s].n;
     d.dense_iterate = 0;      // one kernel variant for every mix: a scene's result depends on the scene only
     const long long total = (long long)frames * b->res.p.substeps;
     if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");

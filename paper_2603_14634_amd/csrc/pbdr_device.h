@@ -109,6 +109,8 @@ struct Scene {
     // the key grouping holds the stepped particles only (cells[T].x of them).
     const int32_t* pscene;    // [N]
     const MultiScene* mscene; // [S]
+    int32_t n_extent;         // launch extent: particles 0 .. n_extent - 1 may be stepped
+    int32_t n_active;         // particles stepped by the current launches
 };
 
 // Enqueues `count` substeps of K = iterations solver iterations.  s2 (or

@@ -793,17 +793,23 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
                             hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
-    const unsigned nb = blocks_for((size_t)s.n);
-    const unsigned nb_pred = blocks_for((size_t)s.n > (size_t)s.n_scan_tiles ? (size_t)s.n : (size_t)s.n_scan_tiles);
+    const bool multi = s.pscene != nullptr;
+    if (multi && s.n_active <= 0) return hipSuccess;
+    // multi-scene mode: the particle kernels cover the arena up to its last
+    // scene, the neighbour kernel the stepped particles only (its workgroups
+    // are renumbered across XCDs, so the grid must hold no idle tail)
+    const size_t extent = multi ? (size_t)s.n_extent : (size_t)s.n;
+    const unsigned nb = blocks_for(extent);
+    const unsigned nb_nbr = multi ? blocks_for((size_t)s.n_active) : nb;
+    const unsigned nb_pred = blocks_for(extent > (size_t)s.n_scan_tiles ? extent : (size_t)s.n_scan_tiles);
     const size_t nbr_lds = (size_t)c.nbr_cap * kBlock * sizeof(uint32_t);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
-    const bool multi = s.pscene != nullptr;
     for (int sub = 0; sub < count; ++sub) {
         if (multi) {
             hipLaunchKernelGGL(k_predict_keys<true>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
             hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
             hipLaunchKernelGGL(k_scatter<true>, dim3(nb), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb_nbr), dim3(kBlock), nbr_lds, stream, s, c);
         } else {
             hipLaunchKernelGGL(k_predict_keys<false>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c,
                                sub == 0 ? -1 : last);
