@@ -56,13 +56,16 @@ def _ulp32(a):
     return (np.spacing(a)).astype(np.float64)
 
 
-def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=None, label=""):
-    """One substep from the FP32 state (x, v) on both sides; asserts parity."""
+def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=None, label="", quiet=False):
+    """One substep from the FP32 state (x, v) on both sides; asserts parity.
+    The largest error/tolerance ratios of displacement and velocity are left in
+    `check_substep.ratios`."""
     import torch
 
     x = np.ascontiguousarray(x, dtype=np.float32)
     v = np.ascontiguousarray(v, dtype=np.float32)
-    print("[parity] %s n=%d bodies=%d flags=%#x" % (label or sc.name, sc.n, sc.n_bodies, flags), flush=True)
+    if not quiet:
+        print("[parity] %s n=%d bodies=%d flags=%#x" % (label or sc.name, sc.n, sc.n_bodies, flags), flush=True)
     s = solver or _gpu_solver(sc, flags=flags, cap=cap, bits=bits)
     s.set_state(x, v)
     acc_t = None
@@ -99,9 +102,12 @@ def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=
     tol_d = 1e-5 * r
     tol_x = 1e-5 * r + _ulp32(xo)
     tol_v = 1e-5 * r / h + 2 * _ulp32(vo)
-    print("[parity]   max |d err| %.3g (tol %.3g)  max |v err| %.3g  contacts max %d"
-          % (d_err.max() if sc.n else 0, tol_d, v_err.max() if sc.n else 0, int(cnt.max()) if sc.n else 0),
-          flush=True)
+    check_substep.ratios = (float((d_err / tol_d).max()) if sc.n else 0.0,
+                            float((v_err / tol_v).max()) if sc.n else 0.0)
+    if not quiet:
+        print("[parity]   max |d err| %.3g (tol %.3g)  max |v err| %.3g  contacts max %d"
+              % (d_err.max() if sc.n else 0, tol_d, v_err.max() if sc.n else 0, int(cnt.max()) if sc.n else 0),
+              flush=True)
     assert np.all(d_err <= tol_d), "displacement error %.3g > %.3g" % (d_err.max(), tol_d)
     assert np.all(x_err <= tol_x)
     assert np.all(v_err <= tol_v), "velocity error %.3g" % v_err.max()
@@ -136,6 +142,46 @@ def test_drop_cubes_along_reference_trajectory(orc, seed):
         contacts = max(contacts, c)
     lowest = min(float(xs[2].min()) for xs, _ in states.values())
     assert lowest < sc.radius          # ground contact was exercised
+
+
+def _oracle_substep_states(orc, sc, substeps, threads=THREADS):
+    """FP32-rounded reference states after each listed number of substeps."""
+    p = _orc_params(orc, sc, threads=threads)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    out, done = {}, 0
+    for k in sorted(substeps):
+        if k > done:
+            x, v, _ = orc.substep(p, rest, x, v, n_substeps=k - done)
+            done = k
+        out[k] = (x.astype(np.float32), v.astype(np.float32))
+    return out
+
+
+def _sampled_gate(orc, sc, picks, solver, label):
+    """check_substep at each listed substep of the reference trajectory; prints
+    the largest error/tolerance ratios over all of them."""
+    states = _oracle_substep_states(orc, sc, picks)
+    worst_d = worst_v = 0.0
+    contacts = []
+    for k in sorted(picks):
+        x, v = states.pop(k)
+        _, _, _, c = check_substep(orc, sc, x, v, solver=solver, label="%s substep %d" % (label, k),
+                                   quiet=len(picks) > 20)
+        worst_d = max(worst_d, check_substep.ratios[0])
+        worst_v = max(worst_v, check_substep.ratios[1])
+        contacts.append(c)
+    print("[gate] %s: %d substeps, worst |d err|/tol %.3f, worst |v err|/tol %.3f, contacts max %d"
+          % (label, len(picks), worst_d, worst_v, max(contacts)), flush=True)
+    return contacts
+
+
+def test_drop_cubes_every_substep_of_200_frames(orc):
+    """The 512-particle drop at every one of the 800 substeps of 200 frames,
+    each from the reference state rounded to FP32: free fall, impact, rest."""
+    sc = scenes.drop_cubes(0)
+    contacts = _sampled_gate(orc, sc, list(range(200 * sc.substeps)), _gpu_solver(sc), "drop_cubes")
+    assert max(contacts) >= 1
 
 
 def test_drop_cubes_free_running_divergence(orc):
@@ -173,24 +219,28 @@ def test_drop_cubes_free_running_divergence(orc):
 # full-size workloads
 # ---------------------------------------------------------------------------
 
-def test_cuboid_rain_full_size(orc):
+def test_cuboid_rain_16_substeps_of_the_first_40_frames(orc):
+    """The 171k-particle rain at 16 evenly spaced substeps of its first 40
+    frames, each from the reference state rounded to FP32."""
     sc = scenes.cuboid_rain(0)
-    states = _oracle_states(orc, sc, [0, 12])
-    for f, (x, v) in states.items():
-        s = _gpu_solver(sc)
-        assert s.info().iteration_kernel == 0      # the grid fits the GPU at once
-        check_substep(orc, sc, x, v, solver=s, label="cuboid_rain frame %d" % f)
+    s = _gpu_solver(sc)
+    assert s.info().iteration_kernel == 0      # the grid fits the GPU at once
+    picks = [int(round(k)) for k in np.linspace(0, 40 * sc.substeps - 1, 16)]
+    assert max(_sampled_gate(orc, sc, picks, s, "cuboid_rain")) >= 1
 
 
-def test_dense_pile_full_size(orc):
+def test_dense_pile_16_substeps_of_the_first_4_frames(orc):
+    """The 20k-body pile (2.0M particles, overlapping start) at 16 evenly
+    spaced substeps of its first 4 frames (the reference takes seconds per
+    substep at this size)."""
     sc = scenes.dense_pile(0, gap_frac=-0.05)
     s = _gpu_solver(sc)
     info = s.info()
     assert info.iteration_kernel == 1          # 20k bodies oversubscribe the GPU
     assert info.waves_per_block == 4           # bodies of up to 4 waves in 4-wave workgroups, the rest apart
     assert int(np.diff(sc.body_start).max()) > 256
-    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, solver=s, label="dense_pile 20k")
-    assert c >= 1
+    picks = [int(round(k)) for k in np.linspace(0, 4 * sc.substeps - 1, 16)]
+    assert min(_sampled_gate(orc, sc, picks, s, "dense_pile")) >= 1
 
 
 # ---------------------------------------------------------------------------
