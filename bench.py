@@ -84,11 +84,28 @@ def measured_traffic(workload: str):
         return None
 
 
-def cpu_baseline(sc, budget_s: float):
+def host_cpu() -> str:
+    """CPU model and logical CPU count of this host."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s, %d logical CPUs" % (model, os.cpu_count() or 1)
+
+
+def oracle_threads(requested: int) -> int:
+    return max(1, min(requested, os.cpu_count() or 1))
+
+
+def cpu_baseline(sc, budget_s: float, threads: int):
     from oracle import oracle as ref
     import numpy as np
 
-    threads = max(1, min(16, os.cpu_count() or 1))
     p = ref.params_for(sc, threads=threads)
     rest = ref.Body(sc.x, sc.mass, sc.body_start)
     x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
@@ -103,7 +120,7 @@ def cpu_baseline(sc, budget_s: float):
     subs = 1 + extra
     return {"value": sc.n * subs / total, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
             "sample": "%d substeps of %s from its initial state (%d particles, K=%d), FP64, %d OpenMP threads"
-                      % (subs, sc.name, sc.n, sc.iterations, threads)}
+                      % (subs, sc.name, sc.n, sc.iterations, threads), "host": host_cpu()}
 
 
 def pool_bytes_per_particle_substep(iterations: int, kbar: float) -> float:
@@ -113,11 +130,10 @@ def pool_bytes_per_particle_substep(iterations: int, kbar: float) -> float:
     return iterations * iterate_bytes_per_particle(kbar) + 60.0 + 24.0 + 4.0 * kbar
 
 
-def cpu_baseline_scenes(scs, budget_s: float, label: str):
+def cpu_baseline_scenes(scs, budget_s: float, label: str, threads: int):
     """The FP64 reference over whole scenes, one substep each, until the budget is spent."""
     from oracle import oracle as ref
 
-    threads = max(1, min(16, os.cpu_count() or 1))
     done_n, used, count = 0, 0.0, 0
     for sc in scs:
         p = ref.params_for(sc, threads=threads)
@@ -131,7 +147,7 @@ def cpu_baseline_scenes(scs, budget_s: float, label: str):
             break
     return {"value": done_n / used, "unit": "particle-substeps/s", "cores": threads, "kind": "oracle",
             "sample": "one substep of each of the first %d scenes of %s (%d particles), FP64, %d OpenMP threads"
-                      % (count, label, done_n, threads)}
+                      % (count, label, done_n, threads), "host": host_cpu()}
 
 
 def bench_pool(args):
@@ -190,7 +206,8 @@ def bench_pool(args):
             "kernel": "k_pool (one workgroup per scene, all substeps of the call)",
             "us_per_call": round(ms * 1e3 / args.steps, 1), "bytes_per_particle_substep": bpps,
             "note": "state stays on chip across iterations, so HBM carries far less than the algorithmic bytes"}
-    cpu = None if args.no_cpu_baseline else cpu_baseline_scenes(batch, args.cpu_budget_s, "batch_4096")
+    cpu = None if args.no_cpu_baseline else cpu_baseline_scenes(batch, args.cpu_budget_s, "batch_4096",
+                                                                     oracle_threads(args.cpu_threads))
     line = {
         "metric": "particle-substeps/s at stated error vs FP64 oracle",
         "value": round(value, 1), "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
@@ -245,7 +262,7 @@ def bench_serving(args):
             "kernel": "k_pool and the batch's multi-workgroup kernels over the ticks (time the GPU was stepping)",
             "bytes_per_particle_substep": bpps}
     cpu = None if args.no_cpu_baseline else cpu_baseline_scenes([r.scene for r in reqs], args.cpu_budget_s,
-                                                                "the serving trace")
+                                                                "the serving trace", oracle_threads(args.cpu_threads))
     line = {
         "metric": "particle-substeps/s at stated error vs FP64 oracle; p50/p99 rollout latency",
         "value": round(out["throughput"], 1), "unit": "particle-substeps/s", "n_gpus": 1,
@@ -275,6 +292,7 @@ def main():
     ap.add_argument("--hash-bits", type=int, default=0, help="override the hash-grid key bits (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
+    ap.add_argument("--cpu-threads", type=int, default=16, help="OpenMP threads of the FP64 reference baseline")
     ap.add_argument("--iter-launches", type=int, default=200, help="launches timed for the roofline")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB (3 times), the "
@@ -381,7 +399,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 reference on the host", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(sc, args.cpu_budget_s)
+        cpu = cpu_baseline(sc, args.cpu_budget_s, oracle_threads(args.cpu_threads))
 
     line = {
         "metric": "particle-substeps/s at stated error vs FP64 oracle",
