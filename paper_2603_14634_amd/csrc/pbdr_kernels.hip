@@ -31,7 +31,7 @@
 // for nearby particles), and body-relative coordinates are formed against an
 // anchor particle of the body.  Velocities follow the paper's incremental
 // update V_{i+1} = V_i + dX / dt.  Per-body sums are fixed-order reductions
-// (DPP within a wave, then the wave partials in wave order), so results are
+// (lane swaps and DPP within a wave, then the wave partials in wave order), so results are
 // bitwise reproducible.
 //
 // The neighbour-search decisions (key, predicate) are taken in FP32 with no
@@ -370,7 +370,7 @@ k_neighbours(Scene s, StepConsts c)
 // ---------------------------------------------------------------------------
 
 // Bodies are packed into workgroups of W waves; each body owns ceil(n/64)
-// consecutive waves, one particle per lane.  Per-body sums are wave sums (DPP)
+// consecutive waves, one particle per lane.  Per-body sums are wave sums (lane swaps, DPP)
 // combined over the body's waves; the per-body 3x3 algebra runs on lane j of
 // wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
 // the substep: from the second iteration on, the rotation is refined from the
@@ -495,10 +495,11 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         for (int j = 0; j < 3; ++j) S[j] = m * y[j];
         for (int a = 0; a < 3; ++a)
             for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
-        for (int j = 0; j < NSM; ++j) S[j] = wave_sum_to_63(S[j]);
-        if (lane == 63)
-            for (int j = 0; j < NSM / 4; ++j)
-                red_sm[wave * (NSM / 4) + j] = make_float4(S[4 * j], S[4 * j + 1], S[4 * j + 2], S[4 * j + 3]);
+        wave_sums_by_row<NSM>(S);
+        if ((lane & 15) == 15) {      // row j holds sums j NSM/4 .. j NSM/4 + NSM/4 - 1
+            float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
+            for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
+        }
     }
     __syncthreads();
     if (body_lane) {            // one lane per body: centre, covariance, rotation
@@ -558,10 +559,11 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         S[19] = -m * za[0] * za[2];
         S[20] = -m * za[1] * za[2];
         S[21] = S[22] = S[23] = 0.0f;
-        for (int j = 0; j < 21; ++j) S[j] = wave_sum_to_63(S[j]);
-        if (lane == 63)
-            for (int j = 0; j < NMOM / 4; ++j)
-                red_mom[wave * (NMOM / 4) + j] = make_float4(S[4 * j], S[4 * j + 1], S[4 * j + 2], S[4 * j + 3]);
+        wave_sums_by_row<NMOM>(S);
+        if ((lane & 15) == 15) {
+            float* dst = (float*)red_mom + wave * NMOM + (lane >> 4) * (NMOM / 4);
+            for (int j = 0; j < NMOM / 4; ++j) dst[j] = S[j];
+        }
     }
     __syncthreads();
 

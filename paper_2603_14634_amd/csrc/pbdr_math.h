@@ -77,6 +77,46 @@ __device__ inline float wave_sum_to_63(float v)
     return v;
 }
 
+// Sums over the 64 lanes of K values at once (K a multiple of 4), in a fixed
+// order.  The gfx950 lane swaps pair up values: v_permlane32_swap exchanges
+// the upper half of one register with the lower half of another, so one swap
+// and one add fold two values from 64 lanes to 32; v_permlane16_swap does the
+// same for rows (16 lanes) within each half; DPP then sums each row.  That is
+// about 2.5 K instructions where K separate wave sums take 6 K or more.  On
+// return, every lane of row j (lanes 16 j .. 16 j + 15) of v[p] holds the sum
+// of value j K/4 + p, for p < K/4.
+template <int K>
+__device__ inline void wave_sums_by_row(float* v)
+{
+    static_assert(K % 4 == 0, "K must be a multiple of 4");
+    constexpr int H = K / 2, Q = K / 4;
+    // value p in lanes 0-31, value p + H in lanes 32-63
+#pragma unroll
+    for (int p = 0; p < H; ++p) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[p]), __float_as_uint(v[p + H]), false,
+                                                        false);
+        const unsigned lo = r[0], hi = r[1];   // (element-wise __builtin_bit_cast of r drops r[1])
+        v[p] = __uint_as_float(lo) + __uint_as_float(hi);
+    }
+    // value p in row 0, p + Q in row 1, p + H in row 2, p + H + Q in row 3
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[p]), __float_as_uint(v[p + Q]), false,
+                                                        false);
+        const unsigned lo = r[0], hi = r[1];
+        v[p] = __uint_as_float(lo) + __uint_as_float(hi);
+    }
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        float t = v[p];
+        t = dpp_add<0xb1, 0xf>(t);    // quad_perm [1,0,3,2]
+        t = dpp_add<0x4e, 0xf>(t);    // quad_perm [2,3,0,1]
+        t = dpp_add<0x141, 0xf>(t);   // row_half_mirror
+        t = dpp_add<0x140, 0xf>(t);   // row_mirror: the row sum in all 16 lanes
+        v[p] = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // small 3x3 algebra (FP32)
 // ---------------------------------------------------------------------------
