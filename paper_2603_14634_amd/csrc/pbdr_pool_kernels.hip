@@ -354,14 +354,17 @@ __device__ inline void mom_terms(const Ctx& x, bool act, const float* br, const 
     Sv[21] = Sv[22] = Sv[23] = 0.0f;
 }
 
-// Reduces a wave's terms into lane 63 and stores NV float4s of them at dst.
+// Sums a wave's 4 NV terms over its lanes and stores them at dst[0 .. 4 NV):
+// after the reduction row j of the wave holds terms j NV .. j NV + NV - 1, and
+// one lane per row stores them.
 template <int NV>
 __device__ inline void wave_store(float* Sv, float* dst, int lane)
 {
-    for (int j = 0; j < 4 * NV; ++j) Sv[j] = wave_sum_to_63(Sv[j]);
-    if (lane == 63)
-        for (int j = 0; j < NV; ++j)
-            *(float4*)(dst + 4 * j) = make_float4(Sv[4 * j], Sv[4 * j + 1], Sv[4 * j + 2], Sv[4 * j + 3]);
+    wave_sums_by_row<4 * NV>(Sv);
+    if ((lane & 15) == 15) {
+        float* d = dst + (lane >> 4) * NV;
+        for (int j = 0; j < NV; ++j) d[j] = Sv[j];
+    }
 }
 
 // Body lane: centre, covariance and rotation from the slot sums (Sec. III-C).
