@@ -120,23 +120,58 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 // known; a wave inspects 64 predecessors per step)
 // ---------------------------------------------------------------------------
 
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* wave_tot, uint32_t* total)
+// Inclusive prefix sum over the lanes of a wave: shifts by 1, 2, 4, 8 within
+// each 16-lane row (DPP, lanes without a source add 0), then each row adds the
+// last lane of the rows before it (row broadcasts).
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane: row sums by DPP,
+// the four row sums gathered in lane 63 by row broadcasts, then read out.
+__device__ inline uint32_t wave_total(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);  // row_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Exclusive prefix sums of N values per thread over the workgroup, each value
+// scanned on its own (the N scans share one barrier).  tot[k] receives the
+// workgroup total of value k.
+template <int N>
+__device__ inline void block_exclusive_scans(const uint32_t* v, uint32_t (*wave_tot)[kWaves], uint32_t* excl,
+                                             uint32_t* tot)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t x = v;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wave_tot[wave] = x;
+    uint32_t incl[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) incl[k] = wave_inclusive_scan(v[k]);
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < N; ++k) wave_tot[k][wave] = incl[k];
     __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (int w = 0; w < kWaves; ++w) {
-        if (w < wave) before += wave_tot[w];
-        all += wave_tot[w];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        uint32_t before = 0, all = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) before += wave_tot[k][w];
+            all += wave_tot[k][w];
+        }
+        excl[k] = before + incl[k] - v[k];
+        tot[k] = all;
     }
-    *total = all;
-    return before + x - v;
 }
 
 constexpr unsigned long long kTileAggregate = 1ull << 32, kTileInclusive = 2ull << 32;
@@ -154,22 +189,30 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
     // that already run; the wait is bounded all the same
     const uint32_t tile = blockIdx.x;
     const size_t tbase = (size_t)tile * kScanTile;
-    uint32_t vals[kChunks][4], excl[kChunks], chunk_tot[kChunks];
+    uint32_t vals[kChunks][4], csum[kChunks], excl[kChunks], chunk_tot[kChunks];
+    // all chunks are loaded before any is scanned, so their loads overlap
+#pragma unroll
     for (int ch = 0; ch < kChunks; ++ch) {
         const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
         if (base + 3 < s.T) {
             const uint4 v = *(const uint4*)&s.cell_count[base];
             vals[ch][0] = v.x; vals[ch][1] = v.y; vals[ch][2] = v.z; vals[ch][3] = v.w;
-            *(uint4*)&s.cell_count[base] = make_uint4(0u, 0u, 0u, 0u);   // ready for the next substep
         } else {
-            for (int k = 0; k < 4; ++k) {
-                vals[ch][k] = base + k < s.T ? s.cell_count[base + k] : 0u;
-                if (base + k < s.T) s.cell_count[base + k] = 0u;
-            }
+            for (int k = 0; k < 4; ++k) vals[ch][k] = base + k < s.T ? s.cell_count[base + k] : 0u;
         }
-        excl[ch] = block_exclusive_scan(vals[ch][0] + vals[ch][1] + vals[ch][2] + vals[ch][3], wave_tot[ch],
-                                        &chunk_tot[ch]);
     }
+#pragma unroll
+    for (int ch = 0; ch < kChunks; ++ch) {       // counts ready for the next substep
+        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
+        if (base + 3 < s.T) {
+            *(uint4*)&s.cell_count[base] = make_uint4(0u, 0u, 0u, 0u);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (base + k < s.T) s.cell_count[base + k] = 0u;
+        }
+        csum[ch] = vals[ch][0] + vals[ch][1] + vals[ch][2] + vals[ch][3];
+    }
+    block_exclusive_scans<kChunks>(csum, wave_tot, excl, chunk_tot);
     uint32_t total = 0;
     for (int ch = 0; ch < kChunks; ++ch) total += chunk_tot[ch];
     if (threadIdx.x < 64) {                       // wave 0: publish and look back
@@ -203,8 +246,7 @@ __global__ void __launch_bounds__(kBlock) k_scan(Scene s)
                     continue;
                 }
                 uint32_t v = lane <= stop ? (uint32_t)st : 0u;
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                prefix += v;
+                prefix += wave_total(v);
                 if (incl) break;
                 top -= 64;
             }
@@ -369,13 +411,42 @@ k_neighbours(Scene s, StepConsts c)
 // one Jacobi iteration (Alg. 1 loop body)
 // ---------------------------------------------------------------------------
 
+// Sum of the per-wave partials (NV float4 per wave) of a body's waves w0 ..
+// w0 + nw - 1, in wave order; the LDS reads of U waves are issued together.
+template <int NV, int U>
+__device__ inline void sum_wave_partials(const float4* red, int w0, int nw, float* T)
+{
+    for (int j = 0; j < 4 * NV; ++j) T[j] = 0.0f;
+    for (int w = 0; w < nw; w += U) {
+        float4 p[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int wu = w + u < nw ? w + u : nw - 1;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) p[u][j] = red[(w0 + wu) * NV + j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (w + u >= nw) break;
+#pragma unroll
+            for (int j = 0; j < NV; ++j) {
+                T[4 * j] += p[u][j].x;
+                T[4 * j + 1] += p[u][j].y;
+                T[4 * j + 2] += p[u][j].z;
+                T[4 * j + 3] += p[u][j].w;
+            }
+        }
+    }
+}
+
 // Bodies are packed into workgroups of W waves; each body owns ceil(n/64)
 // consecutive waves, one particle per lane.  Per-body sums are wave sums (lane swaps, DPP)
 // combined over the body's waves; the per-body 3x3 algebra runs on lane j of
 // wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
 // the substep: from the second iteration on, the rotation is refined from the
-// previous iteration's.
-template <bool MULTI>
+// previous iteration's.  SM_UNROLL / MOM_UNROLL: waves whose partial sums the
+// per-body lane reads from LDS at once.
+template <bool MULTI, int SM_UNROLL, int MOM_UNROLL>
 __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it)
 {
     constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
@@ -384,7 +455,9 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     __shared__ float body_sm[kMaxWaves * 12];    // per body of the workgroup: R (9), centre (3)
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
 
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // the wave index as a wave-uniform (scalar) value: the per-wave table and
+    // body entries below then come through scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int blk = xcd_block();
     const int g = blk * s.waves_per_block + wave;
     const int b = s.wave_body[g];                 // -1: idle wave
@@ -410,11 +483,12 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     const bool body_lane = wave == 0 && lane < blk_nb;
     const int bb = blk_b0 + (body_lane ? lane : 0);
     int bl_w0 = 0, bl_nw = 0;
-    float bl_M = 1.0f, Rprev[9];
+    float bl_M = 1.0f, Rprev[9], mq3[3];
     if (body_lane) {
         bl_w0 = s.body_wave0[bb] - blk * s.waves_per_block;
         bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
         bl_M = s.body_mass[bb];
+        for (int j = 0; j < 3; ++j) mq3[j] = s.body_mq[3 * (size_t)bb + j];
         if (it > 0)
             for (int j = 0; j < 9; ++j) Rprev[j] = s.body_rot[9 * (size_t)bb + j];
     }
@@ -504,18 +578,8 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     __syncthreads();
     if (body_lane) {            // one lane per body: centre, covariance, rotation
         float T[NSM];
-        for (int j = 0; j < NSM; ++j) T[j] = 0.0f;
-        for (int w = 0; w < bl_nw; ++w)
-#pragma unroll
-            for (int j = 0; j < NSM / 4; ++j) {
-                const float4 p = red_sm[(bl_w0 + w) * (NSM / 4) + j];
-                T[4 * j] += p.x;
-                T[4 * j + 1] += p.y;
-                T[4 * j + 2] += p.z;
-                T[4 * j + 3] += p.w;
-            }
+        sum_wave_partials<NSM / 4, SM_UNROLL>(red_sm, bl_w0, bl_nw, T);
         const float im = frcp(bl_M);
-        const float mq3[3] = {s.body_mq[3 * bb], s.body_mq[3 * bb + 1], s.body_mq[3 * bb + 2]};
         float cc[3], A[9], Rb[9];
         for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
         for (int a = 0; a < 3; ++a)
@@ -570,16 +634,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     // momentum conservation constraint, one lane per body
     if (body_lane) {
         float T[NMOM];
-        for (int j = 0; j < NMOM; ++j) T[j] = 0.0f;
-        for (int w = 0; w < bl_nw; ++w)
-#pragma unroll
-            for (int j = 0; j < NMOM / 4; ++j) {
-                const float4 p = red_mom[(bl_w0 + w) * (NMOM / 4) + j];
-                T[4 * j] += p.x;
-                T[4 * j + 1] += p.y;
-                T[4 * j + 2] += p.z;
-                T[4 * j + 3] += p.w;
-            }
+        sum_wave_partials<NMOM / 4, MOM_UNROLL>(red_mom, bl_w0, bl_nw, T);
         const float Mb = bl_M, im = frcp(Mb);
         float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
         for (int j = 0; j < 3; ++j) {
@@ -640,19 +695,19 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 }
 
 // The iteration kernel in two register budgets: the compiler's choice (about
-// 100 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
-// (6 waves per SIMD) for grids that oversubscribe it, where two workgroups per
-// CU hide each other's per-body phases.
+// 85 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
+// (6 waves per SIMD, a few values spilled) for grids that oversubscribe it,
+// where more workgroups per CU hide each other's per-body phases.
 template <bool MULTI>
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<MULTI>(s, c, src, it);
+    iterate_body<MULTI, 4, 4>(s, c, src, it);
 }
 
 __global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<false>(s, c, src, it);
+    iterate_body<false, 2, 2>(s, c, src, it);
 }
 
 // Canonical (key, id) order from the key grouping of the last substep: the
