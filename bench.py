@@ -291,6 +291,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--hash-bits", type=int, default=0, help="override the hash-grid key bits (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--iteration-launches", action="store_true",
+                    help="one launch per solver iteration even where the substep could run them as one")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=16, help="OpenMP threads of the FP64 reference baseline")
     ap.add_argument("--iter-launches", type=int, default=200, help="launches timed for the roofline")
@@ -342,7 +344,8 @@ def main():
     sc = scenes.WORKLOADS[args.workload](args.seed)
     print("[bench] workload %s: %d particles, %d bodies" % (sc.name, sc.n, sc.n_bodies), file=sys.stderr,
           flush=True)
-    solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits)
+    solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits,
+                                 flags=B.FLAG_ITERATION_LAUNCHES if args.iteration_launches else 0)
     stream = solver.stream
     settle = args.settle if args.settle is not None else (240 if args.workload == "dense_pile_20k" else 0)
     if settle:
@@ -369,11 +372,14 @@ def main():
     print("[bench] %d frames in %.3f ms (wall %.3f s): %.4g particle-substeps/s" % (args.steps, ms, wall, value),
           file=sys.stderr, flush=True)
 
-    # dominant kernel: one solver iteration over all bodies.  Each launch
+    # dominant kernel: the iteration kernel of the substep, one Jacobi
+    # iteration over all bodies per launch, or all K of them where the
+    # substep runs them as one launch (iteration_kernel 2).  Each launch
     # carries a pair of HIP events bound to its own dispatch on the solver's
     # stream (begin and end of the kernel, no marker packets between), so the
     # average is the kernel's duration; the back-to-back rate (which adds the
     # gap between dependent launches) is reported beside it.
+    per_launch = sc.iterations if solver.info().iteration_kernel == 2 else 1
     solver.launch_iterations(10)
     torch.cuda.synchronize()
     n_it = args.iter_launches
@@ -385,12 +391,14 @@ def main():
     k1.record(stream)
     torch.cuda.synchronize()
     interval_ms = k0.elapsed_time(k1) / n_it
-    bytes_launch = sc.n * iterate_bytes_per_particle(kbar) + sc.n_bodies * iterate_bytes_per_body()
+    bytes_launch = per_launch * (sc.n * iterate_bytes_per_particle(kbar) + sc.n_bodies * iterate_bytes_per_body())
     achieved = bytes_launch / (it_ms / 1e3) / 1e9
     traffic = measured_traffic(sc.name)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_iterate (one Jacobi iteration, all bodies)",
+            "kernel": ("k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)"
+                       % per_launch) if per_launch > 1 else "k_iterate (one Jacobi iteration, all bodies)",
+            "iterations_per_launch": per_launch,
             "avg_launch_us": round(it_ms * 1e3, 3), "launch_interval_us": round(interval_ms * 1e3, 3),
             "bytes_per_launch": int(bytes_launch), "mean_neighbours": round(kbar, 4)}
     print("[bench] iteration kernel %.2f us/launch (%.2f us apart back to back), %.1f GB/s algorithmic"

@@ -61,6 +61,11 @@ typedef enum {
 #define PBDR_FLAG_NO_ANG_MOM 0x4u    /* drop the angular momentum correction, Eq. (5)  */
 #define PBDR_FLAG_NO_GRAPH 0x10u     /* enqueue kernels directly instead of replaying a
                                         captured HIP graph per frame                    */
+#define PBDR_FLAG_ITERATION_LAUNCHES 0x20u  /* one launch per solver iteration even when the
+                                        scene's iteration grid fits the GPU at once (the
+                                        one-launch form needs every workgroup resident:
+                                        scenes stepped concurrently on other streams
+                                        should set this)                                */
 #define PBDR_PP_AVG_MAX (0u << 8)    /* pair correction / max(n_p, n_q)  (default)      */
 #define PBDR_PP_AVG_OWN (1u << 8)    /* pair correction / n_p                           */
 #define PBDR_PP_AVG_NONE (2u << 8)   /* pair corrections summed                         */
@@ -131,8 +136,11 @@ typedef struct {
     int32_t waves_per_block;      /* iteration kernel: 64-lane waves per workgroup */
     int32_t iteration_blocks;     /* iteration kernel: workgroups per launch */
     int32_t max_body_particles;
-    int32_t iteration_kernel;     /* 0: register-rich variant; 1: 80-VGPR variant, taken
-                                     when the grid oversubscribes the GPU */
+    int32_t iteration_kernel;     /* 0: register-rich variant, one launch per iteration;
+                                     1: 80-VGPR variant, taken when the grid
+                                     oversubscribes the GPU; 2: all K iterations of a
+                                     substep in one launch (small scenes: at most half
+                                     as many workgroups as CUs, all resident) */
     size_t workspace_bytes;
 } pbdr_scene_info;
 
@@ -230,10 +238,13 @@ enum {
 pbdr_status pbdr_scene_read_debug(pbdr_scene* scene, int32_t what, void* dst_host);
 
 /* Measurement aid: enqueues n_launches back-to-back launches of the solver
- * iteration kernel (one Jacobi iteration of Alg. 1 over all bodies) on the
- * buffers of the last substep, as the substep itself does K times.  The state
- * (x, v) is unchanged; the next substep overwrites the iteration buffers.
- * Requires at least one completed substep (else PBDR_ERR_STATE). */
+ * iteration kernel on the buffers of the last substep.  A launch is one Jacobi
+ * iteration of Alg. 1 over all bodies, as the substep itself does K times; for
+ * a scene whose substep runs all K iterations as one launch (iteration_kernel
+ * 2 in pbdr_scene_info), it is that launch (preceded by a small kernel that
+ * resets the launch's synchronisation flags).  The state (x, v) is unchanged;
+ * the next substep overwrites the iteration buffers.  Requires at least one
+ * completed substep (else PBDR_ERR_STATE). */
 pbdr_status pbdr_scene_launch_iterations(pbdr_scene* scene, int32_t n_launches);
 
 /* Measurement aid: as pbdr_scene_launch_iterations, with a pair of HIP events

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpbdr.so")
 
 OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_DEVICE, ERR_CAPACITY, ERR_NONFINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 FLAG_STD_VELOCITY, FLAG_NO_LIN_MOM, FLAG_NO_ANG_MOM, FLAG_NO_GRAPH = 0x1, 0x2, 0x4, 0x10
+FLAG_ITERATION_LAUNCHES = 0x20
 PP_AVG_MAX, PP_AVG_OWN, PP_AVG_NONE = 0, 1 << 8, 2 << 8
 DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3, 4, 5
 DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8

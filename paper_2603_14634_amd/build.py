@@ -19,9 +19,11 @@ SOURCES = ["pbdr_kernels.hip", "pbdr_pool_kernels.hip", "pbdr_state.hip", "pbdr_
            "pbdr_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# The pool kernel is instantiated for several launch shapes; contraction only
-# within one source expression keeps its rounding identical in all of them.
-EXTRA_FLAGS = {"pbdr_pool_kernels.hip": ["-ffp-contract=on"]}
+# Contraction only within one source expression keeps the rounding of the same
+# arithmetic identical wherever it is instantiated: the pool kernel in its
+# several launch shapes, the solver iteration in its per-iteration, multi-scene
+# and one-launch kernels.
+EXTRA_FLAGS = {"pbdr_pool_kernels.hip": ["-ffp-contract=on"], "pbdr_kernels.hip": ["-ffp-contract=on"]}
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

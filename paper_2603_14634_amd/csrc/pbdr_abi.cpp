@@ -92,7 +92,7 @@ using pbdr::host::g_err;
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
         sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
-        body_wave0, block_body, body_mq, body_out, total;
+        body_wave0, block_body, iter_flags, body_mq, body_out, total;
 };
 
 // Upper bound on the padded wave count of the iteration kernel's body packing
@@ -147,6 +147,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.wave_body = take(4 * max_iteration_waves(n, nb));
     L.body_wave0 = take(4 * B);
     L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 2));
+    L.iter_flags = take(4 * (max_iteration_waves(n, nb) / 4 + 2));
     L.body_mq = take(12 * B);
     L.body_out = take(18 * sizeof(double) * B);
     L.total = off;
@@ -305,6 +306,8 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.wave_body = (const int32_t*)(w + L.wave_body);
     d.body_wave0 = (const int32_t*)(w + L.body_wave0);
     d.block_body = (const int32_t*)(w + L.block_body);
+    d.iter_flags = (uint32_t*)(w + L.iter_flags);
+    d.resident_iterate = 0;
     d.body_mq = (const float*)(w + L.body_mq);
     d.pscene = nullptr;                   // one scene
     d.mscene = nullptr;
@@ -483,6 +486,15 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         delete s;
         return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
     }
+    // all iterations of a substep in one launch for small scenes: every
+    // workgroup of the single iteration launch must be resident at once, and
+    // the launch pays off where the gaps between dependent launches dominate
+    // (up to half as many workgroups as CUs; measured: 512 particles +36 %,
+    // 171k particles in 464 workgroups -1.7 %)
+    if (!s->split && !s->dev.dense_iterate && !(s->res.p.flags & PBDR_FLAG_ITERATION_LAUNCHES) &&
+        s->dev.n_iter_blocks > 0 && s->dev.n_iter_blocks <= cus / 2 &&
+        s->dev.n_iter_blocks <= pbdr::resident_iterate_capacity(s->dev.waves_per_block))
+        s->dev.resident_iterate = 1;
     s->dev2 = s->dev;
     if (s->split) {
         s->dev2.wave_body = s->dev.wave_body + wave_body.size();
@@ -592,7 +604,8 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
     if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
-    hipError_t e = pbdr::enqueue_iterations(s->dev, second_launch(s), s->consts, n_launches, s->stream);
+    hipError_t e = pbdr::enqueue_iterations(s->dev, second_launch(s), s->consts, s->res.p.iterations, n_launches,
+                                            s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return PBDR_OK;
 }
@@ -616,8 +629,8 @@ pbdr_status pbdr_scene_time_iterations(pbdr_scene* s, int32_t n_launches, float*
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     if (e == hipSuccess)
-        e = pbdr::enqueue_iterations_timed(s->dev, second_launch(s), s->consts, n_launches, s->stream, ev.data(),
-                                           ev.data() + n_launches);
+        e = pbdr::enqueue_iterations_timed(s->dev, second_launch(s), s->consts, s->res.p.iterations, n_launches,
+                                           s->stream, ev.data(), ev.data() + n_launches);
     if (e == hipSuccess) e = hipEventSynchronize(ev.back());
     for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) {
         float ms = 0.0f;
@@ -771,7 +784,7 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->waves_per_block = s->dev.waves_per_block;
     out->iteration_blocks = s->dev.n_iter_blocks + (s->split ? s->dev2.n_iter_blocks : 0);
     out->max_body_particles = s->max_body;
-    out->iteration_kernel = s->dev.dense_iterate;
+    out->iteration_kernel = s->dev.resident_iterate ? 2 : s->dev.dense_iterate;
     out->workspace_bytes = s->lay.total;
     return PBDR_OK;
 }

@@ -111,6 +111,10 @@ struct Scene {
     const MultiScene* mscene; // [S]
     int32_t n_extent;         // launch extent: particles 0 .. n_extent - 1 may be stepped
     int32_t n_active;         // particles stepped by the current launches
+    // one-launch iterations (single scene whose iteration grid is resident at
+    // once): per-workgroup count of published iterations, reset each substep
+    uint32_t* iter_flags = nullptr;   // [n_iter_blocks]
+    int32_t resident_iterate = 0;     // 1: the K iterations run as one launch
 };
 
 // Enqueues `count` substeps of K = iterations solver iterations.  s2 (or
@@ -120,13 +124,20 @@ struct Scene {
 hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                             hipStream_t stream);
 
-// Enqueues `count` iterations of the iteration kernel(s) alone (measurement);
-// all but the first continue from the rotation of the iteration before.
-hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int count, hipStream_t stream);
+// Workgroups of the one-launch iteration kernel (64 waves_per_block threads)
+// that the GPU holds at once; 0 if it cannot be queried.
+int resident_iterate_capacity(int waves_per_block);
 
-// As enqueue_iterations, iteration `it` bound to the events t0[it] (begin of
-// its first launch) and t1[it] (end of its last).
-hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int count,
+// Enqueues `count` launches of the iteration kernel(s) alone (measurement):
+// one Jacobi iteration each (all but the first continue from the rotation of
+// the one before), or, for a scene whose substep runs its `iterations`
+// iterations as one launch, that launch.
+hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+                              hipStream_t stream);
+
+// As enqueue_iterations, launch `k` bound to the events t0[k] (begin of its
+// first kernel) and t1[k] (end of its last).
+hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1);
 
 // Writes the canonical (key, id) order of the last substep into `sorted`.

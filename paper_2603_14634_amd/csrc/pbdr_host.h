@@ -15,7 +15,7 @@ struct StepConsts;
 namespace host {
 
 constexpr uint32_t kKnownFlags = PBDR_FLAG_STD_VELOCITY | PBDR_FLAG_NO_LIN_MOM | PBDR_FLAG_NO_ANG_MOM |
-                                 PBDR_FLAG_NO_GRAPH | PBDR_PP_AVG_MASK;
+                                 PBDR_FLAG_NO_GRAPH | PBDR_FLAG_ITERATION_LAUNCHES | PBDR_PP_AVG_MASK;
 constexpr int32_t kMaxParticles = 1 << 28;
 constexpr int kMinHashBits = 6, kMaxHashBits = 28;
 

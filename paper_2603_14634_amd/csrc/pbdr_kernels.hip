@@ -75,6 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
+    if (!MULTI && s.iter_flags && i < s.n_iter_blocks) s.iter_flags[i] = 0u;   // one-launch iterations
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     const MultiScene* ms = nullptr;
@@ -411,6 +412,44 @@ k_neighbours(Scene s, StepConsts c)
 // one Jacobi iteration (Alg. 1 loop body)
 // ---------------------------------------------------------------------------
 
+// Contact with a particle of another body (constraint (2)) from X_i: the
+// mass-weighted split of the penetration, Coulomb friction from the relative
+// displacement since X_init, and the pair weight of the averaging mode.  xq,
+// dq: the partner's X_init and X_i - X_init; mq, nq: its mass and list length.
+// Shared by both iteration kernels, with contraction limited to single
+// expressions, so that both round alike.
+__device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t avg, float mu, const float* x0,
+                                                const float* del, float m, uint32_t ni, const float* xq,
+                                                const float* dq, float mq, uint32_t nq, float* Cd)
+{
+#pragma clang fp contract(on)
+    float d[3], u[3];
+    for (int j = 0; j < 3; ++j) {
+        d[j] = (x0[j] - xq[j]) + (del[j] - dq[j]);
+        u[j] = del[j] - dq[j];
+    }
+    const float l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const float l = __builtin_amdgcn_sqrtf(l2);
+    if (!(l > 0.0f) || !(l < c.two_r)) return;
+    const float il = frcp(l);
+    const float nx = d[0] * il, ny = d[1] * il, nz = d[2] * il;
+    const float pen = c.two_r - l;
+    const float alpha = mq * frcp(m + mq);          // w_p / (w_p + w_q)
+    const float un = u[0] * nx + u[1] * ny + u[2] * nz;
+    const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
+    const float ut2 = ux * ux + uy * uy + uz * uz;
+    const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+    float wgt = 1.0f;
+    if (avg == 0u)
+        wgt = frcp((float)(ni > nq ? ni : nq));
+    else if (avg == 1u)
+        wgt = frcp((float)ni);
+    const float sc = alpha * wgt;
+    Cd[0] += sc * (pen * nx - f * ux);
+    Cd[1] += sc * (pen * ny - f * uy);
+    Cd[2] += sc * (pen * nz - f * uz);
+}
+
 // Sum of the per-wave partials (NV float4 per wave) of a body's waves w0 ..
 // w0 + nw - 1, in wave order; the LDS reads of U waves are issued together.
 template <int NV, int U>
@@ -526,35 +565,12 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
         for (uint32_t sl = 0; sl < cnt; ++sl) {
             const uint32_t jq = s.nbr[sl * n + i];
-            float d[3], u[3];
+            float xq[3], dq[3];
             for (int j = 0; j < 3; ++j) {
-                const float dj = dl[j * n + jq];
-                d[j] = (x0[j] - s.x[j * n + jq]) + (del[j] - dj);
-                u[j] = del[j] - dj;
+                xq[j] = s.x[j * n + jq];
+                dq[j] = dl[j * n + jq];
             }
-            const float l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            const float l = __builtin_amdgcn_sqrtf(l2);
-            if (!(l > 0.0f) || !(l < c.two_r)) continue;
-            const float il = frcp(l);
-            const float nx = d[0] * il, ny = d[1] * il, nz = d[2] * il;
-            const float pen = c.two_r - l;
-            const float mq = s.mass[jq];
-            const float alpha = mq * frcp(m + mq);          // w_p / (w_p + w_q)
-            const float un = u[0] * nx + u[1] * ny + u[2] * nz;
-            const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
-            const float ut2 = ux * ux + uy * uy + uz * uz;
-            const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
-            float wgt = 1.0f;
-            if (avg == 0u) {
-                const uint32_t nq = s.nbr_n[jq];
-                wgt = frcp((float)(ni > nq ? ni : nq));
-            } else if (avg == 1u) {
-                wgt = frcp((float)ni);
-            }
-            const float sc = alpha * wgt;
-            Cd[0] += sc * (pen * nx - f * ux);
-            Cd[1] += sc * (pen * ny - f * uy);
-            Cd[2] += sc * (pen * nz - f * uz);
+            pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
         }
     }
 
@@ -710,6 +726,273 @@ k_iterate_dense(Scene s, StepConsts c, int src, int it)
     iterate_body<false, 2, 2>(s, c, src, it);
 }
 
+// ---------------------------------------------------------------------------
+// all K iterations of a substep in one launch
+// ---------------------------------------------------------------------------
+
+// For a scene whose iteration grid the GPU holds at once (checked on the host
+// from the kernel's occupancy), the K Jacobi iterations of a substep run in
+// one launch.  A workgroup keeps its particles' state in registers across the
+// iterations and synchronises only with the workgroups that hold its
+// particles' contact partners: before iteration it reads a partner's X_it it
+// waits until the partner's workgroup has published the end of iteration
+// it - 1 in its own flag.  Partner positions are written and read with
+// agent-scope atomic accesses (coherent across the XCDs' L2 caches), the
+// flag only after those stores have completed.  Waiting for a partner's previous
+// iteration also orders the reuse of the double buffer: a partner has read
+// X_{it-1} before it publishes, and X_{it+1} overwrites it only after that.
+// A workgroup whose particles have no partners in other bodies never waits.
+// Every wait is bounded: one that gives up latches kErrInternal instead of
+// hanging.  The arithmetic is that of iterate_body, in the same order.
+constexpr uint32_t kWaitLimit = 1u << 20;
+
+__device__ inline float coherent_load(const float* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, StepConsts c, int K)
+{
+    constexpr int NSM = 12, NMOM = 24;
+    __shared__ float4 red_sm[kMaxWaves * NSM / 4];
+    __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
+    __shared__ float body_sm[kMaxWaves * 12];
+    __shared__ float body_mom[kMaxWaves * 9];
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int blk = xcd_block();
+    const int W = s.waves_per_block;
+    const int g = blk * W + wave;
+    const int b = s.wave_body[g];                 // -1: idle wave
+    const int blk_b0 = s.block_body[2 * blk], blk_nb = s.block_body[2 * blk + 1];
+    int s0 = 0, e0 = 0, lw0 = wave;
+    if (b >= 0) {
+        s0 = s.body_start[b];
+        e0 = s.body_start[b + 1];
+        lw0 = s.body_wave0[b] - blk * W;
+    }
+    const int lb = b >= blk_b0 ? b - blk_b0 : 0;
+    const int i = s0 + (wave - lw0) * 64 + lane;
+    const bool act = b >= 0 && i < e0;
+    const size_t n = (size_t)s.n;
+    const float ax = s.x[s0], ay = s.x[n + s0], az = s.x[2 * n + s0];   // body anchor
+    const uint32_t avg = (c.flags >> kAvgShift) & 3u;
+
+    const bool body_lane = wave == 0 && lane < blk_nb;
+    const int bb = blk_b0 + (body_lane ? lane : 0);
+    int bl_w0 = 0, bl_nw = 0;
+    float bl_M = 1.0f, Rprev[9], mq3[3];
+    if (body_lane) {
+        bl_w0 = s.body_wave0[bb] - blk * W;
+        bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
+        bl_M = s.body_mass[bb];
+        for (int j = 0; j < 3; ++j) mq3[j] = s.body_mq[3 * (size_t)bb + j];
+    }
+
+    // X_0 - X_init and V_0 from the integration step; the rest is constant
+    float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
+    float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f;
+    uint32_t ni = 0u;
+    if (act) {
+        for (int j = 0; j < 3; ++j) {
+            x0[j] = s.x[j * n + i];
+            del[j] = s.dl[0][j * n + i];
+            V[j] = s.vel[0][j * n + i];
+            q[j] = s.q[j * n + i];
+        }
+        m = s.mass[i];
+        ni = s.nbr_n[i];
+    }
+    const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
+    const float mu = c.mu;
+
+    for (int it = 0; it < K; ++it) {
+        const float* dl = s.dl[it & 1];           // X_it - X_init of the contact partners
+        float Cd[3] = {0.0f, 0.0f, 0.0f};
+        if (act) {
+            for (int pl = 0; pl < c.n_planes; ++pl) {
+                const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
+                const float un = nx * del[0] + ny * del[1] + nz * del[2];
+                const float e = ((nx * x0[0] + ny * x0[1] + nz * x0[2]) - c.plane_d[pl]) + un;
+                if (!(e < c.radius)) continue;
+                const float pen = c.radius - e;
+                const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
+                const float ut2 = ux * ux + uy * uy + uz * uz;
+                const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+                Cd[0] += pen * nx - f * ux;
+                Cd[1] += pen * ny - f * uy;
+                Cd[2] += pen * nz - f * uz;
+            }
+            for (uint32_t sl = 0; sl < cnt; ++sl) {
+                const uint32_t jq = s.nbr[sl * n + i];
+                if (it > 0) {                         // the partner's iteration it - 1 is published
+                    const int wq = s.body_wave0[s.body[jq]] / W;
+                    uint32_t spins = 0;
+                    while (__hip_atomic_load(&s.iter_flags[wq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                           (uint32_t)it) {
+                        if (++spins > kWaitLimit) {
+                            atomicOr(&s.counters->err, kErrInternal);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                float xq[3], dq[3];
+                for (int j = 0; j < 3; ++j) {
+                    xq[j] = s.x[j * n + jq];
+                    dq[j] = coherent_load(&dl[j * n + jq]);
+                }
+                pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
+            }
+        }
+
+        float y[3];
+        y[0] = (x0[0] - ax) + del[0];
+        y[1] = (x0[1] - ay) + del[1];
+        y[2] = (x0[2] - az) + del[2];
+        {
+            float S[NSM];
+            for (int j = 0; j < 3; ++j) S[j] = m * y[j];
+            for (int a = 0; a < 3; ++a)
+                for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
+            wave_sums_by_row<NSM>(S);
+            if ((lane & 15) == 15) {
+                float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
+                for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
+            }
+        }
+        __syncthreads();
+        if (body_lane) {
+            float T[NSM];
+            sum_wave_partials<NSM / 4, 4>(red_sm, bl_w0, bl_nw, T);
+            const float im = frcp(bl_M);
+            float cc[3], A[9], Rb[9];
+            for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
+            for (int a = 0; a < 3; ++a)
+                for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+            if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
+            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rprev[j] = Rb[j];
+            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+        }
+        __syncthreads();
+        float R[9], cyv[3];
+        for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+        for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
+
+        float r[3], Dd[3];
+        for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
+        for (int a = 0; a < 3; ++a)
+            Dd[a] = act ? (R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2]) - r[a] : 0.0f;
+        {
+            float S[NMOM];
+            float zb[3], za[3], vb[3], t[3];
+            for (int j = 0; j < 3; ++j) {
+                zb[j] = r[j] + Cd[j];
+                za[j] = zb[j] + Dd[j];
+                vb[j] = V[j] + Cd[j] * c.inv_h;
+                S[j] = m * Cd[j];
+                S[3 + j] = m * Dd[j];
+                S[6 + j] = m * vb[j];
+            }
+            cross(zb, Dd, t);
+            for (int j = 0; j < 3; ++j) S[9 + j] = m * t[j];
+            cross(Dd, vb, t);
+            for (int j = 0; j < 3; ++j) S[12 + j] = m * t[j];
+            S[15] = m * (za[1] * za[1] + za[2] * za[2]);
+            S[16] = m * (za[0] * za[0] + za[2] * za[2]);
+            S[17] = m * (za[0] * za[0] + za[1] * za[1]);
+            S[18] = -m * za[0] * za[1];
+            S[19] = -m * za[0] * za[2];
+            S[20] = -m * za[1] * za[2];
+            S[21] = S[22] = S[23] = 0.0f;
+            wave_sums_by_row<NMOM>(S);
+            if ((lane & 15) == 15) {
+                float* dst = (float*)red_mom + wave * NMOM + (lane >> 4) * (NMOM / 4);
+                for (int j = 0; j < NMOM / 4; ++j) dst[j] = S[j];
+            }
+        }
+        __syncthreads();
+        if (body_lane) {
+            float T[NMOM];
+            sum_wave_partials<NMOM / 4, 4>(red_mom, bl_w0, bl_nw, T);
+            const float Mb = bl_M, im = frcp(Mb);
+            float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
+            for (int j = 0; j < 3; ++j) {
+                cb[j] = T[j] * im;
+                Db[j] = T[3 + j] * im;
+                cab[j] = cb[j] + Db[j];
+            }
+            if (!(c.flags & kFlagNoLinMom))
+                for (int j = 0; j < 3; ++j) dvb[j] = -T[3 + j] * c.inv_h * im;
+            if (!(c.flags & kFlagNoAngMom)) {
+                float cbxD[3], DbxP[3], dL[3], I6[6];
+                cross(cb, &T[3], cbxD);
+                cross(Db, &T[6], DbxP);
+                for (int j = 0; j < 3; ++j) dL[j] = (T[9 + j] - cbxD[j]) * c.inv_h + T[12 + j] - DbxP[j];
+                I6[0] = T[15] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
+                I6[1] = T[16] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
+                I6[2] = T[17] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
+                I6[3] = T[18] + Mb * cab[0] * cab[1];
+                I6[4] = T[19] + Mb * cab[0] * cab[2];
+                I6[5] = T[20] + Mb * cab[1] * cab[2];
+                const float scale = fmaxf(I6[0] + I6[1] + I6[2], Mb * c.two_r * c.two_r);
+                solve_inertia(I6, dL, scale, wb);
+            }
+            for (int j = 0; j < 3; ++j) {
+                body_mom[lane * 9 + j] = dvb[j];
+                body_mom[lane * 9 + 3 + j] = wb[j];
+                body_mom[lane * 9 + 6 + j] = cab[j];
+            }
+        }
+        __syncthreads();
+        if (act) {
+            float dv[3], w[3], ca[3], ra[3], wr[3];
+            for (int j = 0; j < 3; ++j) {
+                dv[j] = body_mom[lb * 9 + j];
+                w[j] = body_mom[lb * 9 + 3 + j];
+                ca[j] = body_mom[lb * 9 + 6 + j];
+            }
+            for (int j = 0; j < 3; ++j) ra[j] = r[j] + Cd[j] + Dd[j] - ca[j];
+            cross(w, ra, wr);
+            for (int j = 0; j < 3; ++j) {
+                const float step = Cd[j] + Dd[j];
+                const float dvi = dv[j] - wr[j];
+                const float dnew = (del[j] + step) + c.h * dvi;
+                if (c.flags & kFlagStdVelocity) {
+                    const float xw = x0[j] + dnew;
+                    V[j] = (xw - x0[j]) * c.inv_h;
+                } else {
+                    V[j] = (V[j] + step * c.inv_h) + dvi;
+                }
+                del[j] = dnew;
+            }
+        }
+        if (it + 1 < K) {           // publish X_{it+1} of the particles that partners read
+            float* dn = s.dl[(it + 1) & 1];
+            if (act && cnt > 0u)
+                for (int j = 0; j < 3; ++j)
+                    __hip_atomic_store(&dn[j * n + i], del[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // the positions are agent-coherent stores: waiting for their
+            // completion orders them before the flag (no L2 write-back needed)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_store(&s.iter_flags[blk], (uint32_t)(it + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // X_K - X_init and V_K where the finalize step reads them
+    if (act) {
+        float* dn = s.dl[K & 1];
+        float* vn = s.vel[K & 1];
+        for (int j = 0; j < 3; ++j) {
+            dn[j * n + i] = del[j];
+            vn[j * n + i] = V[j];
+        }
+    }
+    if (body_lane && s.body_rot)
+        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rprev[j];
+}
+
 // Canonical (key, id) order from the key grouping of the last substep: the
 // grouping keeps an arbitrary order inside a key (slots from atomic ranks);
 // particle i goes to its key's first slot plus the number of smaller ids
@@ -757,6 +1040,12 @@ __global__ void __launch_bounds__(kBlock) k_clear_counters(Counters* c, NbrStats
         st[i].sum = 0ull;
         st[i].rows = 0ull;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_reset_iter_flags(uint32_t* f, int32_t n)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) f[i] = 0u;
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
@@ -817,9 +1106,19 @@ hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int count, hipStream_t stream)
+hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+                              hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
+    if (s.resident_iterate) {       // each launch: all K iterations
+        for (int k = 0; k < count; ++k) {
+            hipLaunchKernelGGL(k_reset_iter_flags, dim3(blocks_for((size_t)s.n_iter_blocks)), dim3(kBlock), 0, stream,
+                               s.iter_flags, s.n_iter_blocks);
+            hipLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s,
+                               c, iterations);
+        }
+        return hipGetLastError();
+    }
     int src = 0;
     for (int it = 0; it < count; ++it) {
         launch_iterate(s, c, src, it, stream);
@@ -829,10 +1128,19 @@ hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts&
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int count,
+hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
+    if (s.resident_iterate) {       // each launch: all K iterations; the flag reset is outside the events
+        for (int k = 0; k < count; ++k) {
+            hipLaunchKernelGGL(k_reset_iter_flags, dim3(blocks_for((size_t)s.n_iter_blocks)), dim3(kBlock), 0, stream,
+                               s.iter_flags, s.n_iter_blocks);
+            hipExtLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream,
+                                  t0[k], t1[k], 0, s, c, iterations);
+        }
+        return hipGetLastError();
+    }
     int src = 0;
     for (int it = 0; it < count; ++it) {
         if (s2) {       // one iteration = both launches: begin of the first, end of the second
@@ -844,6 +1152,17 @@ hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepC
         src ^= 1;
     }
     return hipGetLastError();
+}
+
+int resident_iterate_capacity(int waves_per_block)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iterate_resident, 64 * waves_per_block, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
 }
 
 hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
@@ -873,6 +1192,11 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
             hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
             hipLaunchKernelGGL(k_scatter<false>, dim3(nb), dim3(kBlock), 0, stream, s);
             hipLaunchKernelGGL(k_neighbours<false>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+        }
+        if (!multi && s.resident_iterate) {
+            hipLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s,
+                               c, iterations);
+            continue;
         }
         int src = 0;
         for (int it = 0; it < iterations; ++it) {

@@ -224,7 +224,7 @@ def test_cuboid_rain_16_substeps_of_the_first_40_frames(orc):
     frames, each from the reference state rounded to FP32."""
     sc = scenes.cuboid_rain(0)
     s = _gpu_solver(sc)
-    assert s.info().iteration_kernel == 0      # the grid fits the GPU at once
+    assert s.info().iteration_kernel == 0      # the grid fits the GPU at once; too large for the one-launch form
     picks = [int(round(k)) for k in np.linspace(0, 40 * sc.substeps - 1, 16)]
     assert max(_sampled_gate(orc, sc, picks, s, "cuboid_rain")) >= 1
 
@@ -430,6 +430,29 @@ def test_split_iteration_launches_graph_equals_direct_launches():
         del s
     np.testing.assert_array_equal(runs[1][0], runs[0][0])
     np.testing.assert_array_equal(runs[1][1], runs[0][1])
+
+
+@pytest.mark.parametrize("scene", ["drop_cubes", "touching"])
+def test_one_launch_iterations_equal_iteration_launches(scene):
+    """The K iterations of a substep as one launch (workgroups waiting only
+    for their contact partners) give the same state as K launches."""
+    sc = scenes.drop_cubes(0) if scene == "drop_cubes" else _touching_bodies([511, 513, 64, 1, 7, 300, 300])
+    frames = 60 if scene == "drop_cubes" else 3
+    out = []
+    for flags in (0, B.FLAG_ITERATION_LAUNCHES, 0):      # the one-launch run twice: no race
+        s = B.Solver(B.params_for(sc, flags=flags), sc.x, sc.v, sc.mass, sc.body_start)
+        assert s.info().iteration_kernel == (2 if flags == 0 else 0)
+        s.step(frames)
+        out.append(s.read_state())
+        s.check()
+        s.close()
+    dx = float(np.abs(out[0][0].astype(np.float64) - out[1][0]).max())
+    dv = float(np.abs(out[0][1].astype(np.float64) - out[1][1]).max())
+    print("[one-launch] %s %d frames: max |dx| %.3g  max |dv| %.3g" % (scene, frames, dx, dv), flush=True)
+    np.testing.assert_array_equal(out[0][0], out[2][0])
+    np.testing.assert_array_equal(out[0][1], out[2][1])
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
 
 
 def test_checkpoint_resume_is_bit_identical():
