@@ -139,8 +139,8 @@ typedef struct {
     int32_t iteration_kernel;     /* 0: register-rich variant, one launch per iteration;
                                      1: 80-VGPR variant, taken when the grid
                                      oversubscribes the GPU; 2: all K iterations of a
-                                     substep in one launch (small scenes: at most half
-                                     as many workgroups as CUs, all resident) */
+                                     substep in one launch (the grid is resident at
+                                     once, K < 64) */
     size_t workspace_bytes;
 } pbdr_scene_info;
 

@@ -92,7 +92,7 @@ using pbdr::host::g_err;
 struct Layout {
     size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
         sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
-        body_wave0, block_body, iter_flags, body_mq, body_out, total;
+        body_wave0, block_body, tagged, body_mq, body_out, total;
 };
 
 // Upper bound on the padded wave count of the iteration kernel's body packing
@@ -147,7 +147,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.wave_body = take(4 * max_iteration_waves(n, nb));
     L.body_wave0 = take(4 * B);
     L.block_body = take(8 * (max_iteration_waves(n, nb) / 4 + 2));
-    L.iter_flags = take(4 * (max_iteration_waves(n, nb) / 4 + 2));
+    L.tagged = take(48 * N);
     L.body_mq = take(12 * B);
     L.body_out = take(18 * sizeof(double) * B);
     L.total = off;
@@ -306,7 +306,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.wave_body = (const int32_t*)(w + L.wave_body);
     d.body_wave0 = (const int32_t*)(w + L.body_wave0);
     d.block_body = (const int32_t*)(w + L.block_body);
-    d.iter_flags = (uint32_t*)(w + L.iter_flags);
+    d.tagged = (unsigned long long*)(w + L.tagged);
     d.resident_iterate = 0;
     d.body_mq = (const float*)(w + L.body_mq);
     d.pscene = nullptr;                   // one scene
@@ -486,13 +486,11 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         delete s;
         return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
     }
-    // all iterations of a substep in one launch for small scenes: every
-    // workgroup of the single iteration launch must be resident at once, and
-    // the launch pays off where the gaps between dependent launches dominate
-    // (up to half as many workgroups as CUs; measured: 512 particles +36 %,
-    // 171k particles in 464 workgroups -1.7 %)
+    // all iterations of a substep in one launch when every workgroup of the
+    // single iteration launch is resident at once (and K fits the 6-bit
+    // iteration field of the tags)
     if (!s->split && !s->dev.dense_iterate && !(s->res.p.flags & PBDR_FLAG_ITERATION_LAUNCHES) &&
-        s->dev.n_iter_blocks > 0 && s->dev.n_iter_blocks <= cus / 2 &&
+        s->dev.n_iter_blocks > 0 && s->res.p.iterations < 64 &&
         s->dev.n_iter_blocks <= pbdr::resident_iterate_capacity(s->dev.waves_per_block))
         s->dev.resident_iterate = 1;
     s->dev2 = s->dev;
@@ -548,6 +546,8 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     }
     if (e == hipSuccess) e = pbdr::enqueue_clear_counters(s->dev, s->stream);
     if (e == hipSuccess) e = pbdr::enqueue_init_tables(s->dev, s->stream);
+    // one-launch iterations: no tag may match before it is written
+    if (e == hipSuccess) e = hipMemsetAsync(s->dev.tagged, 0, 48 * (size_t)n, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
         delete s;

@@ -25,7 +25,7 @@ enum : uint32_t {
 // Device-side error bits, latched until read by the host.
 struct Counters {
     uint32_t err;                  // kErr* bits
-    uint32_t pad;
+    uint32_t epoch;                // substeps begun (one-launch iterations tag their data with it)
 };
 
 // Neighbour-list statistics, one slot per neighbour-kernel workgroup (no
@@ -112,9 +112,10 @@ struct Scene {
     int32_t n_extent;         // launch extent: particles 0 .. n_extent - 1 may be stepped
     int32_t n_active;         // particles stepped by the current launches
     // one-launch iterations (single scene whose iteration grid is resident at
-    // once): per-workgroup count of published iterations, reset each substep
-    uint32_t* iter_flags = nullptr;   // [n_iter_blocks]
-    int32_t resident_iterate = 0;     // 1: the K iterations run as one launch
+    // once): X_i - X_init of particles with contact partners, each component
+    // with the tag of its iteration, (tag << 32) | float bits, double buffered
+    unsigned long long* tagged = nullptr;   // [2][3][N]
+    int32_t resident_iterate = 0;           // 1: the K iterations run as one launch
 };
 
 // Enqueues `count` substeps of K = iterations solver iterations.  s2 (or

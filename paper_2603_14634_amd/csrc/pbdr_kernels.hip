@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
-    if (!MULTI && s.iter_flags && i < s.n_iter_blocks) s.iter_flags[i] = 0u;   // one-launch iterations
+    if (!MULTI && i == 0) s.counters->epoch += 1u;      // a new substep: fresh tags for one-launch iterations
     if (i >= s.n) return;
     const size_t n = (size_t)s.n;
     const MultiScene* ms = nullptr;
@@ -733,26 +733,26 @@ k_iterate_dense(Scene s, StepConsts c, int src, int it)
 // For a scene whose iteration grid the GPU holds at once (checked on the host
 // from the kernel's occupancy), the K Jacobi iterations of a substep run in
 // one launch.  A workgroup keeps its particles' state in registers across the
-// iterations and synchronises only with the workgroups that hold its
-// particles' contact partners: before iteration it reads a partner's X_it it
-// waits until the partner's workgroup has published the end of iteration
-// it - 1 in its own flag.  Partner positions are written and read with
-// agent-scope atomic accesses (coherent across the XCDs' L2 caches), the
-// flag only after those stores have completed.  Waiting for a partner's previous
-// iteration also orders the reuse of the double buffer: a partner has read
-// X_{it-1} before it publishes, and X_{it+1} overwrites it only after that.
-// A workgroup whose particles have no partners in other bodies never waits.
-// Every wait is bounded: one that gives up latches kErrInternal instead of
-// hanging.  The arithmetic is that of iterate_body, in the same order.
+// iterations.  A particle with contact partners publishes each component of
+// its X_{it+1} - X_init as one 64-bit word, the value's bits under a tag that
+// names the substep and the iteration, with an agent-scope (XCD-coherent)
+// atomic store; a partner reading X_it polls the word with agent-scope
+// atomic loads until the tag is that of iteration it.  Value and readiness
+// travel together, so a read costs one memory round trip once the value is
+// there.  Waiting for a partner's X_it also orders the reuse of the double
+// buffer: the partner wrote X_it after it had read this particle's X_{it-1},
+// so X_{it+1} can replace X_{it-1}.  Particles without partners in other
+// bodies never wait.  Every wait is bounded: one that gives up latches
+// kErrInternal instead of hanging.  The arithmetic is that of iterate_body,
+// in the same order.
 constexpr uint32_t kWaitLimit = 1u << 20;
 
-__device__ inline float coherent_load(const float* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// tag of X_it in substep `epoch` (K < 64 iterations; tags repeat after 2^26 substeps)
+__device__ inline uint32_t iter_tag(uint32_t epoch, int it) { return (epoch << 6) | (uint32_t)it; }
 
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, StepConsts c, int K)
 {
+    constexpr int PG = 4;                // contact partners whose positions are loaded together
     constexpr int NSM = 12, NMOM = 24;
     __shared__ float4 red_sm[kMaxWaves * NSM / 4];
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
@@ -805,9 +805,10 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     }
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
     const float mu = c.mu;
+    const uint32_t epoch = s.counters->epoch;
 
     for (int it = 0; it < K; ++it) {
-        const float* dl = s.dl[it & 1];           // X_it - X_init of the contact partners
+        const unsigned long long* tg = s.tagged + (size_t)(it & 1) * 3 * n;   // partners' X_it, tagged
         float Cd[3] = {0.0f, 0.0f, 0.0f};
         if (act) {
             for (int pl = 0; pl < c.n_planes; ++pl) {
@@ -823,26 +824,44 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                 Cd[1] += pen * ny - f * uy;
                 Cd[2] += pen * nz - f * uz;
             }
-            for (uint32_t sl = 0; sl < cnt; ++sl) {
-                const uint32_t jq = s.nbr[sl * n + i];
-                if (it > 0) {                         // the partner's iteration it - 1 is published
-                    const int wq = s.body_wave0[s.body[jq]] / W;
+            // partners PG at a time: their tagged words are loaded together
+            // and polled again only while a tag is not yet that of X_it
+            const uint32_t want = iter_tag(epoch, it);
+            for (uint32_t sl = 0; sl < cnt; sl += PG) {
+                uint32_t jq[PG];
+                float xq[PG][3], dq[PG][3];
+                for (int g = 0; g < PG; ++g) {
+                    jq[g] = sl + g < cnt ? s.nbr[(sl + g) * n + i] : s.nbr[sl * n + i];
+                    for (int j = 0; j < 3; ++j) xq[g][j] = s.x[j * n + jq[g]];
+                }
+                if (it == 0) {                        // X_0 from the integration step
+                    for (int g = 0; g < PG; ++g)
+                        for (int j = 0; j < 3; ++j) dq[g][j] = s.dl[0][j * n + jq[g]];
+                } else {
+                    unsigned long long w[PG][3];
                     uint32_t spins = 0;
-                    while (__hip_atomic_load(&s.iter_flags[wq], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                           (uint32_t)it) {
+                    while (true) {
+                        for (int g = 0; g < PG; ++g)
+                            for (int j = 0; j < 3; ++j)
+                                w[g][j] = __hip_atomic_load(&tg[j * n + jq[g]], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+                        bool ready = true;
+                        for (int g = 0; g < PG; ++g)
+                            for (int j = 0; j < 3; ++j) ready = ready && (uint32_t)(w[g][j] >> 32) == want;
+                        if (ready) break;
                         if (++spins > kWaitLimit) {
                             atomicOr(&s.counters->err, kErrInternal);
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
+                    for (int g = 0; g < PG; ++g)
+                        for (int j = 0; j < 3; ++j) dq[g][j] = __uint_as_float((uint32_t)w[g][j]);
                 }
-                float xq[3], dq[3];
-                for (int j = 0; j < 3; ++j) {
-                    xq[j] = s.x[j * n + jq];
-                    dq[j] = coherent_load(&dl[j * n + jq]);
-                }
-                pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
+                for (int g = 0; g < PG; ++g)
+                    if (sl + g < cnt)
+                        pair_correction(c, avg, mu, x0, del, m, ni, xq[g], dq[g], s.mass[jq[g]],
+                                        avg == 0u ? s.nbr_n[jq[g]] : 0u, Cd);
             }
         }
 
@@ -967,17 +986,12 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                 del[j] = dnew;
             }
         }
-        if (it + 1 < K) {           // publish X_{it+1} of the particles that partners read
-            float* dn = s.dl[(it + 1) & 1];
-            if (act && cnt > 0u)
-                for (int j = 0; j < 3; ++j)
-                    __hip_atomic_store(&dn[j * n + i], del[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // the positions are agent-coherent stores: waiting for their
-            // completion orders them before the flag (no L2 write-back needed)
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            if (threadIdx.x == 0)
-                __hip_atomic_store(&s.iter_flags[blk], (uint32_t)(it + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (it + 1 < K && act && cnt > 0u) {   // publish X_{it+1} for the partners
+            unsigned long long* tn = s.tagged + (size_t)((it + 1) & 1) * 3 * n;
+            const unsigned long long tag = (unsigned long long)iter_tag(epoch, it + 1) << 32;
+            for (int j = 0; j < 3; ++j)
+                __hip_atomic_store(&tn[j * n + i], tag | __float_as_uint(del[j]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
     // X_K - X_init and V_K where the finalize step reads them
@@ -1042,10 +1056,9 @@ __global__ void __launch_bounds__(kBlock) k_clear_counters(Counters* c, NbrStats
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_reset_iter_flags(uint32_t* f, int32_t n)
+__global__ void __launch_bounds__(64) k_next_epoch(Counters* c)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) f[i] = 0u;
+    if (threadIdx.x == 0) c->epoch += 1u;
 }
 
 __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
@@ -1112,8 +1125,7 @@ hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts&
     if (s.n <= 0 || count <= 0) return hipSuccess;
     if (s.resident_iterate) {       // each launch: all K iterations
         for (int k = 0; k < count; ++k) {
-            hipLaunchKernelGGL(k_reset_iter_flags, dim3(blocks_for((size_t)s.n_iter_blocks)), dim3(kBlock), 0, stream,
-                               s.iter_flags, s.n_iter_blocks);
+            hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(64), 0, stream, s.counters);
             hipLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s,
                                c, iterations);
         }
@@ -1132,10 +1144,9 @@ hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepC
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
-    if (s.resident_iterate) {       // each launch: all K iterations; the flag reset is outside the events
+    if (s.resident_iterate) {       // each launch: all K iterations; the new epoch is set outside the events
         for (int k = 0; k < count; ++k) {
-            hipLaunchKernelGGL(k_reset_iter_flags, dim3(blocks_for((size_t)s.n_iter_blocks)), dim3(kBlock), 0, stream,
-                               s.iter_flags, s.n_iter_blocks);
+            hipLaunchKernelGGL(k_next_epoch, dim3(1), dim3(64), 0, stream, s.counters);
             hipExtLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream,
                                   t0[k], t1[k], 0, s, c, iterations);
         }

@@ -224,7 +224,7 @@ def test_cuboid_rain_16_substeps_of_the_first_40_frames(orc):
     frames, each from the reference state rounded to FP32."""
     sc = scenes.cuboid_rain(0)
     s = _gpu_solver(sc)
-    assert s.info().iteration_kernel == 0      # the grid fits the GPU at once; too large for the one-launch form
+    assert s.info().iteration_kernel == 2      # the grid fits the GPU at once: one launch per substep
     picks = [int(round(k)) for k in np.linspace(0, 40 * sc.substeps - 1, 16)]
     assert max(_sampled_gate(orc, sc, picks, s, "cuboid_rain")) >= 1
 
