@@ -752,7 +752,7 @@ __device__ inline uint32_t iter_tag(uint32_t epoch, int it) { return (epoch << 6
 
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, StepConsts c, int K)
 {
-    constexpr int PG = 4;                // contact partners whose positions are loaded together
+    constexpr int PG = 2;                // contact partners whose positions are loaded together
     constexpr int NSM = 12, NMOM = 24;
     __shared__ float4 red_sm[kMaxWaves * NSM / 4];
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
@@ -809,6 +809,58 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
 
     for (int it = 0; it < K; ++it) {
         const unsigned long long* tg = s.tagged + (size_t)(it & 1) * 3 * n;   // partners' X_it, tagged
+        // the first PE partners' words are loaded before the shape-matching
+        // phase, which does not need them, and checked after it
+        constexpr int PE = 2;
+        const uint32_t want = iter_tag(epoch, it);
+        uint32_t je[PE];
+        unsigned long long we[PE][3];
+        for (int g = 0; g < PE; ++g) {
+            je[g] = 0u;
+            for (int j = 0; j < 3; ++j) we[g][j] = 0ull;
+        }
+        if (act && cnt > 0u) {
+            for (int g = 0; g < PE; ++g) je[g] = s.nbr[((uint32_t)g < cnt ? g : 0) * n + i];
+            if (it > 0)
+                for (int g = 0; g < PE; ++g)
+                    for (int j = 0; j < 3; ++j)
+                        we[g][j] = __hip_atomic_load(&tg[j * n + je[g]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+
+        float y[3];
+        y[0] = (x0[0] - ax) + del[0];
+        y[1] = (x0[1] - ay) + del[1];
+        y[2] = (x0[2] - az) + del[2];
+        {
+            float S[NSM];
+            for (int j = 0; j < 3; ++j) S[j] = m * y[j];
+            for (int a = 0; a < 3; ++a)
+                for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
+            wave_sums_by_row<NSM>(S);
+            if ((lane & 15) == 15) {
+                float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
+                for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
+            }
+        }
+        __syncthreads();
+        if (body_lane) {
+            float T[NSM];
+            sum_wave_partials<NSM / 4, 4>(red_sm, bl_w0, bl_nw, T);
+            const float im = frcp(bl_M);
+            float cc[3], A[9], Rb[9];
+            for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
+            for (int a = 0; a < 3; ++a)
+                for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+            if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
+            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rprev[j] = Rb[j];
+            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+        }
+        __syncthreads();
+        float R[9], cyv[3];
+        for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+        for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
+
+        // contacts from X_i (planes, then partners in list order)
         float Cd[3] = {0.0f, 0.0f, 0.0f};
         if (act) {
             for (int pl = 0; pl < c.n_planes; ++pl) {
@@ -824,10 +876,42 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                 Cd[1] += pen * ny - f * uy;
                 Cd[2] += pen * nz - f * uz;
             }
-            // partners PG at a time: their tagged words are loaded together
-            // and polled again only while a tag is not yet that of X_it
-            const uint32_t want = iter_tag(epoch, it);
-            for (uint32_t sl = 0; sl < cnt; sl += PG) {
+            // the early group: its words are usually ready by now
+            if (cnt > 0u) {
+                float xe[PE][3], de[PE][3];
+                for (int g = 0; g < PE; ++g)
+                    for (int j = 0; j < 3; ++j) xe[g][j] = s.x[j * n + je[g]];
+                if (it == 0) {                        // X_0 from the integration step
+                    for (int g = 0; g < PE; ++g)
+                        for (int j = 0; j < 3; ++j) de[g][j] = s.dl[0][j * n + je[g]];
+                } else {
+                    uint32_t spins = 0;
+                    while (true) {
+                        bool ready = true;
+                        for (int g = 0; g < PE; ++g)
+                            for (int j = 0; j < 3; ++j) ready = ready && (uint32_t)(we[g][j] >> 32) == want;
+                        if (ready) break;
+                        if (++spins > kWaitLimit) {
+                            atomicOr(&s.counters->err, kErrInternal);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        for (int g = 0; g < PE; ++g)
+                            for (int j = 0; j < 3; ++j)
+                                we[g][j] = __hip_atomic_load(&tg[j * n + je[g]], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    for (int g = 0; g < PE; ++g)
+                        for (int j = 0; j < 3; ++j) de[g][j] = __uint_as_float((uint32_t)we[g][j]);
+                }
+                for (int g = 0; g < PE; ++g)
+                    if ((uint32_t)g < cnt)
+                        pair_correction(c, avg, mu, x0, del, m, ni, xe[g], de[g], s.mass[je[g]],
+                                        avg == 0u ? s.nbr_n[je[g]] : 0u, Cd);
+            }
+            // further partners PG at a time: their tagged words are loaded
+            // together and polled again only while a tag is not yet X_it's
+            for (uint32_t sl = PE; sl < cnt; sl += PG) {
                 uint32_t jq[PG];
                 float xq[PG][3], dq[PG][3];
                 for (int g = 0; g < PG; ++g) {
@@ -865,38 +949,6 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
             }
         }
 
-        float y[3];
-        y[0] = (x0[0] - ax) + del[0];
-        y[1] = (x0[1] - ay) + del[1];
-        y[2] = (x0[2] - az) + del[2];
-        {
-            float S[NSM];
-            for (int j = 0; j < 3; ++j) S[j] = m * y[j];
-            for (int a = 0; a < 3; ++a)
-                for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
-            wave_sums_by_row<NSM>(S);
-            if ((lane & 15) == 15) {
-                float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
-                for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
-            }
-        }
-        __syncthreads();
-        if (body_lane) {
-            float T[NSM];
-            sum_wave_partials<NSM / 4, 4>(red_sm, bl_w0, bl_nw, T);
-            const float im = frcp(bl_M);
-            float cc[3], A[9], Rb[9];
-            for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
-            for (int a = 0; a < 3; ++a)
-                for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
-            if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
-            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rprev[j] = Rb[j];
-            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
-        }
-        __syncthreads();
-        float R[9], cyv[3];
-        for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
-        for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
 
         float r[3], Dd[3];
         for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
