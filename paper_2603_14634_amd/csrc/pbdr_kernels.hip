@@ -811,7 +811,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         const unsigned long long* tg = s.tagged + (size_t)(it & 1) * 3 * n;   // partners' X_it, tagged
         // the first PE partners' words are loaded before the shape-matching
         // phase, which does not need them, and checked after it
-        constexpr int PE = 2;
+        constexpr int PE = 3;
         const uint32_t want = iter_tag(epoch, it);
         uint32_t je[PE];
         unsigned long long we[PE][3];
