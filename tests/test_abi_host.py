@@ -83,6 +83,9 @@ def test_scene_bytes_and_parameter_validation():
         assert B.scene_bytes(pp, sc.n, sc.n_bodies) == 0, kw
         assert B.last_error() != ""
     assert B.scene_bytes(p, sc.n, 0) == 0          # particles without bodies
+    for ok_flags in (B.FLAG_ITERATION_LAUNCHES, B.FLAG_NO_GRAPH | B.FLAG_ITERATION_LAUNCHES):
+        assert B.scene_bytes(B.params_for(sc, flags=ok_flags), sc.n, sc.n_bodies) == nbytes
+    assert B.scene_bytes(B.params_for(sc, flags=0x40), sc.n, sc.n_bodies) == 0
     assert B.scene_bytes(p, 0, 0) > 0              # an empty scene is valid
 
 
