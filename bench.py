@@ -84,6 +84,26 @@ def measured_traffic(workload: str):
         return None
 
 
+def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
+    """HBM bandwidth a plain device-to-device copy reaches on this GPU (bytes
+    read + written per second, GB/s), beside the datasheet peak."""
+    import torch
+
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / sec / 1e9
+
+
 def host_cpu() -> str:
     """CPU model and logical CPU count of this host."""
     model = "unknown CPU"
@@ -341,6 +361,7 @@ def main():
         print("[bench] calibration copy: %d bytes read and %d bytes written per launch" % (nbytes, nbytes),
               file=sys.stderr, flush=True)
         del src, dst
+    copy_gbs = measured_copy_gbs()
     sc = scenes.WORKLOADS[args.workload](args.seed)
     print("[bench] workload %s: %d particles, %d bodies" % (sc.name, sc.n, sc.n_bodies), file=sys.stderr,
           flush=True)
@@ -398,7 +419,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": ("k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)"
                        % per_launch) if per_launch > 1 else "k_iterate (one Jacobi iteration, all bodies)",
-            "iterations_per_launch": per_launch,
+            "iterations_per_launch": per_launch, "measured_copy_gbs": round(copy_gbs, 1),
             "avg_launch_us": round(it_ms * 1e3, 3), "launch_interval_us": round(interval_ms * 1e3, 3),
             "bytes_per_launch": int(bytes_launch), "mean_neighbours": round(kbar, 4)}
     print("[bench] iteration kernel %.2f us/launch (%.2f us apart back to back), %.1f GB/s algorithmic"
