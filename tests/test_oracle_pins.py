@@ -140,6 +140,137 @@ def test_one_particle_bodies_move_only_by_contact(orc, seed):
     np.testing.assert_allclose(x[0], expect, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("avg", ["own", "none"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pair_weight_modes_on_a_chain(orc, avg, seed):
+    # the chain of the test above under the two other pair weights: 1/n_p
+    # (each particle averages over its own list) and 1 (plain sum).  The middle
+    # particle has two neighbours, the ends one, so the modes differ there and
+    # at the ends by a factor of two.
+    rng = np.random.default_rng(20 + seed)
+    r, pen = 0.01, 0.006
+    m = rng.uniform(0.005, 0.05, size=3)
+    xs = np.array([0.0, 2 * r - pen, 2 * (2 * r - pen)]) + rng.uniform(-1, 1)
+    flags = orc.PP_AVG_OWN if avg == "own" else orc.PP_AVG_NONE
+    sc = scenes.from_bodies([np.array([[x], [0.25], [0.5]]) for x in xs], [np.zeros(3)] * 3, list(m),
+                            radius=r, gravity=(0.0, 0.0, 0.0), planes=(), mu=0.0, iterations=1)
+    x, v, mx, p, _ = _run(orc, sc, flags=flags)
+    assert mx == 2
+    m = sc.mass.astype(np.float64)
+    x0 = sc.x.astype(np.float64)
+    gaps = np.diff(x0[0])
+    p01, p12 = 2 * r - gaps[0], 2 * r - gaps[1]
+    # inverse-mass shares of each pair: w_a / (w_a + w_b) = m_b / (m_a + m_b)
+    a0, a1 = m[1] / (m[0] + m[1]), m[0] / (m[0] + m[1])
+    b1, b2 = m[2] / (m[1] + m[2]), m[1] / (m[1] + m[2])
+    wmid = 0.5 if avg == "own" else 1.0                 # the middle particle's own weight
+    expect = x0[0] + np.array([-a0 * p01, wmid * (a1 * p01 - b1 * p12), b2 * p12])
+    np.testing.assert_allclose(x[0], expect, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(x[1:], x0[1:])
+    np.testing.assert_allclose(v[0] * p.h, x[0] - x0[0], rtol=0, atol=1e-15)
+    P = (m * v[0]).sum()
+    if avg == "none":          # equal and opposite corrections: momentum kept
+        assert P == pytest.approx(0.0, abs=1e-12 * np.abs(m * v[0]).max())
+    else:                      # 1/n_p is not symmetric: the ends push twice as hard
+        assert abs(P) > 1e-3 * np.abs(m * v[0]).max()
+
+
+def _sliding_pair(m1, m2, s, mu, r=0.05, pen=4e-3):
+    # Two one-particle bodies with h = 1/1024 s (dt_frame 1/256 s, 4 substeps;
+    # every product below is exact in FP32).  Particle 0 starts at (-a, -h s, 0)
+    # moving +s along y, particle 1 at (a, h s, 0) moving -s: after the
+    # integration step both lie on the x axis, so the contact normal is x and
+    # their relative displacement since X_init, (0, 2 h s, 0), is tangential.
+    h = 1.0 / 1024.0
+    a = (2 * r - pen) / 2
+    sc = scenes.from_bodies([np.array([[-a], [-h * s], [0.0]]), np.array([[a], [h * s], [0.0]])],
+                            [np.array([0.0, s, 0.0]), np.array([0.0, -s, 0.0])], [m1, m2], radius=r,
+                            gravity=(0.0, 0.0, 0.0), planes=(), mu=mu, iterations=1,
+                            dt_frame=1.0 / 256.0, substeps=4)
+    return sc, h
+
+
+@pytest.mark.parametrize("kind", ["static", "kinetic"])
+@pytest.mark.parametrize("m1,m2", [(1.0, 1.0), (0.5, 2.5)])
+def test_pair_friction_static_and_kinetic(orc, kind, m1, m2):
+    mu, pen = 0.5, 4e-3
+    # |u_t| = 2 h s against mu * pen = 2e-3: 1e-3 (static) or 6e-3 (kinetic)
+    s = 0.512 if kind == "static" else 3.072
+    sc, h = _sliding_pair(m1, m2, s, mu, pen=pen)
+    x, v, mx, p, _ = _run(orc, sc)
+    assert mx == 1 and p.h == h
+    x0 = sc.x.astype(np.float64)
+    sv = float(sc.v[1, 0])
+    assert h * sv + x0[1, 0] == 0.0                    # exactly on the x axis after prediction
+    m = sc.mass.astype(np.float64)
+    w = 1.0 / m
+    al = w / w.sum()                                   # each particle's share of the pair
+    pe = 2 * sc.radius - (x0[0, 1] - x0[0, 0])         # penetration of the stored positions
+    ut = 2 * h * sv
+    removed = ut if kind == "static" else mu * pe      # tangential displacement taken away
+    moved = x - x0
+    # normal: the penetration, split by inverse mass
+    np.testing.assert_allclose(moved[0], [-al[0] * pe, al[1] * pe], rtol=1e-13, atol=1e-17)
+    # tangential: the relative slip shrinks by `removed`, split the same way
+    np.testing.assert_allclose(moved[1], [h * sv - al[0] * removed, -h * sv + al[1] * removed],
+                               rtol=1e-13, atol=1e-17)
+    slip = moved[1, 0] - moved[1, 1]
+    if kind == "static":
+        assert abs(slip) <= 1e-15                       # the slip is removed entirely
+    else:
+        assert slip == pytest.approx(ut - mu * pe, rel=1e-12)
+    np.testing.assert_array_equal(moved[2], 0.0)
+    np.testing.assert_allclose(v * h, moved, rtol=0, atol=1e-16)
+    np.testing.assert_allclose((m * v).sum(axis=1), (m * sc.v.astype(np.float64)).sum(axis=1), rtol=0,
+                               atol=1e-13)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_sliding_block_velocity_in_both_update_modes(orc, flags):
+    # A 3x2 lattice plate (one body) starts a depth pen inside the ground,
+    # sliding along a diagonal of the plane with no gravity.  Iteration 1 pushes
+    # every particle out by pen and kinetic friction removes mu * pen of the
+    # tangential displacement; iterations 2 and 3 find nothing to correct, and
+    # shape matching and the momentum constraint leave the uniform motion alone.
+    # With either velocity update (incremental, or standard PBD's
+    # (X_K - X_init) / h) the velocity after K = 3 iterations is the whole
+    # substep's displacement over h.
+    r, pen, mu = 0.05, 1e-3, 0.4
+    vt = np.array([0.6, 0.8]) * 2.0
+    sc = _body_scene(scenes.lattice_box(3, 2, 1, 2 * r), centre=(0.1, -0.2, r - pen),
+                     velocity=(vt[0], vt[1], 0.0), radius=r, gravity=(0.0, 0.0, 0.0), mu=mu, iterations=3)
+    x, v, _, p, _ = _run(orc, sc, flags=flags)
+    h = p.h
+    x0 = sc.x.astype(np.float64)
+    pe = r - x0[2, 0]
+    u = h * sc.v[:2, 0].astype(np.float64)
+    un = float(np.linalg.norm(u))
+    assert un > mu * pe                                     # kinetic
+    moved = x - x0
+    np.testing.assert_allclose(moved[:2], np.repeat((u * (1.0 - mu * pe / un))[:, None], sc.n, axis=1),
+                               rtol=0, atol=1e-15)
+    np.testing.assert_allclose(x[2], r, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(v, moved / h, rtol=0, atol=1e-12)
+
+
+def test_standard_and_incremental_velocity_agree_in_contact(orc):
+    # In exact arithmetic V_{i+1} = V_i + dX_i / h and (X_{i+1} - X_init) / h
+    # are the same after every iteration, momentum correction included; in FP64
+    # the two branches agree to rounding, also with contacts, shape matching
+    # and the momentum correction all acting.
+    sc = scenes.drop_cubes(seed=1)
+    p = orc.params_for(sc)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v, _ = orc.substep(p, rest, sc.x, sc.v, n_substeps=4 * 150)   # first cubes have landed
+    assert (x[2] < sc.radius).any()
+    xi, vi, _ = orc.substep(p, rest, x, v)
+    xs, vs, _ = orc.substep(orc.params_for(sc, flags=orc.STD_VELOCITY), rest, x, v)
+    np.testing.assert_allclose(vs * p.h, xs - x, rtol=0, atol=1e-12 * p.h * np.abs(vs).max())
+    np.testing.assert_allclose(xs, xi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(vs, vi, rtol=0, atol=1e-9 * np.abs(vi).max())
+    assert np.abs(vi - v).max() > 1e-2                       # the contacts did act
+
+
 def test_symmetric_averaging_conserves_total_momentum(orc):
     rng = np.random.default_rng(7)
     r = 0.05
