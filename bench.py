@@ -1,25 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the PBD-R solver substep on one MI355X.
 
-Workloads: ``cuboid_rain_1000`` (default), ``drop_cubes_8x64`` and
-``dense_pile_20k`` run one scene through the single-scene solver;
+Workloads: ``dense_pile_20k`` (default), ``cuboid_rain_1000`` and
+``drop_cubes_8x64`` run one scene through the single-scene solver;
 ``batch_4096`` steps 4096 independent scenes (log-normal 100-5000 particles)
 in a scene pool; ``serving`` serves Poisson-arriving rollout requests with
 continuous batching and reports p50/p99 latency beside throughput.
 
-Default workload: ``cuboid_rain_1000`` -- 1000 randomly oriented cuboid
-lattices (per-axis sizes U{3..8}, about 171k particles, r = 0.01 m), ground
-plane, dt = 1/240 s, 4 substeps x 10 iterations per frame, seeded synthetic
-input.  A "step" is one frame: 4 full substeps (prediction, hash-grid
-neighbour search, 10 Jacobi iterations of contacts + shape matching + momentum
-constraint, velocity update), replayed as one HIP graph.
+Default workload: ``dense_pile_20k`` -- 20k mixed cuboid and lattice-ball
+bodies (log-normal counts, mean 100; about 2.0M particles, r = 0.01 m) in a
+walled 4 x 4 m bin, dt = 1/240 s, 8 substeps x 20 iterations per frame,
+seeded synthetic input, timed after 240 untimed frames in which the pile
+settles into contact.  A "step" is one frame: 8 full substeps (prediction,
+hash-grid neighbour search, 20 Jacobi iterations of contacts + shape matching
++ momentum constraint, velocity update), replayed from a HIP graph.
 
 Prints one JSON line:
   value          particle-substeps per second over the timed frames (inputs
                  resident in HBM, HIP events on the solver's stream)
   roofline       the dominant kernel (one solver iteration over all bodies):
                  algorithmic bytes per launch / its average duration, timed
-                 live with HIP events on the same stream, against 8 TB/s
+                 live with HIP events on the same stream, against 8 TB/s;
+                 beside it the whole substep against the same peak
   cpu_baseline   the FP64 reference on this host's cores for a bounded sample
 """
 from __future__ import annotations
@@ -55,6 +57,23 @@ def iterate_bytes_per_particle(kbar: float) -> float:
 def iterate_bytes_per_body() -> float:
     """body_start (8), body mass (4), rotation written (36)."""
     return 48.0
+
+
+def substep_bytes_per_particle(iterations: int, kbar: float, hash_bits: int) -> float:
+    """Algorithmic bytes of one particle-substep, B = 112 + 16 P + 4 k + K (84 + 4 k).
+
+    Per substep: prediction (read x, v: 24; write X_init, delta_0, V_0: 36),
+    key (4), P sort passes of 8-bit digits over (key, id) pairs (16 each), cell
+    table (about 20), neighbour build (24 + 4 k); then K iterations of 84 + 4 k
+    (``iterate_bytes_per_particle``).  k = mean neighbour count, P = ceil(bits / 8).
+    """
+    passes = (hash_bits + 7) // 8
+    return 112.0 + 16.0 * passes + 4.0 * kbar + iterations * iterate_bytes_per_particle(kbar)
+
+
+# untimed frames before the warm-up: the pile settles into contact, the rain
+# lands, so that the timed frames carry contacts and partner waits
+SETTLE_FRAMES = {"dense_pile_20k": 240, "cuboid_rain_1000": 120}
 
 
 def source_digest() -> str:
@@ -307,7 +326,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed frames")
     ap.add_argument("--warmup", type=int, default=20, help="untimed frames")
-    ap.add_argument("--workload", default="cuboid_rain_1000")
+    ap.add_argument("--workload", default="dense_pile_20k")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--hash-bits", type=int, default=0, help="override the hash-grid key bits (0 = default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -328,7 +347,7 @@ def main():
     ap.add_argument("--large-gib", type=int, default=4, help="serving: HBM budget of the scene batch")
     ap.add_argument("--settle", type=int, default=None,
                     help="untimed frames before the warm-up (default: 240 for dense_pile_20k, so the pile has "
-                         "settled into contact, else 0)")
+                         "settled into contact, 120 for cuboid_rain_1000, so the rain has landed, else 0)")
     args = ap.parse_args()
     if args.workload == "serving":
         # the serving lanes (pool and batch) and the pool's side-by-side classes
@@ -368,10 +387,18 @@ def main():
     solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits,
                                  flags=B.FLAG_ITERATION_LAUNCHES if args.iteration_launches else 0)
     stream = solver.stream
-    settle = args.settle if args.settle is not None else (240 if args.workload == "dense_pile_20k" else 0)
+    settle = args.settle if args.settle is not None else SETTLE_FRAMES.get(args.workload, 0)
     if settle:
         print("[bench] settling %d frames (untimed)" % settle, file=sys.stderr, flush=True)
         solver.step(settle)
+        solver.check()
+        # the neighbour statistics restart here (setting the same state clears
+        # them), so the mean list length is that of the warm-up and timed frames
+        xd = torch.empty((3, sc.n), dtype=torch.float32, device="cuda")
+        vd = torch.empty_like(xd)
+        solver.read_state_device(xd, vd)
+        solver.set_state(xd, vd)
+        del xd, vd
     solver.step(args.warmup)
     torch.cuda.synchronize()
     solver.check()
@@ -400,7 +427,8 @@ def main():
     # stream (begin and end of the kernel, no marker packets between), so the
     # average is the kernel's duration; the back-to-back rate (which adds the
     # gap between dependent launches) is reported beside it.
-    per_launch = sc.iterations if solver.info().iteration_kernel == 2 else 1
+    info = solver.info()
+    per_launch = sc.iterations if info.iteration_kernel == 2 else 1
     solver.launch_iterations(10)
     torch.cuda.synchronize()
     n_it = args.iter_launches
@@ -415,13 +443,23 @@ def main():
     bytes_launch = per_launch * (sc.n * iterate_bytes_per_particle(kbar) + sc.n_bodies * iterate_bytes_per_body())
     achieved = bytes_launch / (it_ms / 1e3) / 1e9
     traffic = measured_traffic(sc.name)
+    kernel = {0: "k_iterate (one Jacobi iteration, all bodies, one launch)",
+              1: "k_iterate_dense + k_iterate (one Jacobi iteration, all bodies: bodies of up to 4 waves in "
+                 "4-wave workgroups, larger ones in a second launch)",
+              2: "k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)" % per_launch}
+    sub_b = substep_bytes_per_particle(sc.iterations, kbar, info.hash_bits)
+    sub_gbs = value * sub_b / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": ("k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)"
-                       % per_launch) if per_launch > 1 else "k_iterate (one Jacobi iteration, all bodies)",
+            "kernel": kernel[info.iteration_kernel],
             "iterations_per_launch": per_launch, "measured_copy_gbs": round(copy_gbs, 1),
             "avg_launch_us": round(it_ms * 1e3, 3), "launch_interval_us": round(interval_ms * 1e3, 3),
-            "bytes_per_launch": int(bytes_launch), "mean_neighbours": round(kbar, 4)}
+            "bytes_per_launch": int(bytes_launch), "mean_neighbours": round(kbar, 4),
+            # HBM bytes the counters saw per launch, over the same duration
+            "counter_frac": (round(traffic / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None),
+            # the whole substep (index build + K iterations) on the survey's byte model
+            "substep": {"bytes_per_particle_substep": round(sub_b, 1), "achieved": round(sub_gbs, 2),
+                        "frac": round(sub_gbs / HBM_PEAK_GBS, 4)}}
     print("[bench] iteration kernel %.2f us/launch (%.2f us apart back to back), %.1f GB/s algorithmic"
           % (it_ms * 1e3, interval_ms * 1e3, achieved), file=sys.stderr, flush=True)
 

@@ -24,10 +24,14 @@
  *    synchronise that stream.
  *  - Every call returns a pbdr_status.  Invalid arguments are rejected before
  *    any device work is enqueued.  Conditions found on the device (a neighbour
- *    list over capacity, a non-finite state) are latched in the workspace and
- *    reported by the next call that synchronises (pbdr_scene_read_*,
- *    pbdr_scene_check).  pbdr_last_error() gives a message for the calling
- *    thread's last failure.
+ *    list over capacity, a non-finite state, a device-side wait that gave up)
+ *    are latched in the workspace and reported by the next call that
+ *    synchronises (pbdr_scene_read_*, pbdr_scene_check).  The frame in which
+ *    one is raised is discarded: the scene's state (x, v) is committed only at
+ *    the end of a frame with no latched condition, so it stays at the last
+ *    frame completed before the condition, and later pbdr_scene_step calls
+ *    leave it there until pbdr_scene_set_state clears the latch.
+ *    pbdr_last_error() gives a message for the calling thread's last failure.
  *  - A scene is not thread-safe; distinct scenes may be used from distinct
  *    threads.
  */
@@ -49,9 +53,12 @@ typedef enum {
     PBDR_OK = 0,
     PBDR_ERR_INVALID_ARG = -1, /* bad pointer, size, body partition or parameter   */
     PBDR_ERR_WORKSPACE = -2,   /* workspace too small or misaligned (256 B)         */
-    PBDR_ERR_DEVICE = -3,      /* a HIP runtime call failed                          */
-    PBDR_ERR_CAPACITY = -4,    /* a neighbour list exceeded nbr_cap (lists truncated)*/
-    PBDR_ERR_NONFINITE = -5,   /* a position or velocity became NaN/Inf              */
+    PBDR_ERR_DEVICE = -3,      /* a HIP runtime call failed, or a device-side wait
+                                  gave up (the frame was discarded)                 */
+    PBDR_ERR_CAPACITY = -4,    /* a neighbour list exceeded nbr_cap (the frame was
+                                  discarded; recreate the scene with a larger cap)  */
+    PBDR_ERR_NONFINITE = -5,   /* a position or velocity became NaN/Inf (the frame
+                                  was discarded)                                    */
     PBDR_ERR_STATE = -6        /* call not valid in the scene's current state        */
 } pbdr_status;
 
@@ -149,6 +156,22 @@ typedef struct pbdr_scene pbdr_scene;
 /* ABI version this library implements (PBDR_ABI_VERSION). */
 int32_t pbdr_abi_version(void);
 
+/* Device conditions a workspace latches (bits).  A frame that raises any of
+ * them is discarded (see Conventions). */
+#define PBDR_COND_CAPACITY 0x1u      /* a neighbour list exceeded nbr_cap            */
+#define PBDR_COND_NONFINITE 0x2u     /* a position or velocity became NaN/Inf        */
+#define PBDR_COND_SCAN_WAIT 0x4u     /* the cell-table scan's look-back gave up      */
+#define PBDR_COND_PARTNER_WAIT 0x8u  /* a one-launch iteration's wait for a contact
+                                        partner gave up (its workgroups were not all
+                                        resident together)                           */
+
+/* The status that the synchronising calls return for a set of latched
+ * conditions, and the message they leave for pbdr_last_error: PBDR_OK for
+ * none; PBDR_ERR_CAPACITY before PBDR_ERR_NONFINITE before PBDR_ERR_DEVICE
+ * (the waits), since an overflowing list can make partner waits give up.
+ * Host only; no device work. */
+pbdr_status pbdr_condition_status(uint32_t conditions);
+
 /* Message describing the calling thread's last failed call ("" if none). */
 const char* pbdr_last_error(void);
 
@@ -176,14 +199,23 @@ pbdr_status pbdr_scene_set_accel(pbdr_scene* scene, const float* accel_dev);
  * stream that other work keeps busy.  PBDR_ERR_DEVICE if the wait fails. */
 pbdr_status pbdr_scene_set_stream(pbdr_scene* scene, void* hip_stream);
 
-/* Advances n_frames frames of `substeps` substeps each (asynchronous). */
+/* Advances n_frames frames (asynchronous).  A frame is `substeps` substeps of
+ * Alg. 1, each the integration step, the neighbour search and `iterations`
+ * Jacobi iterations of ground and particle contact and shape matching with
+ * the velocity update of Sec. III-B and the momentum constraint of Sec. III-C
+ * (frames of substeps as in Sec. IV-B).  The state is committed at the end of
+ * every frame that latched no device condition; see Conventions.  Frames are
+ * replayed from a captured HIP graph unless PBDR_FLAG_NO_GRAPH.
+ * PBDR_ERR_INVALID_ARG for n_frames < 0; PBDR_ERR_DEVICE if a launch fails. */
 pbdr_status pbdr_scene_step(pbdr_scene* scene, int32_t n_frames);
 
-/* Advances n_substeps substeps (asynchronous); for substep-level checks. */
+/* Advances n_substeps substeps of Alg. 1 as one frame (asynchronous; the
+ * state is committed after the last of them); for substep-level checks. */
 pbdr_status pbdr_scene_substep(pbdr_scene* scene, int32_t n_substeps);
 
 /* Replaces positions and velocities ([3][N] each; host pointers if
- * on_device == 0, device pointers otherwise).  Bodies and rest pose are kept. */
+ * on_device == 0, device pointers otherwise) and clears the latched device
+ * conditions.  Bodies and rest pose are kept. */
 pbdr_status pbdr_scene_set_state(pbdr_scene* scene, const float* x, const float* v, int32_t on_device);
 
 /* Copies positions and velocities out ([3][N] each, either may be NULL) and

@@ -25,9 +25,10 @@ DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3
 DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8
 MAX_PLANES = 8
 MAX_TIMED_LAUNCHES = 4096
+COND_CAPACITY, COND_NONFINITE, COND_SCAN_WAIT, COND_PARTNER_WAIT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
-    "pbdr_abi_version", "pbdr_last_error", "pbdr_scene_bytes", "pbdr_scene_create",
+    "pbdr_abi_version", "pbdr_last_error", "pbdr_condition_status", "pbdr_scene_bytes", "pbdr_scene_create",
     "pbdr_scene_set_accel", "pbdr_scene_set_stream", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
     "pbdr_scene_read_state", "pbdr_scene_read_bodies", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
     "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations",
@@ -151,6 +152,8 @@ def load_library(path: str = LIB_PATH):
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     lib.pbdr_abi_version.restype = i32
     lib.pbdr_last_error.restype = ctypes.c_char_p
+    lib.pbdr_condition_status.restype = i32
+    lib.pbdr_condition_status.argtypes = [ctypes.c_uint32]
     lib.pbdr_scene_bytes.restype = sz
     lib.pbdr_scene_bytes.argtypes = [ctypes.POINTER(Params), i32, i32]
     lib.pbdr_scene_create.restype = i32
@@ -213,6 +216,11 @@ def load_library(path: str = LIB_PATH):
 
 def last_error() -> str:
     return load_library().pbdr_last_error().decode()
+
+
+def condition_status(conditions: int) -> int:
+    """Status the library reports for a set of latched device-condition bits."""
+    return int(load_library().pbdr_condition_status(conditions))
 
 
 def _check(status: int):
@@ -296,6 +304,7 @@ class Solver:
                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self._h = handle
         self._accel = None
+        self.workspace.record_stream(self.stream)   # the allocator waits for this stream's work on free
 
     @classmethod
     def from_scene(cls, scene, device: str = "cuda:0", **param_overrides) -> "Solver":
@@ -313,6 +322,7 @@ class Solver:
         """Moves later work to ``stream`` (a torch stream) after the current one drains."""
         _check(self._lib.pbdr_scene_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
         self.stream = stream
+        self.workspace.record_stream(stream)
 
     def set_accel(self, accel):
         """accel: torch float32 device tensor [3, N] (kept alive here) or None."""
@@ -437,6 +447,7 @@ class Pool:
                                           self.workspace.data_ptr(), int(nbytes),
                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self._h = handle
+        self.workspace.record_stream(self.stream)
         self.sizes = {}
 
     def try_add(self, scene):
@@ -601,6 +612,7 @@ class Batch:
                                            self.workspace.data_ptr(), int(nbytes),
                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self._h = handle
+        self.workspace.record_stream(self.stream)
         self.sizes = {}
 
     def try_add(self, scene):

@@ -35,6 +35,33 @@ void clear_error() { g_err[0] = 0; }
 
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+static_assert(pbdr::kErrCapacity == PBDR_COND_CAPACITY && pbdr::kErrNonFinite == PBDR_COND_NONFINITE &&
+                  pbdr::kErrInternal == PBDR_COND_SCAN_WAIT && pbdr::kErrWait == PBDR_COND_PARTNER_WAIT,
+              "latched condition bits");
+
+pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap)
+{
+    // a list over capacity first: it can make one-launch waits give up as well
+    if ((err & pbdr::kErrCapacity) && cap > 0)
+        return fail(PBDR_ERR_CAPACITY,
+                    "a neighbour list reached %u entries, above nbr_cap %d; the state is that of the last frame "
+                    "completed before it",
+                    max_nbr, cap);
+    if (err & pbdr::kErrCapacity)
+        return fail(PBDR_ERR_CAPACITY,
+                    "a neighbour list exceeded nbr_cap; the state is that of the last frame completed before it");
+    if (err & pbdr::kErrNonFinite)
+        return fail(PBDR_ERR_NONFINITE,
+                    "a position or velocity became non-finite; the state is that of the last frame completed before it");
+    if (err & pbdr::kErrWait)
+        return fail(PBDR_ERR_DEVICE,
+                    "a one-launch iteration gave up waiting for a contact partner (workgroups not resident together; "
+                    "PBDR_FLAG_ITERATION_LAUNCHES avoids the form); the frame was discarded");
+    if (err & pbdr::kErrInternal)
+        return fail(PBDR_ERR_DEVICE, "the cell-table scan gave up waiting for a preceding tile; the frame was discarded");
+    return PBDR_OK;
+}
+
 pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out)
 {
     if (!in) return fail(PBDR_ERR_INVALID_ARG, "params is NULL");
@@ -90,7 +117,7 @@ using pbdr::host::resolve;
 using pbdr::host::g_err;
 
 struct Layout {
-    size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
+    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
         sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
         body_wave0, block_body, tagged, body_mq, body_out, total;
 };
@@ -121,6 +148,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     Layout L;
     L.x = take(12 * N);
     L.v = take(12 * N);
+    L.x0 = take(12 * N);
     L.mass = take(4 * N);
     L.body = take(4 * N);
     L.q = take(12 * N);
@@ -228,14 +256,9 @@ pbdr_status latched(pbdr_scene* s)
     pbdr::Counters c;
     pbdr_status st = read_counters(s, &c);
     if (st != PBDR_OK) return st;
-    if (c.err & pbdr::kErrInternal) return fail(PBDR_ERR_DEVICE, "a device-side wait gave up (cell-table scan)");
-    if (c.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity became non-finite");
-    if (c.err & pbdr::kErrCapacity) {
-        uint32_t mx = 0;
-        read_nbr_stats(s, &mx, nullptr);
-        return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", mx, s->res.cap);
-    }
-    return PBDR_OK;
+    uint32_t mx = 0;
+    if (c.err & pbdr::kErrCapacity) read_nbr_stats(s, &mx, nullptr);
+    return pbdr::host::latched_status(c.err, mx, s->res.cap);
 }
 
 void fill_consts(pbdr_scene* s) { pbdr::host::fill_step_consts(s->res, &s->consts); }
@@ -280,6 +303,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.n_scan_tiles = (uint32_t)(((size_t)d.T + pbdr::kScanTile - 1) / pbdr::kScanTile);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
+    d.x0 = (float*)(w + L.x0);
     d.mass = (const float*)(w + L.mass);
     d.body = (const int32_t*)(w + L.body);
     d.q = (const float*)(w + L.q);
@@ -359,6 +383,12 @@ pbdr_status capture(pbdr_scene* s, int frames, hipGraph_t* graph, hipGraphExec_t
 extern "C" {
 
 int32_t pbdr_abi_version(void) { return PBDR_ABI_VERSION; }
+
+pbdr_status pbdr_condition_status(uint32_t conditions)
+{
+    g_err[0] = 0;
+    return pbdr::host::latched_status(conditions, 0u, 0);
+}
 
 const char* pbdr_last_error(void) { return g_err; }
 
@@ -792,6 +822,8 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
 void pbdr_scene_destroy(pbdr_scene* s)
 {
     if (!s) return;
+    // the scene's work ends before the caller may free the workspace
+    (void)hipStreamSynchronize(s->stream);
     drop_graph(s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     delete s;

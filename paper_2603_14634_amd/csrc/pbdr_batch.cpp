@@ -42,8 +42,8 @@ int table_bits(int32_t n)
 }
 
 struct BLayout {
-    size_t x, v, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank, sorted_raw, sorted,
-        nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, body_mq, pscene, plan, total;
+    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank, sorted_raw,
+        sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, body_mq, pscene, plan, total;
     size_t plan_bytes, mscene_off, wave_off, block_off, wave0_off;   // within the plan region
     size_t max_waves, max_blocks;
 };
@@ -70,6 +70,7 @@ BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
     BLayout L;
     L.x = take(12 * N);
     L.v = take(12 * N);
+    L.x0 = take(12 * N);
     L.mass = take(4 * N);
     L.body = take(4 * N);
     L.q = take(12 * N);
@@ -178,11 +179,7 @@ pbdr_status blatched(pbdr_batch* b, int32_t* max_nbr)
     uint32_t mx = 0;
     for (const auto& e : st) mx = std::max(mx, e.max_nbr);
     if (max_nbr) *max_nbr = (int32_t)mx;
-    if (c.err & pbdr::kErrInternal) return fail(PBDR_ERR_DEVICE, "a device-side wait gave up (cell-table scan)");
-    if (c.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity became non-finite");
-    if (c.err & pbdr::kErrCapacity)
-        return fail(PBDR_ERR_CAPACITY, "a neighbour list reached %u entries, above nbr_cap %d", mx, b->res.cap);
-    return PBDR_OK;
+    return pbdr::host::latched_status(c.err, mx, b->res.cap);
 }
 
 // Plans and enqueues `frames` frames of the scenes flagged in `active`.
@@ -339,6 +336,7 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.n_scan_tiles = (uint32_t)((K + pbdr::kScanTile - 1) / pbdr::kScanTile);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
+    d.x0 = (float*)(w + L.x0);
     d.mass = (const float*)(w + L.mass);
     d.body = (const int32_t*)(w + L.body);
     d.q = (const float*)(w + L.q);

@@ -13,7 +13,12 @@ constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
 constexpr int kScanItems = 16;   // cell-table scan: counts per thread
 constexpr int kScanTile = kBlock * kScanItems;
 
-enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u };
+// kErrInternal: the cell-table scan's look-back (or a pool launch shape) gave
+// up; kErrWait: a one-launch iteration's wait for a contact partner gave up.
+enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u, kErrWait = 8u };
+// Any of these discards the frame in which it is raised: the committed state
+// keeps the last frame completed without one.
+constexpr uint32_t kErrDiscard = kErrCapacity | kErrNonFinite | kErrInternal | kErrWait;
 
 enum : uint32_t {
     kFlagStdVelocity = 0x1u,
@@ -24,7 +29,7 @@ enum : uint32_t {
 
 // Device-side error bits, latched until read by the host.
 struct Counters {
-    uint32_t err;                  // kErr* bits
+    uint32_t err;                  // kErr* bits (latched until cleared by the host)
     uint32_t epoch;                // substeps begun (one-launch iterations tag their data with it)
 };
 
@@ -70,8 +75,9 @@ struct Scene {
     int32_t n, nb;
     uint32_t T;               // 2^k cells
     uint32_t n_scan_tiles;    // ceil(T / kScanTile)
-    float* x;                 // [3][N] state positions (X_init during a substep)
-    float* v;                 // [3][N] state velocities
+    float* x;                 // [3][N] committed positions: the state after the last clean frame
+    float* v;                 // [3][N] committed velocities
+    float* x0;                // [3][N] X_init of the current substep (the working state)
     const float* mass;        // [N]
     const int32_t* body;      // [N] body of each particle
     const float* q;           // [3][N] rest offsets

@@ -83,6 +83,9 @@ struct Resolved {
 pbdr_status fail(pbdr_status st, const char* fmt, ...);
 void clear_error();
 bool finite3(const double* v);
+// Status for latched device error bits (pbdr::kErr*): PBDR_OK if none; a list
+// over capacity before a non-finite state before a wait that gave up.
+pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap);
 // Validates params for a scene of n particles and resolves the defaults.
 pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out);
 // FP32 constants of one substep from resolved parameters.

@@ -89,14 +89,16 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
     bool finite = true;
     for (int k = 0; k < 3; ++k) {
         const size_t j = k * n + i;
-        float x = s.x[j], v = s.v[j];
-        if (fold_src >= 0) {           // end of the previous substep
-            x = x + s.dl[fold_src][j];
+        float x, v;
+        if (fold_src >= 0) {           // end of the previous substep of this frame
+            x = s.x0[j] + s.dl[fold_src][j];
             v = s.vel[fold_src][j];
-            s.x[j] = x;
-            s.v[j] = v;
             finite = finite && isfinite(x) && isfinite(v);
+        } else {                       // first substep of a frame: the committed state
+            x = s.x[j];
+            v = s.v[j];
         }
+        s.x0[j] = x;                   // X_init of this substep
         const float a = g[k] + (s.accel ? s.accel[j] : 0.0f);
         const float dv = c.h * a;
         const float vt = v + dv;
@@ -515,7 +517,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     const float* vl = s.vel[src];
     float* dn = s.dl[src ^ 1];
     float* vn = s.vel[src ^ 1];
-    const float ax = s.x[s0], ay = s.x[n + s0], az = s.x[2 * n + s0];   // body anchor
+    const float ax = s.x0[s0], ay = s.x0[n + s0], az = s.x0[2 * n + s0];   // body anchor
     const uint32_t avg = (c.flags >> kAvgShift) & 3u;
 
     // per-body lane of wave 0: body slot `lane` of this workgroup
@@ -536,7 +538,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
     if (act) {
         for (int j = 0; j < 3; ++j) {
-            x0[j] = s.x[j * n + i];
+            x0[j] = s.x0[j * n + i];
             del[j] = dl[j * n + i];
             V[j] = vl[j * n + i];
             q[j] = s.q[j * n + i];
@@ -567,7 +569,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
             const uint32_t jq = s.nbr[sl * n + i];
             float xq[3], dq[3];
             for (int j = 0; j < 3; ++j) {
-                xq[j] = s.x[j * n + jq];
+                xq[j] = s.x0[j * n + jq];
                 dq[j] = dl[j * n + jq];
             }
             pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
@@ -743,12 +745,27 @@ k_iterate_dense(Scene s, StepConsts c, int src, int it)
 // buffer: the partner wrote X_it after it had read this particle's X_{it-1},
 // so X_{it+1} can replace X_{it-1}.  Particles without partners in other
 // bodies never wait.  Every wait is bounded: one that gives up latches
-// kErrInternal instead of hanging.  The arithmetic is that of iterate_body,
-// in the same order.
+// kErrWait instead of hanging, and the frame is then discarded.  The
+// arithmetic is that of iterate_body, in the same order.
 constexpr uint32_t kWaitLimit = 1u << 20;
 
 // tag of X_it in substep `epoch` (K < 64 iterations; tags repeat after 2^26 substeps)
 __device__ inline uint32_t iter_tag(uint32_t epoch, int it) { return (epoch << 6) | (uint32_t)it; }
+
+// Called once per unsuccessful poll of a partner wait: true (and nowait set)
+// once this wait has polled kWaitLimit times, which latches kErrWait, or, checked
+// every 256 polls, once some other wait of the launch has given up.
+__device__ inline bool stop_waiting(const Scene& s, uint32_t spins, bool& nowait)
+{
+    if (spins > kWaitLimit) {
+        atomicOr(&s.counters->err, kErrWait);
+        nowait = true;
+    } else if ((spins & 255u) == 0u &&
+               (__hip_atomic_load(&s.counters->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrWait)) {
+        nowait = true;
+    }
+    return nowait;
+}
 
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, StepConsts c, int K)
 {
@@ -775,7 +792,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     const int i = s0 + (wave - lw0) * 64 + lane;
     const bool act = b >= 0 && i < e0;
     const size_t n = (size_t)s.n;
-    const float ax = s.x[s0], ay = s.x[n + s0], az = s.x[2 * n + s0];   // body anchor
+    const float ax = s.x0[s0], ay = s.x0[n + s0], az = s.x0[2 * n + s0];   // body anchor
     const uint32_t avg = (c.flags >> kAvgShift) & 3u;
 
     const bool body_lane = wave == 0 && lane < blk_nb;
@@ -795,7 +812,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     uint32_t ni = 0u;
     if (act) {
         for (int j = 0; j < 3; ++j) {
-            x0[j] = s.x[j * n + i];
+            x0[j] = s.x0[j * n + i];
             del[j] = s.dl[0][j * n + i];
             V[j] = s.vel[0][j * n + i];
             q[j] = s.q[j * n + i];
@@ -806,6 +823,11 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
     const float mu = c.mu;
     const uint32_t epoch = s.counters->epoch;
+    // No waiting once a list has overflowed (partners then need not list each
+    // other both ways) or a wait has given up anywhere: the frame is discarded
+    // in either case, and the launch only has to end.
+    bool nowait = (__hip_atomic_load(&s.counters->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+                   (kErrCapacity | kErrWait)) != 0u;
 
     for (int it = 0; it < K; ++it) {
         const unsigned long long* tg = s.tagged + (size_t)(it & 1) * 3 * n;   // partners' X_it, tagged
@@ -880,21 +902,17 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
             if (cnt > 0u) {
                 float xe[PE][3], de[PE][3];
                 for (int g = 0; g < PE; ++g)
-                    for (int j = 0; j < 3; ++j) xe[g][j] = s.x[j * n + je[g]];
+                    for (int j = 0; j < 3; ++j) xe[g][j] = s.x0[j * n + je[g]];
                 if (it == 0) {                        // X_0 from the integration step
                     for (int g = 0; g < PE; ++g)
                         for (int j = 0; j < 3; ++j) de[g][j] = s.dl[0][j * n + je[g]];
                 } else {
                     uint32_t spins = 0;
-                    while (true) {
+                    while (!nowait) {
                         bool ready = true;
                         for (int g = 0; g < PE; ++g)
                             for (int j = 0; j < 3; ++j) ready = ready && (uint32_t)(we[g][j] >> 32) == want;
-                        if (ready) break;
-                        if (++spins > kWaitLimit) {
-                            atomicOr(&s.counters->err, kErrInternal);
-                            break;
-                        }
+                        if (ready || stop_waiting(s, ++spins, nowait)) break;
                         __builtin_amdgcn_s_sleep(1);
                         for (int g = 0; g < PE; ++g)
                             for (int j = 0; j < 3; ++j)
@@ -916,7 +934,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                 float xq[PG][3], dq[PG][3];
                 for (int g = 0; g < PG; ++g) {
                     jq[g] = sl + g < cnt ? s.nbr[(sl + g) * n + i] : s.nbr[sl * n + i];
-                    for (int j = 0; j < 3; ++j) xq[g][j] = s.x[j * n + jq[g]];
+                    for (int j = 0; j < 3; ++j) xq[g][j] = s.x0[j * n + jq[g]];
                 }
                 if (it == 0) {                        // X_0 from the integration step
                     for (int g = 0; g < PG; ++g)
@@ -932,11 +950,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                         bool ready = true;
                         for (int g = 0; g < PG; ++g)
                             for (int j = 0; j < 3; ++j) ready = ready && (uint32_t)(w[g][j] >> 32) == want;
-                        if (ready) break;
-                        if (++spins > kWaitLimit) {
-                            atomicOr(&s.counters->err, kErrInternal);
-                            break;
-                        }
+                        if (ready || nowait || stop_waiting(s, ++spins, nowait)) break;
                         __builtin_amdgcn_s_sleep(1);
                     }
                     for (int g = 0; g < PG; ++g)
@@ -1075,8 +1089,13 @@ __global__ void __launch_bounds__(kBlock) k_canonical(Scene s)
     s.sorted[b0 + below] = i;
 }
 
+// End of a frame, in two launches so that a frame is committed whole or not
+// at all: k_check latches a non-finite X_K or V_K; k_commit then writes
+// x = X_init + (X_K - X_init), v = V_K as the new state only if no error has
+// been latched (in this frame or before), so after an error the state stays
+// at the last frame completed without one.
 template <bool MULTI>
-__global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
+__global__ void __launch_bounds__(kBlock) k_check(Scene s, int src)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= s.n) return;
@@ -1088,13 +1107,27 @@ __global__ void __launch_bounds__(kBlock) k_finalize(Scene s, int src)
     bool finite = true;
     for (int k = 0; k < 3; ++k) {
         const size_t j = k * n + i;
-        const float x = s.x[j] + s.dl[src][j];
-        const float v = s.vel[src][j];
-        finite = finite && isfinite(x) && isfinite(v);
-        s.x[j] = x;
-        s.v[j] = v;
+        finite = finite && isfinite(s.x0[j] + s.dl[src][j]) && isfinite(s.vel[src][j]);
     }
     if (!finite) atomicOr(&s.counters->err, kErrNonFinite);
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(kBlock) k_commit(Scene s, int src)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= s.n) return;
+    if (__hip_atomic_load(&s.counters->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrDiscard) return;
+    if (MULTI) {
+        const int32_t sc = s.pscene[i];
+        if (sc < 0 || !s.mscene[sc].active) return;
+    }
+    const size_t n = (size_t)s.n;
+    for (int k = 0; k < 3; ++k) {
+        const size_t j = k * n + i;
+        s.x[j] = s.x0[j] + s.dl[src][j];
+        s.v[j] = s.vel[src][j];
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_clear_counters(Counters* c, NbrStats* st, uint32_t n_slots)
@@ -1268,10 +1301,13 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
             src ^= 1;
         }
     }
-    if (multi)
-        hipLaunchKernelGGL(k_finalize<true>, dim3(nb), dim3(kBlock), 0, stream, s, last);
-    else
-        hipLaunchKernelGGL(k_finalize<false>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+    if (multi) {
+        hipLaunchKernelGGL(k_check<true>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+        hipLaunchKernelGGL(k_commit<true>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+    } else {
+        hipLaunchKernelGGL(k_check<false>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+        hipLaunchKernelGGL(k_commit<false>, dim3(nb), dim3(kBlock), 0, stream, s, last);
+    }
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ static_assert(pbdr::kPoolBigMaxParticles == PBDR_POOL_MAX_PARTICLES, "pool scene
 static_assert(pbdr::kPoolBigMaxBodies == PBDR_POOL_MAX_BODIES, "pool body count");
 
 struct PoolLayout {
-    size_t x, v, mass, q, pbody, dl, xt, sxt4, nbr_n, nbr, save_x, save_v, body_first, body_mass, body_mq, scenes,
+    size_t x, v, x0, mass, q, pbody, dl, xt, sxt4, nbr_n, nbr, save_x, save_v, body_first, body_mass, body_mq, scenes,
         stats, save_stats, order, part, sid, rank, vel, cd, total;
 };
 
@@ -52,6 +52,7 @@ PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
     PoolLayout L;
     L.x = take(12 * p);
     L.v = take(12 * p);
+    L.x0 = take(12 * p);
     L.mass = take(4 * p);
     L.q = take(12 * p);
     L.pbody = take(2 * p);
@@ -144,6 +145,7 @@ struct pbdr_pool {
     // per lane, double-buffered pinned launch lists of (slot, units)
     int2* h_order[kLanes][2] = {};
     hipEvent_t uploaded[kLanes][2] = {};
+    hipEvent_t done[kLanes] = {};        // recorded after each lane's latest launch
     int plan_buf[kLanes] = {};
 };
 
@@ -159,6 +161,7 @@ void release_host(pbdr_pool* p)
             if (p->join[l][c]) (void)hipEventDestroy(p->join[l][c]);
         }
         if (p->fork[l]) (void)hipEventDestroy(p->fork[l]);
+        if (p->done[l]) (void)hipEventDestroy(p->done[l]);
         for (int b = 0; b < 2; ++b) {
             if (p->uploaded[l][b]) (void)hipEventDestroy(p->uploaded[l][b]);
             if (p->h_order[l][b]) (void)hipHostFree(p->h_order[l][b]);
@@ -236,6 +239,7 @@ pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector
         for (int c = 0; c < kLaunchClasses; ++c)
             if (count[c]) HIP_TRY(hipStreamWaitEvent(stream, p->join[lane][c], 0));
     if (t1) HIP_TRY(hipEventRecord(t1, stream));
+    HIP_TRY(hipEventRecord(p->done[lane], stream));
     return PBDR_OK;
 }
 
@@ -246,10 +250,12 @@ pbdr_status scene_status(pbdr_pool* p, int32_t slot, uint32_t* max_nbr)
                            hipMemcpyDeviceToHost, p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
     if (max_nbr) *max_nbr = st.max_nbr;
-    if (st.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity of slot %d became non-finite", slot);
+    // after any of these the slot keeps the state of its last clean frame and is no longer stepped
     if (st.err & pbdr::kErrCapacity)
         return fail(PBDR_ERR_CAPACITY, "a neighbour list of slot %d reached %u entries, above nbr_cap %d", slot, st.max_nbr,
                     p->res.cap);
+    if (st.err & pbdr::kErrNonFinite) return fail(PBDR_ERR_NONFINITE, "a position or velocity of slot %d became non-finite", slot);
+    if (st.err & pbdr::kErrInternal) return fail(PBDR_ERR_DEVICE, "slot %d did not fit its launch shape", slot);
     return PBDR_OK;
 }
 
@@ -351,6 +357,7 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     d.P = max_particles;
     d.x = (float*)(w + lay.x);
     d.v = (float*)(w + lay.v);
+    d.x0 = (float*)(w + lay.x0);
     d.mass = (const float*)(w + lay.mass);
     d.q = (const float*)(w + lay.q);
     d.pbody = (const uint16_t*)(w + lay.pbody);
@@ -378,6 +385,7 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
             if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join[l][k], hipEventDisableTiming);
         }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork[l], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->done[l], hipEventDisableTiming);
         for (int b = 0; b < 2 && e == hipSuccess; ++b) {
             e = hipEventCreateWithFlags(&p->uploaded[l][b], hipEventDisableTiming);
             if (e == hipSuccess) e = hipHostMalloc((void**)&p->h_order[l][b], 8 * (size_t)max_scenes, 0);
@@ -790,6 +798,9 @@ pbdr_status pbdr_pool_info_get(const pbdr_pool* p, pbdr_pool_info* out)
 void pbdr_pool_destroy(pbdr_pool* p)
 {
     if (!p) return;
+    // every lane's work ends before the caller may free the workspace
+    for (int l = 0; l < kLanes; ++l)
+        if (p->done[l]) (void)hipEventSynchronize(p->done[l]);
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     release_host(p);
     delete p;

@@ -42,8 +42,9 @@ struct PoolStat {
 
 struct PoolDev {
     int32_t P;                 // particle capacity = component stride of [3][P] arrays
-    float* x;                  // [3][P] positions (X_init while a substep runs)
-    float* v;                  // [3][P] velocities
+    float* x;                  // [3][P] committed positions (after the last clean frame)
+    float* v;                  // [3][P] committed velocities
+    float* x0;                 // [3][P] X_init of the running substep (read by contact partners)
     const float* mass;         // [P]
     const float* q;            // [3][P] rest offsets
     const uint16_t* pbody;     // [P] scene-local body of each particle

@@ -276,7 +276,7 @@ __device__ inline void contacts(const Ctx& x, int i, const float* x0, const floa
         float dd[3], u[3];
         for (int k = 0; k < 3; ++k) {
             const float dj = d.dl[k * P + gq];
-            dd[k] = (x0[k] - d.x[k * P + gq]) + (del[k] - dj);
+            dd[k] = (x0[k] - d.x0[k * P + gq]) + (del[k] - dj);
             u[k] = del[k] - dj;
         }
         const float l2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
@@ -550,6 +550,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
     const int n = sc.n, nb = sc.nb, p0 = sc.p0, b0 = sc.b0;
     const int units = job.y;
     if (units <= 0 || n <= 0) return;                              // uniform over the workgroup
+    if (d.stats[slot].err & kErrDiscard) return;                   // stays at its last clean frame
     const int total_subs = units * subs_per_unit;
     const int T = blockDim.x, W = T >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     const size_t P = (size_t)d.P;
@@ -607,7 +608,7 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
             const size_t g = (size_t)p0 + i;
             predict_one(x, x0[r], V[r], del[r], xt[r]);
             for (int k = 0; k < 3; ++k) {
-                d.x[k * P + g] = x0[r][k];       // X_init, read by neighbours
+                d.x0[k * P + g] = x0[r][k];      // X_init, read by neighbours
                 d.dl[k * P + g] = del[r][k];
                 if (last_sub) d.xt[k * P + g] = xt[r][k];
             }
@@ -713,15 +714,21 @@ __global__ void __launch_bounds__(LB) k_pool(PoolDev d, PoolConsts c, int first,
             }
         }
         if (!finite) atomicOr(&misc[16], kErrNonFinite);
-    }
-    // state out
+        // ---- end of a unit (a frame, or a substep of pbdr_pool_substep): the
+        // state is committed only if the scene has latched no error, so after
+        // one it keeps the last unit completed without it
+        if ((sub + 1) % subs_per_unit == 0) {
+            __syncthreads();
+            if (misc[16]) break;                                   // uniform: read after the barrier
 #pragma unroll
-    for (int r = 0; r < S; ++r) {
-        if (!act[r]) continue;
-        const size_t g = (size_t)p0 + pid[r];
-        for (int k = 0; k < 3; ++k) {
-            d.x[k * P + g] = x0[r][k];
-            d.v[k * P + g] = V[r][k];
+            for (int r = 0; r < S; ++r) {
+                if (!act[r]) continue;
+                const size_t g = (size_t)p0 + pid[r];
+                for (int k = 0; k < 3; ++k) {
+                    d.x[k * P + g] = x0[r][k];
+                    d.v[k * P + g] = V[r][k];
+                }
+            }
         }
     }
     __syncthreads();
@@ -762,6 +769,7 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
     const int n = sc.n, nb = sc.nb, p0 = sc.p0, b0 = sc.b0;
     const int units = job.y;
     if (units <= 0 || n <= 0) return;                                   // uniform over the workgroup
+    if (d.stats[slot].err & kErrDiscard) return;                        // stays at its last clean frame
     const int total_subs = units * subs_per_unit;
     const int T = blockDim.x, W = T >> 6, wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tid = threadIdx.x;
     const size_t P = (size_t)d.P;
@@ -791,9 +799,15 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
             if (act) {
                 const size_t g = (size_t)p0 + i;
                 float x0[3], V[3], del[3];
-                load3(d.x, P, g, x0);
-                load3(d.v, P, g, V);
+                if (sub % subs_per_unit == 0) {        // first substep of a unit: the committed state
+                    load3(d.x, P, g, x0);
+                    load3(d.v, P, g, V);
+                } else {                               // X_K, V_K of the previous substep
+                    load3(d.x0, P, g, x0);
+                    load3(velg, P, g, V);
+                }
                 predict_one(x, x0, V, del, xt);
+                store3(d.x0, P, g, x0);
                 store3(d.dl, P, g, del);
                 store3(velg, P, g, V);
                 store3(d.xt, P, g, xt);
@@ -866,7 +880,7 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
                 if (act) {
                     const size_t g = (size_t)p0 + i;
                     float Cd[3];
-                    load3(d.x, P, g, x0);
+                    load3(d.x0, P, g, x0);
                     load3(d.dl, P, g, del);
                     load3(d.q, P, g, q);
                     m = d.mass[g];
@@ -888,7 +902,7 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
                       V[3] = {0.0f, 0.0f, 0.0f}, Cd[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f;
                 if (act) {
                     const size_t g = (size_t)p0 + i;
-                    load3(d.x, P, g, x0);
+                    load3(d.x0, P, g, x0);
                     load3(d.dl, P, g, del);
                     load3(d.q, P, g, q);
                     load3(velg, P, g, V);
@@ -908,7 +922,7 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
                 if (lane >= (st.x >> 16)) continue;
                 const size_t g = (size_t)p0 + i;
                 float x0[3], del[3], q[3], V[3], Cd[3];
-                load3(d.x, P, g, x0);
+                load3(d.x0, P, g, x0);
                 load3(d.dl, P, g, del);
                 load3(d.q, P, g, q);
                 load3(velg, P, g, V);
@@ -919,7 +933,7 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
             }
             __syncthreads();
         }
-        // ---- end of substep: X_K, V_K become the state ---------------------------
+        // ---- end of substep: X_K (into the X_init buffer) and V_K ---------------
         bool finite = true;
         for (int s = wave; s < n_slots; s += W) {
             const int2 st = slot_tab[s];
@@ -927,18 +941,31 @@ __global__ void __launch_bounds__(64 * kBigWaves) k_pool_big(PoolDev d, PoolCons
             if (lane >= (st.x >> 16)) continue;
             const size_t g = (size_t)p0 + i;
             float x0[3], del[3], V[3];
-            load3(d.x, P, g, x0);
+            load3(d.x0, P, g, x0);
             load3(d.dl, P, g, del);
             load3(velg, P, g, V);
             for (int k = 0; k < 3; ++k) {
                 x0[k] = x0[k] + del[k];
                 finite = finite && isfinite(x0[k]) && isfinite(V[k]);
             }
-            store3(d.x, P, g, x0);
-            store3(d.v, P, g, V);
+            store3(d.x0, P, g, x0);
         }
         if (!finite) atomicOr(&misc[16], kErrNonFinite);
         __syncthreads();
+        // ---- end of a unit: committed only without a latched error ---------------
+        if ((sub + 1) % subs_per_unit == 0) {
+            if (misc[16]) break;                                   // uniform: read after the barrier
+            for (int s = wave; s < n_slots; s += W) {
+                const int2 st = slot_tab[s];
+                if (lane >= (st.x >> 16)) continue;
+                const size_t g = (size_t)p0 + st.y + lane;
+                float x0[3], V[3];
+                load3(d.x0, P, g, x0);
+                load3(velg, P, g, V);
+                store3(d.x, P, g, x0);
+                store3(d.v, P, g, V);
+            }
+        }
     }
     if (tid == 0) latch(d, slot, misc);
 }

@@ -346,6 +346,57 @@ def test_capacity_overflow_is_reported(orc):
     assert s.neighbour_stats()[0] == 8
 
 
+def _raw_state(s):
+    """Status of pbdr_scene_read_state and the state it copied out (no exception)."""
+    x = np.empty((3, s.n), dtype=np.float32)
+    v = np.empty((3, s.n), dtype=np.float32)
+    st = s._lib.pbdr_scene_read_state(s._h, x.ctypes.data, v.ctypes.data, 0)
+    return st, x, v
+
+
+@pytest.mark.parametrize("flags", [0, B.FLAG_ITERATION_LAUNCHES, B.FLAG_NO_GRAPH])
+def test_capacity_overflow_keeps_the_last_clean_frame(orc, flags):
+    # lattice B slides into lattice A, offset by half a spacing across the
+    # contact face: until the faces meet no particle has a neighbour, then
+    # every face particle has 4, above nbr_cap = 3.  The frame in which the
+    # lists overflow is discarded: the state stays at the frame before it, also
+    # through later steps, until set_state clears the condition.
+    r = 0.01
+    off = scenes.lattice_box(4, 4, 4, 2 * r)
+    sc = scenes.from_bodies([off + np.array([[0.0], [0.5], [0.5]]), off + np.array([[0.2], [0.5 + r], [0.5 + r]])],
+                            [np.zeros(3), np.array([-1.5, 0.0, 0.0])], [0.01, 0.01], radius=r,
+                            gravity=(0.0, 0.0, 0.0), planes=())
+    p = B.params_for(sc, nbr_cap=3, flags=flags)
+    s = B.Solver(p, sc.x, sc.v, sc.mass, sc.body_start)
+    kind = s.info().iteration_kernel
+    print("[capacity] flags %#x, iteration kernel %d" % (flags, kind), flush=True)
+    if flags == 0:
+        assert kind == 2                                   # the one-launch form is the one under test
+    st, xp, vp = _raw_state(s)
+    assert st == B.OK
+    hit = None
+    for f in range(40):
+        s.step(1)
+        st, x, v = _raw_state(s)
+        if st != B.OK:
+            hit = f
+            break
+        xp, vp = x, v
+    assert hit is not None and hit > 0, "the lists never overflowed"
+    assert st == B.ERR_CAPACITY, B.last_error()
+    np.testing.assert_array_equal(x, xp)                   # the overflowing frame was not committed
+    np.testing.assert_array_equal(v, vp)
+    s.step(3)
+    st, x, v = _raw_state(s)
+    assert st == B.ERR_CAPACITY
+    np.testing.assert_array_equal(x, xp)
+    np.testing.assert_array_equal(v, vp)
+    s.set_state(xp, vp)                                    # clears the condition
+    st, _, _ = _raw_state(s)
+    assert st == B.OK
+    print("[capacity] overflow in frame %d; state kept at frame %d" % (hit + 1, hit), flush=True)
+
+
 def test_non_finite_state_is_reported():
     import torch
 
@@ -358,6 +409,11 @@ def test_non_finite_state_is_reported():
     s.substep(1)
     with pytest.raises(B.PbdrError) as e:
         s.read_state()
+    # the frame was discarded: the state is still the one that was set
+    st, xs, vs = _raw_state(s)
+    assert st == B.ERR_NONFINITE
+    np.testing.assert_array_equal(xs, x.cpu().numpy())
+    np.testing.assert_array_equal(vs, v.cpu().numpy())
     assert e.value.status == B.ERR_NONFINITE
 
 
