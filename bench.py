@@ -137,6 +137,32 @@ def host_cpu() -> str:
     return "%s, %d logical CPUs" % (model, os.cpu_count() or 1)
 
 
+class Roctx:
+    """roctx ranges of the profiler SDK, when its library is present: the timed
+    frames (and the calibration copy) are named ranges in a trace."""
+
+    def __init__(self):
+        import ctypes
+
+        self.lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", "librocprofiler-sdk-roctx.so"):
+            try:
+                self.lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+        if self.lib is not None:
+            self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+
+    def begin(self, name: str):
+        if self.lib is not None:
+            self.lib.roctxRangePushA(name.encode())
+
+    def end(self):
+        if self.lib is not None:
+            self.lib.roctxRangePop()
+
+
 def oracle_threads(requested: int) -> int:
     return max(1, min(requested, os.cpu_count() or 1))
 
@@ -205,12 +231,16 @@ def bench_pool(args):
     tuned = pool.autotune(n_frames=2, repeats=1)
     print("[bench] tuned waves per class %s (ms %s)" % (pool.tuning, ["%.2f" % t for t in tuned]), file=sys.stderr,
           flush=True)
-    pool.step(args.warmup)
+    # a step is one frame of every scene: pbdr_pool_step replays the captured
+    # graph of the class launches (captured on the first call)
+    for _ in range(max(1, args.warmup)):
+        pool.step(1)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    pool.step(args.steps)
+    for _ in range(args.steps):
+        pool.step(1)
     t1.record(stream)
     torch.cuda.synchronize()
     ms = t0.elapsed_time(t1)
@@ -218,6 +248,16 @@ def bench_pool(args):
     for sl in slots:
         mx = max(mx, pool.check(sl))
     value = N * S * args.steps / (ms / 1e3)
+    # the same frames as direct launches (pbdr_pool_step_slots over every scene)
+    ones = [1] * len(slots)
+    pool.step_slots(slots, ones)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        pool.step_slots(slots, ones)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    direct = N * S * args.steps / (t0.elapsed_time(t1) / 1e3)
     # per-scene launches of the single-scene solver on a sample, for comparison
     rng = np.random.default_rng(args.seed)
     pick = rng.choice(len(batch), 16, replace=False)
@@ -236,13 +276,13 @@ def bench_pool(args):
         tot_n += batch[j].n
         sv.close()
     per_scene = tot_n * S * 8 / (tot_ms / 1e3)
-    print("[bench] %d frames in %.3f ms: %.4g particle-substeps/s (per-scene launches: %.4g)"
-          % (args.steps, ms, value, per_scene), file=sys.stderr, flush=True)
+    print("[bench] %d frames in %.3f ms: %.4g particle-substeps/s from the graph (direct launches: %.4g; "
+          "per-scene launches: %.4g)" % (args.steps, ms, value, direct, per_scene), file=sys.stderr, flush=True)
     bpps = pool_bytes_per_particle_substep(batch[0].iterations, 0.0)
     achieved = value * bpps / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_pool (one workgroup per scene, all substeps of the call)",
+            "kernel": "k_pool (one workgroup per scene, all substeps of the call), replayed from a HIP graph",
             "us_per_call": round(ms * 1e3 / args.steps, 1), "bytes_per_particle_substep": bpps,
             "note": "state stays on chip across iterations, so HBM carries far less than the algorithmic bytes"}
     cpu = None if args.no_cpu_baseline else cpu_baseline_scenes(batch, args.cpu_budget_s, "batch_4096",
@@ -254,7 +294,8 @@ def bench_pool(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch_4096", "scenes": len(batch), "particles": N, "bodies": NB, "substeps": S,
                    "iterations": batch[0].iterations, "seed": args.seed, "max_neighbours": mx,
-                   "per_scene_launch_rate": round(per_scene, 1), "tuned_waves": pool.tuning},
+                   "per_scene_launch_rate": round(per_scene, 1), "direct_launch_rate": round(direct, 1),
+                   "tuned_waves": pool.tuning},
         "roofline": roof, "cpu_baseline": cpu,
     }
     pool.close()
@@ -374,9 +415,13 @@ def main():
         nbytes = args.calibrate_copy_mib << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        cal = Roctx()
+        cal.begin("calibration copy")
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
+        cal.end()
         print("[bench] calibration copy: %d bytes read and %d bytes written per launch" % (nbytes, nbytes),
               file=sys.stderr, flush=True)
         del src, dst
@@ -390,8 +435,13 @@ def main():
     settle = args.settle if args.settle is not None else SETTLE_FRAMES.get(args.workload, 0)
     if settle:
         print("[bench] settling %d frames (untimed)" % settle, file=sys.stderr, flush=True)
-        solver.step(settle)
-        solver.check()
+        done = 0
+        while done < settle:
+            chunk = min(40, settle - done)
+            solver.step(chunk)
+            solver.check()
+            done += chunk
+            print("[bench]   settled %d frames" % done, file=sys.stderr, flush=True)
         # the neighbour statistics restart here (setting the same state clears
         # them), so the mean list length is that of the warm-up and timed frames
         xd = torch.empty((3, sc.n), dtype=torch.float32, device="cuda")
@@ -406,12 +456,15 @@ def main():
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    marks = Roctx()
+    marks.begin("timed frames: %s" % sc.name)
     wall0 = time.perf_counter()
     t_start.record(stream)
     solver.step(args.steps)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
+    marks.end()
     ms = t_start.elapsed_time(t_end)
     solver.check()
     max_nbr, kbar = solver.neighbour_stats()

@@ -160,7 +160,7 @@ int32_t pbdr_abi_version(void);
  * them is discarded (see Conventions). */
 #define PBDR_COND_CAPACITY 0x1u      /* a neighbour list exceeded nbr_cap            */
 #define PBDR_COND_NONFINITE 0x2u     /* a position or velocity became NaN/Inf        */
-#define PBDR_COND_SCAN_WAIT 0x4u     /* the cell-table scan's look-back gave up      */
+#define PBDR_COND_SORT_WAIT 0x4u     /* the key sort's look-back gave up             */
 #define PBDR_COND_PARTNER_WAIT 0x8u  /* a one-launch iteration's wait for a contact
                                         partner gave up (its workgroups were not all
                                         resident together)                           */
@@ -250,8 +250,11 @@ pbdr_status pbdr_scene_neighbour_stats(pbdr_scene* scene, int32_t* max_neighbour
 /* Debug buffers of the last substep, copied to HOST memory (synchronises):
  *  PBDR_DEBUG_XT          float [3][N] FP32 predicted positions (index input)
  *  PBDR_DEBUG_KEYS        uint32 [N]   cell key of each particle
- *  PBDR_DEBUG_SORTED      uint32 [N]   particle ids sorted by (key, id)
- *  PBDR_DEBUG_CELL_START  uint32 [2^k] first sorted slot of each key
+ *  PBDR_DEBUG_SORTED      uint32 [N]   particle ids sorted by (key, id): the
+ *                                      order of the substep's radix sort
+ *  PBDR_DEBUG_CELL_START  uint32 [2^k] first sorted slot of each key (for an
+ *                                      empty key, that of the next occupied
+ *                                      key, or N)
  *  PBDR_DEBUG_CELL_COUNT  uint32 [2^k] particles per key
  *  PBDR_DEBUG_NBR_COUNT   uint32 [N]   neighbour-list lengths
  *  PBDR_DEBUG_NBR         uint32 [nbr_cap][N] lists, slot-major, ascending

@@ -25,7 +25,7 @@ DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3
 DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8
 MAX_PLANES = 8
 MAX_TIMED_LAUNCHES = 4096
-COND_CAPACITY, COND_NONFINITE, COND_SCAN_WAIT, COND_PARTNER_WAIT = 0x1, 0x2, 0x4, 0x8
+COND_CAPACITY, COND_NONFINITE, COND_SORT_WAIT, COND_PARTNER_WAIT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "pbdr_abi_version", "pbdr_last_error", "pbdr_condition_status", "pbdr_scene_bytes", "pbdr_scene_create",

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -36,7 +37,7 @@ void clear_error() { g_err[0] = 0; }
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
 static_assert(pbdr::kErrCapacity == PBDR_COND_CAPACITY && pbdr::kErrNonFinite == PBDR_COND_NONFINITE &&
-                  pbdr::kErrInternal == PBDR_COND_SCAN_WAIT && pbdr::kErrWait == PBDR_COND_PARTNER_WAIT,
+                  pbdr::kErrInternal == PBDR_COND_SORT_WAIT && pbdr::kErrWait == PBDR_COND_PARTNER_WAIT,
               "latched condition bits");
 
 pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap)
@@ -58,7 +59,7 @@ pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap)
                     "a one-launch iteration gave up waiting for a contact partner (workgroups not resident together; "
                     "PBDR_FLAG_ITERATION_LAUNCHES avoids the form); the frame was discarded");
     if (err & pbdr::kErrInternal)
-        return fail(PBDR_ERR_DEVICE, "the cell-table scan gave up waiting for a preceding tile; the frame was discarded");
+        return fail(PBDR_ERR_DEVICE, "the key sort gave up waiting for a preceding tile; the frame was discarded");
     return PBDR_OK;
 }
 
@@ -117,10 +118,15 @@ using pbdr::host::resolve;
 using pbdr::host::g_err;
 
 struct Layout {
-    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank,
-        sorted_raw, sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, wave_body,
+    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1,
+        ibuf0, ibuf1, nbr_n, nbr, hist, tile_ctr, radix_state, cells, body_rot, counters, nbr_stats, wave_body,
         body_wave0, block_body, tagged, body_mq, body_out, total;
 };
+
+// Passes of the key sort (8-bit digits) for keys of `bits` bits.
+int radix_passes(int bits) { return std::max(1, (bits + pbdr::kRadixBits - 1) / pbdr::kRadixBits); }
+
+size_t radix_tiles(size_t n) { return (n + pbdr::kRadixTile - 1) / pbdr::kRadixTile; }
 
 // Upper bound on the padded wave count of the iteration kernel's body packing
 // (both launches together): each body needs ceil(n_b / 64) <= n_b / 64 + 1
@@ -138,7 +144,6 @@ size_t max_iteration_waves(int32_t n, int32_t nb)
 Layout make_layout(int32_t n, int32_t nb, int k, int cap)
 {
     const size_t N = (size_t)n, B = (size_t)nb, T = (size_t)1 << k;
-    const size_t tiles = (T + pbdr::kScanTile - 1) / pbdr::kScanTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -161,14 +166,16 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.xt = take(12 * N);
     L.sxt4 = take(16 * N);
     L.key = take(4 * N);
-    L.rank = take(4 * N);
-    L.sorted_raw = take(4 * N);
-    L.sorted = take(4 * N);
+    L.kbuf0 = take(4 * N);
+    L.kbuf1 = take(4 * N);
+    L.ibuf0 = take(4 * N);
+    L.ibuf1 = take(4 * N);
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
-    L.cell_count = take(4 * T);
-    L.cells = take(8 * (T + 1));
-    L.tile_state = take(8 * tiles);
+    L.hist = take(4 * pbdr::kMaxRadixPasses * pbdr::kRadixBins);
+    L.tile_ctr = take(4 * pbdr::kMaxRadixPasses);
+    L.radix_state = take(8 * pbdr::kRadixBins * radix_tiles(N));
+    L.cells = take(16 * T);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
     L.nbr_stats = take(sizeof(pbdr::NbrStats) * ((N + pbdr::kBlock - 1) / pbdr::kBlock));
@@ -201,6 +208,12 @@ struct pbdr_scene {
     size_t ws_bytes = 0;
     int max_body = 0;
     bool stepped = false;
+    bool fixed_record = false;           // a reused host record (not freed by destroy)
+    // the one-launch iteration form: possible for this scene (its grid alone
+    // is resident at once), and the number of its workgroups the device holds
+    bool one_launch_ok = false;
+    int one_launch_capacity = 0;
+    int device = 0;
 };
 
 namespace {
@@ -208,6 +221,48 @@ namespace {
 // Frames per graph for long step() calls: replaying one graph per frame
 // leaves the GPU waiting on the host between graphs.
 constexpr int kGraphFrames = 8;
+
+// Scenes that can run their iterations as one launch, per process.  The
+// one-launch kernel's workgroups wait for each other, so they must all be
+// resident at once: a scene takes that form only while its grid and the
+// grids of every such scene on another stream of its device fit on the device
+// together (scenes on one stream run one after another).  Otherwise the call
+// uses one launch per iteration (the same arithmetic, no waits).
+std::mutex g_one_launch_mu;
+std::vector<pbdr_scene*> g_one_launch;
+
+void drop_graph(pbdr_scene* s);
+
+void one_launch_register(pbdr_scene* s)
+{
+    if (!s->one_launch_ok) return;
+    std::lock_guard<std::mutex> lock(g_one_launch_mu);
+    g_one_launch.push_back(s);
+}
+
+void one_launch_unregister(pbdr_scene* s)
+{
+    std::lock_guard<std::mutex> lock(g_one_launch_mu);
+    g_one_launch.erase(std::remove(g_one_launch.begin(), g_one_launch.end(), s), g_one_launch.end());
+}
+
+// Chooses the iteration form of the next enqueued work (drops graphs
+// captured with the other form).
+void choose_iteration_form(pbdr_scene* s)
+{
+    int want = 0;
+    if (s->one_launch_ok) {
+        std::lock_guard<std::mutex> lock(g_one_launch_mu);
+        long long blocks = s->dev.n_iter_blocks;
+        for (const pbdr_scene* o : g_one_launch)
+            if (o != s && o->device == s->device && o->stream != s->stream) blocks += o->dev.n_iter_blocks;
+        want = blocks <= (long long)s->one_launch_capacity ? 1 : 0;
+    }
+    if (want != s->dev.resident_iterate) {
+        drop_graph(s);
+        s->dev.resident_iterate = want;
+    }
+}
 
 // The second iteration launch of a split packing, or NULL.
 const pbdr::Scene* second_launch(const pbdr_scene* s) { return s->split ? &s->dev2 : nullptr; }
@@ -287,7 +342,10 @@ void pbdr::host::fill_step_consts(const Resolved& r, pbdr::StepConsts* out)
     for (int j = 0; j < r.p.n_planes; ++j) {
         for (int k = 0; k < 3; ++k) c.plane_n[j][k] = (float)r.p.planes[j][k];
         c.plane_d[j] = (float)r.p.planes[j][3];
+        c.plane_d_d[j] = r.p.planes[j][3];
     }
+    c.radius_d = r.p.radius;
+    c.two_r_d = 2.0 * r.p.radius;
 }
 
 namespace {
@@ -300,7 +358,9 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.n = n;
     d.nb = nb;
     d.T = (uint32_t)(1ull << s->res.k);
-    d.n_scan_tiles = (uint32_t)(((size_t)d.T + pbdr::kScanTile - 1) / pbdr::kScanTile);
+    d.n_sort = n;
+    d.radix_passes = radix_passes(s->res.k);
+    d.n_radix_tiles = (uint32_t)radix_tiles((size_t)n);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
     d.x0 = (float*)(w + L.x0);
@@ -316,14 +376,18 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.xt = (float*)(w + L.xt);
     d.sxt4 = (float4*)(w + L.sxt4);
     d.key = (uint32_t*)(w + L.key);
-    d.rank = (uint32_t*)(w + L.rank);
-    d.sorted_raw = (uint32_t*)(w + L.sorted_raw);
-    d.sorted = (uint32_t*)(w + L.sorted);
+    d.kbuf[0] = (uint32_t*)(w + L.kbuf0);
+    d.kbuf[1] = (uint32_t*)(w + L.kbuf1);
+    d.ibuf[0] = (uint32_t*)(w + L.ibuf0);
+    d.ibuf[1] = (uint32_t*)(w + L.ibuf1);
+    d.skey = d.kbuf[(d.radix_passes - 1) & 1];
+    d.sorted = d.ibuf[(d.radix_passes - 1) & 1];
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
-    d.cell_count = (uint32_t*)(w + L.cell_count);
-    d.cells = (uint2*)(w + L.cells);
-    d.tile_state = (unsigned long long*)(w + L.tile_state);
+    d.hist = (uint32_t*)(w + L.hist);
+    d.tile_ctr = (uint32_t*)(w + L.tile_ctr);
+    d.radix_state = (unsigned long long*)(w + L.radix_state);
+    d.cells = (uint4*)(w + L.cells);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
     d.nbr_stats = (pbdr::NbrStats*)(w + L.nbr_stats);
@@ -349,6 +413,7 @@ pbdr_status check_host_finite(const float* a, size_t count, const char* what)
 
 pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
 {
+    choose_iteration_form(s);
     hipError_t e = pbdr::enqueue_substeps(s->dev, second_launch(s), s->consts, s->res.p.iterations, substeps_total,
                                           s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -403,8 +468,14 @@ size_t pbdr_scene_bytes(const pbdr_params* params, int32_t n_particles, int32_t 
     return make_layout(n_particles, n_bodies, r.k, r.cap).total;
 }
 
-pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* desc, void* dev_workspace,
-                              size_t ws_bytes, void* hip_stream, pbdr_scene** out)
+}  // extern "C"
+
+namespace {
+
+// pbdr_scene_create into `dev_workspace`; `fixed` (or NULL) is the host
+// record to fill instead of a new one (the static scene of a device).
+pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc, void* dev_workspace,
+                         size_t ws_bytes, void* hip_stream, pbdr_scene* fixed, pbdr_scene** out)
 {
     g_err[0] = 0;
     if (!out) return fail(PBDR_ERR_INVALID_ARG, "out is NULL");
@@ -440,8 +511,18 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     if (((uintptr_t)dev_workspace & 255u) != 0) return fail(PBDR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < lay.total) return fail(PBDR_ERR_WORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
 
-    pbdr_scene* s = new (std::nothrow) pbdr_scene();
-    if (!s) return fail(PBDR_ERR_INVALID_ARG, "out of host memory");
+    pbdr_scene* s = fixed;
+    if (s) {
+        *s = pbdr_scene();
+        s->fixed_record = true;
+        r.p.flags |= PBDR_FLAG_NO_GRAPH;       // direct launches: capturing a graph would allocate
+    } else {
+        s = new (std::nothrow) pbdr_scene();
+        if (!s) return fail(PBDR_ERR_INVALID_ARG, "out of host memory");
+    }
+    auto discard = [&]() {
+        if (!fixed) delete s;
+    };
     s->res = r;
     s->lay = lay;
     s->stream = (hipStream_t)hip_stream;
@@ -500,6 +581,7 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
     // the bodies of up to 4 waves workgroups of 4 waves (so that more of them
     // share a CU) and the larger ones a second launch of W-wave workgroups.
     s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
+    s->dev.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
     s->split = false;
     if (s->dev.dense_iterate && W > 4) {
         wave_body.clear();
@@ -509,27 +591,33 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         s->dev.waves_per_block = 4;
         s->dev.n_iter_blocks = (int32_t)(wave_body.size() / 4);
         s->dev.dense_iterate = s->dev.n_iter_blocks > cus * 4 ? 1 : 0;
+        s->dev.wide_bodies = 0;
     }
     const size_t waves_total = wave_body.size() + wave_body2.size();
     const size_t blocks_total = (block_body.size() + block_body2.size()) / 2;
     if (waves_total > max_iteration_waves(n, nb) || blocks_total > max_iteration_waves(n, nb) / 4 + 2) {
-        delete s;
+        discard();
         return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
     }
     // all iterations of a substep in one launch when every workgroup of the
     // single iteration launch is resident at once (and K fits the 6-bit
     // iteration field of the tags)
+    (void)hipGetDevice(&s->device);
     if (!s->split && !s->dev.dense_iterate && !(s->res.p.flags & PBDR_FLAG_ITERATION_LAUNCHES) &&
-        s->dev.n_iter_blocks > 0 && s->res.p.iterations < 64 &&
-        s->dev.n_iter_blocks <= pbdr::resident_iterate_capacity(s->dev.waves_per_block))
-        s->dev.resident_iterate = 1;
+        s->dev.n_iter_blocks > 0 && s->res.p.iterations < 64) {
+        s->one_launch_capacity = pbdr::resident_iterate_capacity(s->dev.waves_per_block);
+        s->one_launch_ok = s->dev.n_iter_blocks <= s->one_launch_capacity;
+    }
+    s->dev.resident_iterate = s->one_launch_ok ? 1 : 0;
     s->dev2 = s->dev;
     if (s->split) {
         s->dev2.wave_body = s->dev.wave_body + wave_body.size();
         s->dev2.block_body = s->dev.block_body + block_body.size();
         s->dev2.waves_per_block = W;
         s->dev2.n_iter_blocks = (int32_t)(wave_body2.size() / (size_t)W);
-        s->dev2.dense_iterate = s->dev2.n_iter_blocks > cus * (16 / W) ? 1 : 0;
+        // bodies of more than 4 waves: the kernel with FP64 shape-matching sums
+        s->dev2.dense_iterate = 0;
+        s->dev2.wide_bodies = 1;
         wave_body.insert(wave_body.end(), wave_body2.begin(), wave_body2.end());
         block_body.insert(block_body.end(), block_body2.begin(), block_body2.end());
     }
@@ -575,16 +663,53 @@ pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* 
         if (e == hipSuccess) e = h2d(lay.body_mq, bmq.data(), 12 * (size_t)nb);
     }
     if (e == hipSuccess) e = pbdr::enqueue_clear_counters(s->dev, s->stream);
-    if (e == hipSuccess) e = pbdr::enqueue_init_tables(s->dev, s->stream);
+    if (e == hipSuccess) e = pbdr::enqueue_init_tables(s->dev, (size_t)s->dev.T, s->stream);
     // one-launch iterations: no tag may match before it is written
-    if (e == hipSuccess) e = hipMemsetAsync(s->dev.tagged, 0, 48 * (size_t)n, s->stream);
+    if (e == hipSuccess) e = pbdr::enqueue_zero(s->dev.tagged, 48 * (size_t)n, s->stream);
+    // the sort's buffers hold valid ids and keys from the start
+    if (e == hipSuccess) e = pbdr::enqueue_zero(s->ws + lay.kbuf0, lay.nbr_n - lay.kbuf0, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) {
-        delete s;
+        discard();
         return fail(PBDR_ERR_DEVICE, "scene upload failed: %s", hipGetErrorString(e));
     }
+    one_launch_register(s);
     *out = s;
     return PBDR_OK;
+}
+
+constexpr int kFixedRecords = 64;
+pbdr_scene g_fixed_scene[kFixedRecords];     // host records that are reused, not allocated
+
+}  // namespace
+
+pbdr_scene* pbdr::host::fixed_scene_record(int index)
+{
+    return index >= 0 && index < kFixedRecords ? &g_fixed_scene[index] : nullptr;
+}
+
+void pbdr::host::release_fixed_record(pbdr_scene* record)
+{
+    if (record && record->ws) {
+        (void)hipStreamSynchronize(record->stream);
+        one_launch_unregister(record);
+        record->ws = nullptr;
+    }
+}
+
+pbdr_status pbdr::host::create_scene_in(const pbdr_params* params, const pbdr_scene_desc* desc,
+                                        void* dev_workspace, size_t ws_bytes, void* hip_stream,
+                                        pbdr_scene* record, pbdr_scene** out)
+{
+    return create_scene(params, desc, dev_workspace, ws_bytes, hip_stream, record, out);
+}
+
+extern "C" {
+
+pbdr_status pbdr_scene_create(const pbdr_params* params, const pbdr_scene_desc* desc, void* dev_workspace,
+                              size_t ws_bytes, void* hip_stream, pbdr_scene** out)
+{
+    return create_scene(params, desc, dev_workspace, ws_bytes, hip_stream, nullptr, out);
 }
 
 pbdr_status pbdr_scene_set_accel(pbdr_scene* s, const float* accel_dev)
@@ -600,6 +725,7 @@ pbdr_status pbdr_scene_set_stream(pbdr_scene* s, void* hip_stream)
 {
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     HIP_TRY(hipStreamSynchronize(s->stream));
+    std::lock_guard<std::mutex> lock(g_one_launch_mu);
     s->stream = (hipStream_t)hip_stream;
     return PBDR_OK;
 }
@@ -614,6 +740,7 @@ pbdr_status pbdr_scene_step(pbdr_scene* s, int32_t n_frames)
         if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
         return enqueue(s, (int32_t)total);
     }
+    choose_iteration_form(s);
     int32_t left = n_frames;
     if (left >= kGraphFrames) {
         pbdr_status st = capture(s, kGraphFrames, &s->graph_n, &s->exec_n);
@@ -634,6 +761,7 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
     if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
+    choose_iteration_form(s);
     hipError_t e = pbdr::enqueue_iterations(s->dev, second_launch(s), s->consts, s->res.p.iterations, n_launches,
                                             s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -651,6 +779,7 @@ pbdr_status pbdr_scene_time_iterations(pbdr_scene* s, int32_t n_launches, float*
         for (int32_t i = 0; i < n_launches; ++i) out_us[i] = 0.0f;
         return PBDR_OK;
     }
+    choose_iteration_form(s);
     std::vector<hipEvent_t> ev(2 * (size_t)n_launches, nullptr);
     auto release = [&]() {
         for (hipEvent_t e : ev)
@@ -774,18 +903,27 @@ pbdr_status pbdr_scene_read_debug(pbdr_scene* s, int32_t what, void* dst)
     case PBDR_DEBUG_KEYS: off = s->lay.key; bytes = 4 * N; break;
     case PBDR_DEBUG_SORTED:
         if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
-        HIP_TRY(pbdr::enqueue_canonical_order(s->dev, s->stream));
-        off = s->lay.sorted;
+        off = (size_t)((const char*)s->dev.sorted - s->ws);
         bytes = 4 * N;
         break;
     case PBDR_DEBUG_CELL_START:
-    case PBDR_DEBUG_CELL_COUNT: {   // fields of the per-key entries
-        std::vector<uint32_t> e(2 * (T + 1));
-        HIP_TRY(hipMemcpyAsync(e.data(), s->ws + s->lay.cells, 8 * (T + 1), hipMemcpyDeviceToHost, s->stream));
+    case PBDR_DEBUG_CELL_COUNT: {   // the per-key entries of the last substep
+        if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
+        std::vector<uint32_t> e(4 * T);
+        pbdr::Counters c;
+        HIP_TRY(hipMemcpyAsync(e.data(), s->ws + s->lay.cells, 16 * T, hipMemcpyDeviceToHost, s->stream));
+        HIP_TRY(hipMemcpyAsync(&c, s->ws + s->lay.counters, sizeof(c), hipMemcpyDeviceToHost, s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         uint32_t* out = (uint32_t*)dst;
-        for (size_t k = 0; k < T; ++k)
-            out[k] = what == PBDR_DEBUG_CELL_START ? e[2 * k] : e[2 * (k + 1)] - e[2 * k];
+        // an entry of an earlier substep is an empty key, whose first slot is
+        // that of the next occupied key (or N)
+        uint32_t next = (uint32_t)N;
+        for (size_t k = T; k-- > 0;) {
+            const uint32_t* ek = e.data() + 4 * k;
+            const bool occ = ek[3] == c.epoch;
+            if (occ) next = ek[0];
+            out[k] = what == PBDR_DEBUG_CELL_START ? next : (occ ? ek[1] - ek[0] : 0u);
+        }
         return PBDR_OK;
     }
     case PBDR_DEBUG_NBR_COUNT: off = s->lay.nbr_n; bytes = 4 * N; break;
@@ -824,8 +962,13 @@ void pbdr_scene_destroy(pbdr_scene* s)
     if (!s) return;
     // the scene's work ends before the caller may free the workspace
     (void)hipStreamSynchronize(s->stream);
+    one_launch_unregister(s);
     drop_graph(s);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->fixed_record) {         // a reused host record: released, not freed
+        s->ws = nullptr;
+        return;
+    }
     delete s;
 }
 

@@ -42,8 +42,9 @@ int table_bits(int32_t n)
 }
 
 struct BLayout {
-    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, rank, sorted_raw,
-        sorted, nbr_n, nbr, cell_count, cells, tile_state, body_rot, counters, nbr_stats, body_mq, pscene, plan, total;
+    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1, ibuf0,
+        ibuf1, nbr_n, nbr, hist, tile_ctr, radix_state, cells, body_rot, counters, nbr_stats, body_mq, pscene, plan,
+        total;
     size_t plan_bytes, mscene_off, wave_off, block_off, wave0_off;   // within the plan region
     size_t max_waves, max_blocks;
 };
@@ -60,7 +61,7 @@ size_t batch_max_waves(int32_t P, int32_t B, int32_t S)
 BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
 {
     const size_t N = (size_t)P, B = (size_t)BC;
-    const size_t tiles = (K + pbdr::kScanTile - 1) / pbdr::kScanTile;
+    const size_t tiles = (N + pbdr::kRadixTile - 1) / pbdr::kRadixTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -83,14 +84,16 @@ BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
     L.xt = take(12 * N);
     L.sxt4 = take(16 * N);
     L.key = take(4 * N);
-    L.rank = take(4 * N);
-    L.sorted_raw = take(4 * N);
-    L.sorted = take(4 * N);
+    L.kbuf0 = take(4 * N);
+    L.kbuf1 = take(4 * N);
+    L.ibuf0 = take(4 * N);
+    L.ibuf1 = take(4 * N);
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
-    L.cell_count = take(4 * K);
-    L.cells = take(8 * (K + 1));
-    L.tile_state = take(8 * tiles);
+    L.hist = take(4 * pbdr::kMaxRadixPasses * pbdr::kRadixBins);
+    L.tile_ctr = take(4 * pbdr::kMaxRadixPasses);
+    L.radix_state = take(8 * pbdr::kRadixBins * tiles);
+    L.cells = take(16 * K);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
     L.nbr_stats = take(sizeof(pbdr::NbrStats) * ((N + pbdr::kBlock - 1) / pbdr::kBlock));
@@ -259,14 +262,22 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
     pbdr::Scene d = b->dev;
     const uint32_t khi = (uint32_t)b->keys.high_water((int32_t)b->K);
     d.T = khi > 0 ? khi : 1u;
-    d.n_scan_tiles = (uint32_t)(((size_t)d.T + pbdr::kScanTile - 1) / pbdr::kScanTile);
+    // keys of the sort: the scenes' keys (< T) and T for particles not stepped
+    int bits = 1;
+    while (bits < 32 && (d.T >> bits) != 0u) ++bits;
+    d.radix_passes = (bits + pbdr::kRadixBits - 1) / pbdr::kRadixBits;
+    d.skey = d.kbuf[(d.radix_passes - 1) & 1];
+    d.sorted = d.ibuf[(d.radix_passes - 1) & 1];
     d.waves_per_block = W;
     d.n_iter_blocks = (int32_t)nblk;
     d.n_extent = b->parts.high_water(b->P);
+    d.n_sort = d.n_extent;
+    d.n_radix_tiles = (uint32_t)(((size_t)d.n_sort + pbdr::kRadixTile - 1) / pbdr::kRadixTile);
     d.n_active = 0;
     for (int32_t s = 0; s < b->S; ++s)
         if (b->slots[(size_t)s].used && active[(size_t)s]) d.n_active += b->slots[(size_t)s].n;
-    d.dense_iterate = 0;      // one kernel variant for every mix: a scene's result depends on the scene only
+    d.dense_iterate = 0;      // a scene's result depends on the scene only, not on the mix
+    d.wide_bodies = max_need > pbdr::kWideBodyWaves ? 1 : 0;
     const long long total = (long long)frames * b->res.p.substeps;
     if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
     hipError_t e = pbdr::enqueue_substeps(d, nullptr, b->consts, b->res.p.iterations, (int)total, b->stream);
@@ -333,7 +344,9 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.n = max_particles;
     d.nb = b->BC;
     d.T = (uint32_t)K;
-    d.n_scan_tiles = (uint32_t)((K + pbdr::kScanTile - 1) / pbdr::kScanTile);
+    d.n_sort = max_particles;
+    d.radix_passes = 1;
+    d.n_radix_tiles = (uint32_t)(((size_t)max_particles + pbdr::kRadixTile - 1) / pbdr::kRadixTile);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
     d.x0 = (float*)(w + L.x0);
@@ -353,14 +366,18 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.xt = (float*)(w + L.xt);
     d.sxt4 = (float4*)(w + L.sxt4);
     d.key = (uint32_t*)(w + L.key);
-    d.rank = (uint32_t*)(w + L.rank);
-    d.sorted_raw = (uint32_t*)(w + L.sorted_raw);
-    d.sorted = (uint32_t*)(w + L.sorted);
+    d.kbuf[0] = (uint32_t*)(w + L.kbuf0);
+    d.kbuf[1] = (uint32_t*)(w + L.kbuf1);
+    d.ibuf[0] = (uint32_t*)(w + L.ibuf0);
+    d.ibuf[1] = (uint32_t*)(w + L.ibuf1);
+    d.skey = d.kbuf[0];
+    d.sorted = d.ibuf[0];
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
-    d.cell_count = (uint32_t*)(w + L.cell_count);
-    d.cells = (uint2*)(w + L.cells);
-    d.tile_state = (unsigned long long*)(w + L.tile_state);
+    d.hist = (uint32_t*)(w + L.hist);
+    d.tile_ctr = (uint32_t*)(w + L.tile_ctr);
+    d.radix_state = (unsigned long long*)(w + L.radix_state);
+    d.cells = (uint4*)(w + L.cells);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
     d.nbr_stats = (pbdr::NbrStats*)(w + L.nbr_stats);
@@ -377,7 +394,9 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     // no particle belongs to a scene yet; tables empty, counters clear
     if (e == hipSuccess) e = hipMemsetAsync(w + L.pscene, 0xff, 4 * (size_t)max_particles, b->stream);
     if (e == hipSuccess) e = pbdr::enqueue_clear_counters(d, b->stream);
-    if (e == hipSuccess) e = pbdr::enqueue_init_tables(d, b->stream);
+    if (e == hipSuccess) e = pbdr::enqueue_init_tables(d, K, b->stream);
+    // the sort's buffers hold valid ids and keys from the start
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.kbuf0, 0, L.nbr_n - L.kbuf0, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         release_batch(b);

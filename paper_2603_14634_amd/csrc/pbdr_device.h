@@ -10,11 +10,20 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kMaxWaves = 16;    // iteration kernel: waves per workgroup (bodies <= 1024 particles)
 constexpr int kMaxPlanes = 8;
 constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
-constexpr int kScanItems = 16;   // cell-table scan: counts per thread
-constexpr int kScanTile = kBlock * kScanItems;
+// Shape matching's sums over a body of many particles lose precision in FP32
+// (ten or more rounding levels over about 1000 terms of one sign): a body of
+// more than kWideBodyWaves waves (64 particles each) accumulates them in FP64.
+constexpr int kWideBodyWaves = 4;
+constexpr int kRadixBits = 8;                   // key sort: digit width
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kRadixItems = 16;                  // keys per thread of a sort pass
+constexpr int kRadixTile = kBlock * kRadixItems; // keys per workgroup of a sort pass
+constexpr int kMaxRadixPasses = 4;               // keys of up to 32 bits
+constexpr int kHistChunk = 16384;                // keys per workgroup of the digit histogram
+constexpr int kHistMaxBlocks = 128;
 
-// kErrInternal: the cell-table scan's look-back (or a pool launch shape) gave
-// up; kErrWait: a one-launch iteration's wait for a contact partner gave up.
+// kErrInternal: the key sort's look-back (or a pool launch shape) gave up;
+// kErrWait: a one-launch iteration's wait for a contact partner gave up.
 enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u, kErrWait = 8u };
 // Any of these discards the frame in which it is raised: the committed state
 // keeps the last frame completed without one.
@@ -56,6 +65,10 @@ struct StepConsts {
     int32_t n_planes;
     float plane_n[kMaxPlanes][3];
     float plane_d[kMaxPlanes];
+    // contact geometry in FP64 (penetration depths are differences of
+    // centimetre-sized lengths, formed before any rounding to FP32)
+    double radius_d, two_r_d;
+    double plane_d_d[kMaxPlanes];
 };
 
 // Several independent scenes stepped as one (multi-scene mode): per scene,
@@ -73,8 +86,11 @@ struct MultiScene {
 // Device pointers into a scene's workspace.
 struct Scene {
     int32_t n, nb;
-    uint32_t T;               // 2^k cells
-    uint32_t n_scan_tiles;    // ceil(T / kScanTile)
+    uint32_t T;               // keys in use: 2^k (one scene), or the key arena's high water
+                              //     (multi-scene mode; T is also the key of particles not stepped)
+    int32_t n_sort;           // particles taking part in the key sort (0 .. n_sort - 1)
+    int32_t radix_passes;     // ceil(key bits / 8)
+    uint32_t n_radix_tiles;   // ceil(n_sort / kRadixTile)
     float* x;                 // [3][N] committed positions: the state after the last clean frame
     float* v;                 // [3][N] committed velocities
     float* x0;                // [3][N] X_init of the current substep (the working state)
@@ -90,29 +106,33 @@ struct Scene {
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
     int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (80-VGPR kernel)
+    int32_t wide_bodies;      // 1: some body of the iteration launch spans more than 4 waves
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
     float* xt;                // [3][N] FP32 predicted positions
-    float4* sxt4;             // [N] predicted position and body id (bits) in raw sorted order
-    uint32_t* key;            // [N]
-    uint32_t* rank;           // [N] slot within the key from the counting pass
-    uint32_t* sorted_raw;     // [N] ids grouped by key, arbitrary order within a key
-    uint32_t* sorted;         // [N] ids sorted by (key, id), written on demand
+    float4* sxt4;             // [N] predicted position and body id (bits) in (key, id) order
+    uint32_t* key;            // [N] cell key of each particle (by id)
+    uint32_t* kbuf[2];        // [N] keys between sort passes (ping-pong)
+    uint32_t* ibuf[2];        // [N] ids between sort passes (ping-pong)
+    const uint32_t* skey;     // keys in (key, id) order: kbuf[(radix_passes - 1) & 1]
+    const uint32_t* sorted;   // ids in (key, id) order: ibuf[(radix_passes - 1) & 1]
     uint32_t* nbr_n;          // [N] neighbour-list length
     uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
-    uint32_t* cell_count;     // [T] per-key counts (zero outside a substep)
-    uint2* cells;             // [T + 1] per key: first sorted slot, body signature (the one
-                              //     body of all its particles, -1 empty, -2 mixed); the count of
-                              //     key k is cells[k + 1].x - cells[k].x, cells[T].x = N
-    unsigned long long* tile_state;  // [n_scan_tiles] scan look-back: (status << 32) | value
+    uint32_t* hist;           // [kMaxRadixPasses][kRadixBins] digit counts of the substep's keys
+    uint32_t* tile_ctr;       // [kMaxRadixPasses] sort passes: next tile to take
+    unsigned long long* radix_state;   // [n_radix_tiles][kRadixBins] look-back: tag | status | count
+    uint4* cells;             // [T] per key, written for occupied keys only: first sorted slot,
+                              //     end slot, body signature (the one body of all its particles,
+                              //     or -2 mixed), and the substep (epoch) that wrote it; an entry
+                              //     of an earlier substep marks an empty key
 
     float* body_rot;          // [B][9] last rotation of shape matching
     Counters* counters;
     NbrStats* nbr_stats;      // [ceil(N / kBlock)]
     const float* accel;       // [3][N] external acceleration or nullptr
     // multi-scene mode (nullptr otherwise): scene slot of each particle (-1:
-    // none) and the scenes.  Particles of scenes not stepped take no key, so
-    // the key grouping holds the stepped particles only (cells[T].x of them).
+    // none) and the scenes.  Particles of scenes not stepped take key T, so the
+    // sorted order holds the stepped particles first (n_active of them).
     const int32_t* pscene;    // [N]
     const MultiScene* mscene; // [S]
     int32_t n_extent;         // launch extent: particles 0 .. n_extent - 1 may be stepped
@@ -147,13 +167,16 @@ hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts&
 hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1);
 
-// Writes the canonical (key, id) order of the last substep into `sorted`.
-hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream);
+// Zeroes `bytes` (a multiple of 4) at `p` with a fill kernel (no memset node
+// when the caller captures the stream).
+hipError_t enqueue_zero(void* p, size_t bytes, hipStream_t stream);
 
 // Clears the latched counters.
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream);
 
-// Zeroes the per-key counts and writes the end sentinel cells[T] (once, at creation).
-hipError_t enqueue_init_tables(const Scene& s, hipStream_t stream);
+// Clears the key table, the digit counts, the sort passes' tile counters and
+// look-back words, and the substep epoch (once, at creation; `cells` holds
+// `table` entries).
+hipError_t enqueue_init_tables(const Scene& s, size_t table, hipStream_t stream);
 
 }  // namespace pbdr

@@ -90,6 +90,17 @@ pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap);
 pbdr_status resolve(const pbdr_params* in, int32_t n, Resolved* out);
 // FP32 constants of one substep from resolved parameters.
 void fill_step_consts(const Resolved& r, StepConsts* out);
+// pbdr_scene_create into `dev_workspace`, filling `record` (one of the reused
+// host records, or NULL for a new one).  A scene in a reused record steps by
+// direct launches only (no graph capture, which allocates), and
+// pbdr_scene_destroy releases the record without freeing it.
+pbdr_status create_scene_in(const pbdr_params* params, const pbdr_scene_desc* desc, void* dev_workspace,
+                            size_t ws_bytes, void* hip_stream, pbdr_scene* record, pbdr_scene** out);
+// Reused host record `index` (0 .. 63), or NULL.
+pbdr_scene* fixed_scene_record(int index);
+// Waits for the work of the scene in a reused record, if it holds one, and
+// releases the record.
+void release_fixed_record(pbdr_scene* record);
 
 }  // namespace host
 }  // namespace pbdr

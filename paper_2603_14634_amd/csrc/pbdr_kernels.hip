@@ -4,16 +4,17 @@
 // Particle-Based Simulation" (arXiv 2603.14634) as a chain of kernels on one
 // stream:
 //
-//   predict_keys   integration step (Alg. 1, first loop), hash-grid key and
-//                  per-key slot of every particle (atomic counting pass); from
-//                  the second substep of a call on, it first folds the previous
-//                  substep's result into the state (x += dX, v = V)
-//   scan           exclusive prefix sum of the per-key counts in one launch
-//                  (decoupled look-back) -> per-key first slot and count;
-//                  re-zeroes the counts
-//   scatter        particles grouped by key, with sorted copies of the FP32
-//                  predicted positions and body ids, and each key's body
-//                  signature (its single body, or "mixed")
+//   predict_keys   integration step (Alg. 1, first loop) and hash-grid key of
+//                  every particle; from the second substep of a call on, it
+//                  first folds the previous substep's result into the state
+//                  (x += dX, v = V)
+//   radix_hist     counts of every 8-bit digit of the keys
+//   radix_pass x P stable LSD radix sort of (key, id), one sweep per digit
+//                  (local ranking by ballots, decoupled look-back over tiles)
+//   cells          per-key table from the sorted keys, written for occupied
+//                  keys only and tagged with the substep: first and end slot,
+//                  body signature (the key's single body, or "mixed"); sorted
+//                  copies of the FP32 predicted positions and body ids
 //   neighbours     walks particles in key order: 27-cell stencil (skipping
 //                  keys that hold only the particle's own body), FP32
 //                  predicate, ascending lists
@@ -64,7 +65,7 @@ __device__ inline int xcd_block()
 }
 
 // ---------------------------------------------------------------------------
-// integration step + keys + counting pass
+// integration step + keys
 // ---------------------------------------------------------------------------
 
 // MULTI: multi-scene mode (Scene::pscene set); a separate instance, so that
@@ -74,14 +75,21 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 {
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < (int)s.n_scan_tiles) s.tile_state[i] = 0ull;   // scan look-back state of this substep
-    if (!MULTI && i == 0) s.counters->epoch += 1u;      // a new substep: fresh tags for one-launch iterations
-    if (i >= s.n) return;
+    // the key sort of this substep starts from zero digit counts and tile counters
+    if (i < kMaxRadixPasses * kRadixBins) s.hist[i] = 0u;
+    if (i < kMaxRadixPasses) s.tile_ctr[i] = 0u;
+    // a new substep: fresh tags for the sort's look-back, the key table and
+    // one-launch iterations (no other thread of this launch reads the epoch)
+    if (i == 0) s.counters->epoch += 1u;
+    if (i >= s.n_sort) return;
     const size_t n = (size_t)s.n;
     const MultiScene* ms = nullptr;
     if (MULTI) {                       // this particle's scene, if stepped
         const int32_t sc = s.pscene[i];
-        if (sc < 0 || !s.mscene[sc].active) return;
+        if (sc < 0 || !s.mscene[sc].active) {
+            s.key[i] = s.T;            // sorts after every stepped particle
+            return;
+        }
         ms = &s.mscene[sc];
     }
     const float* g = ms ? ms->g : c.g;
@@ -109,18 +117,17 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
         s.vel[0][j] = vt;     // V_0 = V~
     }
     if (!finite) atomicOr(&s.counters->err, kErrNonFinite);
-    const uint32_t key = (ms ? ms->key_base : 0u) + morton(cell_axis(xt[0], c.origin[0], c.inv_cell),
-                                                           cell_axis(xt[1], c.origin[1], c.inv_cell),
-                                                           cell_axis(xt[2], c.origin[2], c.inv_cell),
-                                                           ms ? ms->key_mask : c.key_mask);
-    s.key[i] = key;
-    s.rank[i] = atomicAdd(&s.cell_count[key], 1u);
+    s.key[i] = (ms ? ms->key_base : 0u) + morton(cell_axis(xt[0], c.origin[0], c.inv_cell),
+                                                 cell_axis(xt[1], c.origin[1], c.inv_cell),
+                                                 cell_axis(xt[2], c.origin[2], c.inv_cell),
+                                                 ms ? ms->key_mask : c.key_mask);
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the cell counts in one launch (decoupled look-back: each
-// tile publishes its total at once and its inclusive prefix as soon as it is
-// known; a wave inspects 64 predecessors per step)
+// stable LSD radix sort of (key, id), 8-bit digits, one launch per digit
+// (each pass is a single sweep: tiles rank their keys locally and find the
+// counts of the same digit in all earlier tiles by decoupled look-back; the
+// global digit offsets come from one histogram of all digits, taken first)
 // ---------------------------------------------------------------------------
 
 // Inclusive prefix sum over the lanes of a wave: shifts by 1, 2, 4, 8 within
@@ -137,163 +144,235 @@ __device__ inline uint32_t wave_inclusive_scan(uint32_t v)
     return v;
 }
 
-// Sum over the 64 lanes of a wave, returned to every lane: row sums by DPP,
-// the four row sums gathered in lane 63 by row broadcasts, then read out.
-__device__ inline uint32_t wave_total(uint32_t v)
-{
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);  // row_half_mirror
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);  // row_mirror
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-// Exclusive prefix sums of N values per thread over the workgroup, each value
-// scanned on its own (the N scans share one barrier).  tot[k] receives the
-// workgroup total of value k.
-template <int N>
-__device__ inline void block_exclusive_scans(const uint32_t* v, uint32_t (*wave_tot)[kWaves], uint32_t* excl,
-                                             uint32_t* tot)
+// Exclusive prefix sum of one value per thread over the workgroup (kBlock
+// threads); `tmp` holds kWaves words of LDS.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t incl[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) incl[k] = wave_inclusive_scan(v[k]);
-    if (lane == 63)
-#pragma unroll
-        for (int k = 0; k < N; ++k) wave_tot[k][wave] = incl[k];
+    const uint32_t incl = wave_inclusive_scan(v);
+    if (lane == 63) tmp[wave] = incl;
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        uint32_t before = 0, all = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wave) before += wave_tot[k][w];
-            all += wave_tot[k][w];
-        }
-        excl[k] = before + incl[k] - v[k];
-        tot[k] = all;
-    }
+    uint32_t before = 0;
+    for (int w = 0; w < kWaves; ++w)
+        if (w < wave) before += tmp[w];
+    __syncthreads();                  // tmp may be reused at once
+    return before + incl - v;
 }
 
-constexpr unsigned long long kTileAggregate = 1ull << 32, kTileInclusive = 2ull << 32;
 constexpr uint32_t kSpinLimit = 1u << 22;   // bounded wait: flag an error, never hang
 
-// A tile is kScanTile keys in kChunks chunks of 4 keys per thread, so every
-// count load and entry store of a chunk is one contiguous, coalesced access.
-constexpr int kChunks = kScanTile / (4 * kBlock);
-
-__global__ void __launch_bounds__(kBlock) k_scan(Scene s)
+// Digit counts of every pass over all keys: each workgroup counts a chunk of
+// kHistChunk keys in LDS (16 consecutive keys per thread, equal digits of a
+// run counted once) and adds its non-zero counts to the global table.
+__global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
 {
-    __shared__ uint32_t wave_tot[kChunks][kWaves];
-    __shared__ uint32_t s_prefix;
-    // workgroups are dispatched in index order, so a tile only waits on tiles
-    // that already run; the wait is bounded all the same
-    const uint32_t tile = blockIdx.x;
-    const size_t tbase = (size_t)tile * kScanTile;
-    uint32_t vals[kChunks][4], csum[kChunks], excl[kChunks], chunk_tot[kChunks];
-    // all chunks are loaded before any is scanned, so their loads overlap
+    __shared__ uint32_t h[kMaxRadixPasses * kRadixBins];
+    const int P = s.radix_passes;
+    for (int t = threadIdx.x; t < P * kRadixBins; t += 1024) h[t] = 0u;
+    __syncthreads();
+    const size_t n = (size_t)s.n_sort;
+    const size_t i0 = (size_t)blockIdx.x * kHistChunk + 16 * (size_t)threadIdx.x;
+    uint32_t k[16];
+    if (i0 + 16 <= n) {
+        const uint4* src = reinterpret_cast<const uint4*>(s.key + i0);
 #pragma unroll
-    for (int ch = 0; ch < kChunks; ++ch) {
-        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
-        if (base + 3 < s.T) {
-            const uint4 v = *(const uint4*)&s.cell_count[base];
-            vals[ch][0] = v.x; vals[ch][1] = v.y; vals[ch][2] = v.z; vals[ch][3] = v.w;
-        } else {
-            for (int k = 0; k < 4; ++k) vals[ch][k] = base + k < s.T ? s.cell_count[base + k] : 0u;
+        for (int u = 0; u < 4; ++u) {
+            const uint4 q = src[u];
+            k[4 * u] = q.x; k[4 * u + 1] = q.y; k[4 * u + 2] = q.z; k[4 * u + 3] = q.w;
         }
-    }
+    } else {
 #pragma unroll
-    for (int ch = 0; ch < kChunks; ++ch) {       // counts ready for the next substep
-        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
-        if (base + 3 < s.T) {
-            *(uint4*)&s.cell_count[base] = make_uint4(0u, 0u, 0u, 0u);
-        } else {
-            for (int k = 0; k < 4; ++k)
-                if (base + k < s.T) s.cell_count[base + k] = 0u;
-        }
-        csum[ch] = vals[ch][0] + vals[ch][1] + vals[ch][2] + vals[ch][3];
+        for (int u = 0; u < 16; ++u) k[u] = i0 + u < n ? s.key[i0 + u] : 0u;
     }
-    block_exclusive_scans<kChunks>(csum, wave_tot, excl, chunk_tot);
-    uint32_t total = 0;
-    for (int ch = 0; ch < kChunks; ++ch) total += chunk_tot[ch];
-    if (threadIdx.x < 64) {                       // wave 0: publish and look back
-        const int lane = threadIdx.x;
-        uint32_t prefix = 0;
-        if (tile == 0) {
-            if (lane == 0)
-                __hip_atomic_store(&s.tile_state[0], kTileInclusive | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(&s.tile_state[tile], kTileAggregate | total, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            int top = (int)tile - 1;               // newest predecessor not yet summed
-            uint32_t spins = 0;
-            while (true) {
-                const int t = top - lane;
-                const unsigned long long st =
-                    t >= 0 ? __hip_atomic_load(&s.tile_state[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                           : kTileInclusive;
-                const uint32_t status = (uint32_t)(st >> 32);
-                const unsigned long long incl = __ballot(status == 2u);
-                const unsigned long long empty = __ballot(status == 0u);
-                const int stop = incl ? __ffsll((long long)incl) - 1 : 63;   // lanes 0..stop matter
-                const unsigned long long mask = stop == 63 ? ~0ull : ((1ull << (stop + 1)) - 1ull);
-                if (empty & mask) {               // a predecessor has not published yet
-                    if (++spins > kSpinLimit) {
-                        if (lane == 0) atomicOr(&s.counters->err, kErrInternal);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                uint32_t v = lane <= stop ? (uint32_t)st : 0u;
-                prefix += wave_total(v);
-                if (incl) break;
-                top -= 64;
+    const int cnt = i0 >= n ? 0 : (int)min((size_t)16, n - i0);
+    for (int p = 0; p < P; ++p) {
+        const uint32_t sh = kRadixBits * p;
+        uint32_t run_d = 0, run_n = 0;
+        for (int u = 0; u < cnt; ++u) {
+            const uint32_t d = (k[u] >> sh) & (kRadixBins - 1);
+            if (run_n && d != run_d) {
+                atomicAdd(&h[p * kRadixBins + run_d], run_n);
+                run_n = 0;
             }
-            if (lane == 0)
-                __hip_atomic_store(&s.tile_state[tile], kTileInclusive | (prefix + total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            run_d = d;
+            ++run_n;
         }
-        if (lane == 0) s_prefix = prefix;
+        if (run_n) atomicAdd(&h[p * kRadixBins + run_d], run_n);
     }
     __syncthreads();
-    uint32_t run_chunk = s_prefix;
-    for (int ch = 0; ch < kChunks; ++ch) {
-        const size_t base = tbase + (size_t)ch * 4 * kBlock + 4 * (size_t)threadIdx.x;
-        uint32_t run = run_chunk + excl[ch];
-        for (int k = 0; k < 4; ++k) {
-            if (base + k < s.T) s.cells[base + k] = make_uint2(run, 0xffffffffu);   // signature: empty
-            run += vals[ch][k];
-        }
-        run_chunk += chunk_tot[ch];
-    }
-    // end sentinel: the number of particles grouped (all of them, or in
-    // multi-scene mode those stepped)
-    if (tile == gridDim.x - 1 && threadIdx.x == 0) s.cells[s.T] = make_uint2(s_prefix + total, 0xffffffffu);
+    for (int t = threadIdx.x; t < P * kRadixBins; t += 1024)
+        if (h[t]) atomicAdd(&s.hist[t], h[t]);
 }
 
-template <bool MULTI>
-__global__ void __launch_bounds__(kBlock) k_scatter(Scene s)
+// look-back word: tag (30 bits) | status (2 bits) | count (32 bits); the tag
+// names the substep and the pass, so words of earlier passes read as "not yet
+// published"
+constexpr uint32_t kStAggregate = 1u, kStInclusive = 2u;
+__device__ inline unsigned long long radix_word(uint32_t tag, uint32_t status, uint32_t v)
 {
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= s.n) return;
-    if (MULTI) {                       // stepped particles only
-        const int32_t sc = s.pscene[i];
-        if (sc < 0 || !s.mscene[sc].active) return;
+    return ((unsigned long long)tag << 34) | ((unsigned long long)status << 32) | v;
+}
+
+// One pass over digit p (bits 8p .. 8p + 7): keys kin (ids iin, or the key's
+// index when iin is null) -> kout, iout, stable.  A workgroup takes the next
+// tile of kRadixTile keys (tiles are taken in order, so every tile it waits
+// on belongs to a workgroup that is already running).  Item t of lane l of
+// wave w is key w * 64 * kRadixItems + 64 t + l of the tile: each wave ranks
+// its items in that order by matching equal digits across lanes with ballots,
+// so ranks follow key order within the tile.
+// The last pass also writes each particle's predicted position and body to
+// its sorted slot (sxt4).
+__global__ void __launch_bounds__(kBlock) k_radix_pass(Scene s, int p, const uint32_t* kin, const uint32_t* iin,
+                                                       uint32_t* kout, uint32_t* iout)
+{
+    __shared__ uint32_t s_key[kRadixTile], s_id[kRadixTile];
+    __shared__ uint32_t wcnt[kWaves][kRadixBins];   // per-wave digit counters, then wave offsets
+    __shared__ uint32_t lstart[kRadixBins];         // first LDS slot of each digit in the tile
+    __shared__ int32_t gshift[kRadixBins];          // output position - LDS slot, per digit
+    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_tile = atomicAdd(&s.tile_ctr[p], 1u);
+    for (int t = tid; t < kWaves * kRadixBins; t += kBlock) (&wcnt[0][0])[t] = 0u;
+    __syncthreads();
+    const uint32_t tile = s_tile;
+    const uint32_t n = (uint32_t)s.n_sort;
+    const uint32_t sh = kRadixBits * p;
+    const uint32_t tag = ((s.counters->epoch << 2) | (uint32_t)p) & 0x3fffffffu;
+    const uint32_t first = tile * kRadixTile + (uint32_t)wave * 64u * kRadixItems + (uint32_t)lane;
+
+    uint32_t k[kRadixItems], id[kRadixItems], r[kRadixItems];
+#pragma unroll
+    for (int t = 0; t < kRadixItems; ++t) {
+        const uint32_t e = first + 64u * t;
+        k[t] = e < n ? kin[e] : 0u;
+        id[t] = e < n ? (iin ? iin[e] : e) : 0u;
     }
-    const size_t n = (size_t)s.n;
-    const uint32_t key = s.key[i];
-    const uint32_t slot = s.cells[key].x + s.rank[i];
-    const int32_t b = s.body[i];
-    s.sorted_raw[slot] = (uint32_t)i;
-    s.sxt4[slot] = make_float4(s.xt[i], s.xt[n + i], s.xt[2 * n + i], __int_as_float(b));
-    // body signature of the key: the one body of all its particles, or -2
-    int* sig = (int*)&s.cells[key].y;
-    const int32_t old = atomicCAS(sig, -1, b);
-    if (old != -1 && old != b && old != -2) atomicExch(sig, -2);
+    // rank within the wave, item by item (each lane's items in key order)
+#pragma unroll
+    for (int t = 0; t < kRadixItems; ++t) {
+        const bool valid = first + 64u * t < n;
+        const uint32_t d = (k[t] >> sh) & (kRadixBins - 1);
+        unsigned long long peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < kRadixBits; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
+        const uint32_t prior = valid ? wcnt[wave][d] : 0u;
+        r[t] = prior + below;
+        if (valid && lane == __ffsll((long long)peers) - 1) wcnt[wave][d] = prior + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // thread d: wave offsets and the tile's count of digit d
+    const uint32_t d = (uint32_t)tid;
+    uint32_t total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        const uint32_t c = wcnt[w][d];
+        wcnt[w][d] = total;
+        total += c;
+    }
+    unsigned long long* st = s.radix_state + (size_t)tile * kRadixBins;
+    if (tile > 0)
+        __hip_atomic_store(&st[d], radix_word(tag, kStAggregate, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_store(&st[d], radix_word(tag, kStInclusive, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t local = block_exclusive_scan(total, tmp);          // first slot of digit d in the tile
+    const uint32_t global = block_exclusive_scan(s.hist[p * kRadixBins + d], tmp);   // first position of digit d
+    // count of digit d in all earlier tiles (decoupled look-back): the words
+    // of kLookBack predecessors are loaded together; aggregates are summed
+    // until an inclusive count, and a word not yet published is polled again
+    uint32_t before = 0;
+    if (tile > 0) {
+        constexpr int kLookBack = 8;
+        int t = (int)tile - 1;             // newest predecessor not yet summed
+        uint32_t spins = 0;
+        bool done = false;
+        while (!done) {
+            unsigned long long w[kLookBack];
+#pragma unroll
+            for (int j = 0; j < kLookBack; ++j)
+                w[j] = t - j >= 0 ? __hip_atomic_load(&s.radix_state[(size_t)(t - j) * kRadixBins + d],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0ull;
+            bool stalled = false;
+#pragma unroll
+            for (int j = 0; j < kLookBack; ++j) {
+                if (done || stalled || t < 0) continue;
+                const uint32_t status = (uint32_t)(w[j] >> 32) & 3u;
+                if ((uint32_t)(w[j] >> 34) != tag || status == 0u) {   // not published yet
+                    stalled = true;
+                    continue;
+                }
+                before += (uint32_t)w[j];
+                done = status == kStInclusive;
+                --t;
+            }
+            if (done || t < 0) break;         // (tile 0 is always inclusive: t < 0 only after an error)
+            if (stalled) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(&s.counters->err, kErrInternal);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(&st[d], radix_word(tag, kStInclusive, before + total), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    lstart[d] = local;
+    gshift[d] = (int32_t)(global + before) - (int32_t)local;
+    __syncthreads();
+    // keys to LDS in (digit, key order), then out: the slots of one digit go
+    // to consecutive positions
+#pragma unroll
+    for (int t = 0; t < kRadixItems; ++t) {
+        if (first + 64u * t >= n) continue;
+        const uint32_t dd = (k[t] >> sh) & (kRadixBins - 1);
+        const uint32_t slot = lstart[dd] + wcnt[wave][dd] + r[t];
+        s_key[slot] = k[t];
+        s_id[slot] = id[t];
+    }
+    __syncthreads();
+    const uint32_t in_tile = min((uint32_t)kRadixTile, n - tile * kRadixTile);
+    const bool last = p == s.radix_passes - 1;
+    const size_t ns = (size_t)s.n;
+    for (uint32_t j = (uint32_t)tid; j < in_tile; j += kBlock) {
+        const uint32_t kk = s_key[j], ii = s_id[j];
+        const uint32_t pos = (uint32_t)((int32_t)j + gshift[(kk >> sh) & (kRadixBins - 1)]);
+        if (pos >= n) continue;        // (a look-back that gave up leaves the positions unusable)
+        kout[pos] = kk;
+        iout[pos] = ii;
+        if (last && kk < s.T)          // stepped particles (in multi-scene mode the others take key T)
+            s.sxt4[pos] = make_float4(s.xt[ii], s.xt[ns + ii], s.xt[2 * ns + ii], __int_as_float(s.body[ii]));
+    }
+}
+
+// Per-key table from the sorted keys: the first particle of each key writes
+// the key's entry (first slot, end slot, body signature, substep).
+template <bool MULTI>
+__global__ void __launch_bounds__(kBlock) k_cells(Scene s)
+{
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    const int ng = MULTI ? s.n_active : s.n;     // sorted particles that are stepped
+    if (j >= ng) return;
+    const uint32_t key = s.skey[j];
+    // (only after a sort that gave up can a key be out of range; the frame is
+    // then discarded)
+    if (key >= s.T || (j > 0 && s.skey[j - 1] == key)) return;
+    const int32_t b = __float_as_int(s.sxt4[j].w);
+    int e = j + 1;
+    int32_t sig = b;                 // the one body of all the key's particles, or -2
+    while (e < ng && s.skey[e] == key) {
+        if (__float_as_int(s.sxt4[e].w) != b) sig = -2;
+        ++e;
+    }
+    s.cells[key] = make_uint4((uint32_t)j, (uint32_t)e, (uint32_t)sig, s.counters->epoch);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,18 +388,22 @@ k_neighbours(Scene s, StepConsts c)
     extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
     const int blk = xcd_block();
     const int j = blk * kBlock + threadIdx.x;  // position in key order
-    // multi-scene mode: the key order holds the stepped particles only
-    bool live = j < (MULTI ? (int)s.cells[s.T].x : s.n);
+    // multi-scene mode: the stepped particles come first in key order
+    bool live = j < (MULTI ? s.n_active : s.n);
     const size_t n = (size_t)s.n;
     const int cap = c.nbr_cap;
     const int tid = threadIdx.x;
+    const uint32_t epoch = s.counters->epoch;
     uint32_t count = 0;
-    uint32_t i = live ? s.sorted_raw[j] : 0u;
+    uint32_t i = live ? s.sorted[j] : 0u;
     uint32_t key_base = 0u, key_mask = c.key_mask;
     if (MULTI && live) {                // multi-scene mode: the particle's own scene table
         const int32_t sc = s.pscene[i];
-        key_base = s.mscene[sc].key_base;
-        key_mask = s.mscene[sc].key_mask;
+        live = sc >= 0;                 // (false only after a sort that gave up)
+        if (live) {
+            key_base = s.mscene[sc].key_base;
+            key_mask = s.mscene[sc].key_mask;
+        }
     }
     if (live) {
         const float4 me = s.sxt4[j];
@@ -334,16 +417,16 @@ k_neighbours(Scene s, StepConsts c)
         for (int t = 0; t < 27; ++t) {
             const uint32_t k = key_base + morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
                                                  cz + (uint32_t)(t / 9 - 1), key_mask);
-            const uint2 e = s.cells[k];
-            const uint32_t end = s.cells[k + 1].x;
+            const uint4 e = s.cells[k];
             lo[t] = e.x;
-            // a key holding only this particle's body has no candidates
-            hi[t] = (int32_t)e.y == pb ? e.x : end;
+            // an entry of an earlier substep is an empty key, and a key
+            // holding only this particle's body has no candidates
+            hi[t] = (e.w != epoch || (int32_t)e.z == pb) ? e.x : e.y;
         }
         auto consider = [&](uint32_t q, const float4 o) {
             if (__float_as_int(o.w) == pb) return;            // same body (also excludes i)
             if (!within(px, py, pz, o.x, o.y, o.z, c.search_r2)) return;
-            const uint32_t id = s.sorted_raw[q];
+            const uint32_t id = s.sorted[q];
             // insert keeping the `cap` smallest ids in ascending order
             const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
             ++count;
@@ -414,6 +497,15 @@ k_neighbours(Scene s, StepConsts c)
 // one Jacobi iteration (Alg. 1 loop body)
 // ---------------------------------------------------------------------------
 
+// Signed distance n . X_i - d of a particle from plane pl, in FP64 (the
+// penetration r - e is formed from it before any rounding).
+__device__ __forceinline__ double plane_gap(const StepConsts& c, int pl, const float* x0, const float* del)
+{
+    double e = -c.plane_d_d[pl];
+    for (int j = 0; j < 3; ++j) e += (double)c.plane_n[pl][j] * ((double)x0[j] + (double)del[j]);
+    return e;
+}
+
 // Contact with a particle of another body (constraint (2)) from X_i: the
 // mass-weighted split of the penetration, Coulomb friction from the relative
 // displacement since X_init, and the pair weight of the averaging mode.  xq,
@@ -425,17 +517,21 @@ __device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t av
                                                 const float* dq, float mq, uint32_t nq, float* Cd)
 {
 #pragma clang fp contract(on)
-    float d[3], u[3];
+    // separation, distance, penetration and normal in FP64: the separation
+    // of two FP32 positions and the penetration 2r - l are exact or nearly so
+    // there, and only the correction is rounded
+    double d[3];
+    float u[3];
     for (int j = 0; j < 3; ++j) {
-        d[j] = (x0[j] - xq[j]) + (del[j] - dq[j]);
+        d[j] = ((double)x0[j] - (double)xq[j]) + ((double)del[j] - (double)dq[j]);
         u[j] = del[j] - dq[j];
     }
-    const float l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const float l = __builtin_amdgcn_sqrtf(l2);
-    if (!(l > 0.0f) || !(l < c.two_r)) return;
-    const float il = frcp(l);
-    const float nx = d[0] * il, ny = d[1] * il, nz = d[2] * il;
-    const float pen = c.two_r - l;
+    const double l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) return;
+    const double l = sqrt(l2);
+    const double il = 1.0 / l;
+    const float nx = (float)(d[0] * il), ny = (float)(d[1] * il), nz = (float)(d[2] * il);
+    const float pen = (float)(c.two_r_d - l);
     const float alpha = mq * frcp(m + mq);          // w_p / (w_p + w_q)
     const float un = u[0] * nx + u[1] * ny + u[2] * nz;
     const float ux = u[0] - un * nx, uy = u[1] - un * ny, uz = u[2] - un * nz;
@@ -480,6 +576,89 @@ __device__ inline void sum_wave_partials(const float4* red, int w0, int nw, floa
     }
 }
 
+// Shape matching's goal offset D = R q - (y - c) of one particle, y its
+// position relative to the body's anchor (x0 - anchor + del).  The terms are
+// body-sized (up to decimetres) while D is of the order of the contact
+// corrections (micrometres), so it is formed in FP64: the products of FP32
+// values and the anchor difference are exact there, and only the result is
+// rounded.  In FP32 every particle's goal would carry a rounding of ~ulp(0.1 m)
+// = 7e-9 m that no rigid motion absorbs, and resting contacts amplify such
+// particle-level differences over the iterations.
+__device__ __forceinline__ void goal_offset(const float* R, const float* q, const float* x0, const float* anchor,
+                                            const float* del, const float* c, float* D)
+{
+    for (int a = 0; a < 3; ++a) {
+        const double rq = (double)R[3 * a] * (double)q[0] + (double)R[3 * a + 1] * (double)q[1] +
+                          (double)R[3 * a + 2] * (double)q[2];
+        const double ya = ((double)x0[a] - (double)anchor[a]) + (double)del[a];
+        D[a] = (float)(rq - (ya - (double)c[a]));
+    }
+}
+
+// This wave's partial sums of shape matching, sum m y and sum m y q^T (12
+// values), to LDS: in FP32 (red32), or in FP64 (red64) when `wide`.
+template <bool WIDE_OK>
+__device__ __forceinline__ void sm_wave_partials(bool wide, float m, const float* y, const float* q, int wave,
+                                                 int lane, float4* red32, double* red64)
+{
+    if (WIDE_OK && wide) {
+        // three groups of four sums (fewer FP64 values live at once); after
+        // the reduction row j of group g holds sum 4 g + j
+        const double md = m;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            double S[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = 4 * g + u;          // 0-2: m y, 3-11: m y_a q_b
+                S[u] = k < 3 ? md * (double)y[k] : md * (double)y[(k - 3) / 3] * (double)q[(k - 3) % 3];
+            }
+            wave_sums_by_row64<4>(S);
+            if ((lane & 15) == 15) red64[wave * 12 + 4 * g + (lane >> 4)] = S[0];
+        }
+    } else {
+        float S[12];
+        for (int j = 0; j < 3; ++j) S[j] = m * y[j];
+        for (int a = 0; a < 3; ++a)
+            for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
+        wave_sums_by_row<12>(S);
+        if ((lane & 15) == 15) {
+            float* dst = (float*)red32 + wave * 12 + (lane >> 4) * 3;
+            for (int j = 0; j < 3; ++j) dst[j] = S[j];
+        }
+    }
+}
+
+// Centre (relative to the body's anchor) and covariance A = sum m (y - c) q^T
+// of a body from its waves' partials, on the body's lane:
+// A = sum m y q^T - c (sum m q)^T.
+template <bool WIDE_OK, int UNROLL>
+__device__ __forceinline__ void sm_body_sums(int w0, int nw, float M, const float* mq3, const float4* red32,
+                                             const double* red64, float* cc, float* A)
+{
+    if (WIDE_OK && nw > kWideBodyWaves) {
+        double T[12];
+        for (int j = 0; j < 12; ++j) T[j] = 0.0;
+        for (int w = 0; w < nw; ++w)
+            for (int j = 0; j < 12; ++j) T[j] += red64[(w0 + w) * 12 + j];
+        const double im = 1.0 / (double)M;
+        double c[3];
+        for (int j = 0; j < 3; ++j) {
+            c[j] = T[j] * im;
+            cc[j] = (float)c[j];
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = (float)(T[3 + 3 * a + k2] - c[a] * (double)mq3[k2]);
+    } else {
+        float T[12];
+        sum_wave_partials<3, UNROLL>(red32, w0, nw, T);
+        const float im = frcp(M);
+        for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
+        for (int a = 0; a < 3; ++a)
+            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+    }
+}
+
 // Bodies are packed into workgroups of W waves; each body owns ceil(n/64)
 // consecutive waves, one particle per lane.  Per-body sums are wave sums (lane swaps, DPP)
 // combined over the body's waves; the per-body 3x3 algebra runs on lane j of
@@ -487,11 +666,12 @@ __device__ inline void sum_wave_partials(const float4* red, int w0, int nw, floa
 // the substep: from the second iteration on, the rotation is refined from the
 // previous iteration's.  SM_UNROLL / MOM_UNROLL: waves whose partial sums the
 // per-body lane reads from LDS at once.
-template <bool MULTI, int SM_UNROLL, int MOM_UNROLL>
+template <bool MULTI, bool WIDE_OK, int SM_UNROLL, int MOM_UNROLL>
 __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it)
 {
     constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
     __shared__ float4 red_sm[kMaxWaves * NSM / 4];
+    __shared__ double red_sm64[WIDE_OK ? kMaxWaves * NSM : 1];
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
     __shared__ float body_sm[kMaxWaves * 12];    // per body of the workgroup: R (9), centre (3)
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
@@ -512,12 +692,14 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     const int lb = b >= blk_b0 ? b - blk_b0 : 0;  // body slot within the workgroup
     const int i = s0 + (wave - lw0) * 64 + lane;  // this lane's particle
     const bool act = b >= 0 && i < e0;
+    const bool wide = e0 - s0 > 64 * kWideBodyWaves;
     const size_t n = (size_t)s.n;
     const float* dl = s.dl[src];
     const float* vl = s.vel[src];
     float* dn = s.dl[src ^ 1];
     float* vn = s.vel[src ^ 1];
     const float ax = s.x0[s0], ay = s.x0[n + s0], az = s.x0[2 * n + s0];   // body anchor
+    const float anc[3] = {ax, ay, az};
     const uint32_t avg = (c.flags >> kAvgShift) & 3u;
 
     // per-body lane of wave 0: body slot `lane` of this workgroup
@@ -553,9 +735,9 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         for (int pl = 0; pl < c.n_planes; ++pl) {
             const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
             const float un = nx * del[0] + ny * del[1] + nz * del[2];
-            const float e = ((nx * x0[0] + ny * x0[1] + nz * x0[2]) - c.plane_d[pl]) + un;
-            if (!(e < c.radius)) continue;
-            const float pen = c.radius - e;
+            const double e = plane_gap(c, pl, x0, del);
+            if (!(e < c.radius_d)) continue;
+            const float pen = (float)(c.radius_d - e);
             const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
             const float ut2 = ux * ux + uy * uy + uz * uz;
             const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
@@ -582,26 +764,11 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     y[0] = (x0[0] - ax) + del[0];
     y[1] = (x0[1] - ay) + del[1];
     y[2] = (x0[2] - az) + del[2];
-    {
-        float S[NSM];
-        for (int j = 0; j < 3; ++j) S[j] = m * y[j];
-        for (int a = 0; a < 3; ++a)
-            for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
-        wave_sums_by_row<NSM>(S);
-        if ((lane & 15) == 15) {      // row j holds sums j NSM/4 .. j NSM/4 + NSM/4 - 1
-            float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
-            for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
-        }
-    }
+    sm_wave_partials<WIDE_OK>(wide, m, y, q, wave, lane, red_sm, red_sm64);
     __syncthreads();
     if (body_lane) {            // one lane per body: centre, covariance, rotation
-        float T[NSM];
-        sum_wave_partials<NSM / 4, SM_UNROLL>(red_sm, bl_w0, bl_nw, T);
-        const float im = frcp(bl_M);
         float cc[3], A[9], Rb[9];
-        for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
-        for (int a = 0; a < 3; ++a)
-            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+        sm_body_sums<WIDE_OK, SM_UNROLL>(bl_w0, bl_nw, bl_M, mq3, red_sm, red_sm64, cc, A);
         if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
         for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
         for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
@@ -615,10 +782,9 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 
     // goal offsets D = R q - (x - c) and the momentum sums, in the frame
     // centred on c_i: z_b = r + C (before shape matching), z_a = z_b + D
-    float r[3], Dd[3];
+    float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
     for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
-    for (int a = 0; a < 3; ++a)
-        Dd[a] = act ? (R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2]) - r[a] : 0.0f;
+    if (act) goal_offset(R, q, x0, anc, del, cyv, Dd);
     {
         float S[NMOM];
         float zb[3], za[3], vb[3], t[3];
@@ -716,16 +882,20 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 // 85 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
 // (6 waves per SIMD, a few values spilled) for grids that oversubscribe it,
 // where more workgroups per CU hide each other's per-body phases.
-template <bool MULTI>
+// WIDE: some body of the launch spans more than kWideBodyWaves waves (FP64
+// sums for those bodies; the other bodies' arithmetic is the same in both
+// instances)
+template <bool MULTI, bool WIDE>
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<MULTI, 4, 4>(s, c, src, it);
+    iterate_body<MULTI, WIDE, 4, 4>(s, c, src, it);
 }
 
+// (its bodies span at most 4 waves: never wide)
 __global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<false, 2, 2>(s, c, src, it);
+    iterate_body<false, false, 2, 2>(s, c, src, it);
 }
 
 // ---------------------------------------------------------------------------
@@ -772,6 +942,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     constexpr int PG = 2;                // contact partners whose positions are loaded together
     constexpr int NSM = 12, NMOM = 24;
     __shared__ float4 red_sm[kMaxWaves * NSM / 4];
+    __shared__ double red_sm64[kMaxWaves * NSM];
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
     __shared__ float body_sm[kMaxWaves * 12];
     __shared__ float body_mom[kMaxWaves * 9];
@@ -791,19 +962,24 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     const int lb = b >= blk_b0 ? b - blk_b0 : 0;
     const int i = s0 + (wave - lw0) * 64 + lane;
     const bool act = b >= 0 && i < e0;
+    const bool wide = e0 - s0 > 64 * kWideBodyWaves;
     const size_t n = (size_t)s.n;
     const float ax = s.x0[s0], ay = s.x0[n + s0], az = s.x0[2 * n + s0];   // body anchor
+    const float anc[3] = {ax, ay, az};
     const uint32_t avg = (c.flags >> kAvgShift) & 3u;
 
+    // per-body constants in LDS rather than in registers of every lane; the
+    // previous iteration's rotation is read from the body's LDS slot
+    __shared__ float body_mq_s[kMaxWaves * 3];
     const bool body_lane = wave == 0 && lane < blk_nb;
     const int bb = blk_b0 + (body_lane ? lane : 0);
     int bl_w0 = 0, bl_nw = 0;
-    float bl_M = 1.0f, Rprev[9], mq3[3];
+    float bl_M = 1.0f;
     if (body_lane) {
         bl_w0 = s.body_wave0[bb] - blk * W;
         bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
         bl_M = s.body_mass[bb];
-        for (int j = 0; j < 3; ++j) mq3[j] = s.body_mq[3 * (size_t)bb + j];
+        for (int j = 0; j < 3; ++j) body_mq_s[lane * 3 + j] = s.body_mq[3 * (size_t)bb + j];
     }
 
     // X_0 - X_init and V_0 from the integration step; the rest is constant
@@ -853,34 +1029,29 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         y[0] = (x0[0] - ax) + del[0];
         y[1] = (x0[1] - ay) + del[1];
         y[2] = (x0[2] - az) + del[2];
-        {
-            float S[NSM];
-            for (int j = 0; j < 3; ++j) S[j] = m * y[j];
-            for (int a = 0; a < 3; ++a)
-                for (int k2 = 0; k2 < 3; ++k2) S[3 + 3 * a + k2] = m * y[a] * q[k2];
-            wave_sums_by_row<NSM>(S);
-            if ((lane & 15) == 15) {
-                float* dst = (float*)red_sm + wave * NSM + (lane >> 4) * (NSM / 4);
-                for (int j = 0; j < NSM / 4; ++j) dst[j] = S[j];
-            }
-        }
+        sm_wave_partials<true>(wide, m, y, q, wave, lane, red_sm, red_sm64);
         __syncthreads();
         if (body_lane) {
-            float T[NSM];
-            sum_wave_partials<NSM / 4, 4>(red_sm, bl_w0, bl_nw, T);
-            const float im = frcp(bl_M);
             float cc[3], A[9], Rb[9];
-            for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
-            for (int a = 0; a < 3; ++a)
-                for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
+            float mq3[3], Rprev[9];
+            for (int j = 0; j < 3; ++j) mq3[j] = body_mq_s[lane * 3 + j];
+            sm_body_sums<true, 4>(bl_w0, bl_nw, bl_M, mq3, red_sm, red_sm64, cc, A);
+            for (int j = 0; j < 9; ++j) Rprev[j] = body_sm[lane * 12 + j];   // (it > 0) the last iteration's
             if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
-            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rprev[j] = Rb[j];
+            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
             for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
         }
         __syncthreads();
-        float R[9], cyv[3];
-        for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
-        for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
+        // goal offsets (shape matching), formed before the contacts so that
+        // the rotation need not stay in registers through them
+        float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
+        {
+            float R[9], cyv[3];
+            for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+            for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
+            for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
+            if (act) goal_offset(R, q, x0, anc, del, cyv, Dd);
+        }
 
         // contacts from X_i (planes, then partners in list order)
         float Cd[3] = {0.0f, 0.0f, 0.0f};
@@ -888,9 +1059,9 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
             for (int pl = 0; pl < c.n_planes; ++pl) {
                 const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
                 const float un = nx * del[0] + ny * del[1] + nz * del[2];
-                const float e = ((nx * x0[0] + ny * x0[1] + nz * x0[2]) - c.plane_d[pl]) + un;
-                if (!(e < c.radius)) continue;
-                const float pen = c.radius - e;
+                const double e = plane_gap(c, pl, x0, del);
+                if (!(e < c.radius_d)) continue;
+                const float pen = (float)(c.radius_d - e);
                 const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
                 const float ut2 = ux * ux + uy * uy + uz * uz;
                 const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
@@ -964,10 +1135,6 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         }
 
 
-        float r[3], Dd[3];
-        for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
-        for (int a = 0; a < 3; ++a)
-            Dd[a] = act ? (R[3 * a] * q[0] + R[3 * a + 1] * q[1] + R[3 * a + 2] * q[2]) - r[a] : 0.0f;
         {
             float S[NMOM];
             float zb[3], za[3], vb[3], t[3];
@@ -1070,23 +1237,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         }
     }
     if (body_lane && s.body_rot)
-        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rprev[j];
-}
-
-// Canonical (key, id) order from the key grouping of the last substep: the
-// grouping keeps an arbitrary order inside a key (slots from atomic ranks);
-// particle i goes to its key's first slot plus the number of smaller ids
-// sharing its key.  Run on demand, outside the substep.
-__global__ void __launch_bounds__(kBlock) k_canonical(Scene s)
-{
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= s.n) return;
-    const uint32_t i = s.sorted_raw[j];
-    const uint32_t k = s.key[i];
-    const uint32_t b0 = s.cells[k].x, b1 = s.cells[k + 1].x;
-    uint32_t below = 0;
-    for (uint32_t q = b0; q < b1; ++q) below += (s.sorted_raw[q] < i) ? 1u : 0u;
-    s.sorted[b0 + below] = i;
+        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = body_sm[lane * 12 + j];
 }
 
 // End of a frame, in two launches so that a frame is committed whole or not
@@ -1141,31 +1292,44 @@ __global__ void __launch_bounds__(kBlock) k_clear_counters(Counters* c, NbrStats
     }
 }
 
+__global__ void __launch_bounds__(kBlock) k_zero(uint32_t* p, size_t words)
+{
+    const size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
 __global__ void __launch_bounds__(64) k_next_epoch(Counters* c)
 {
     if (threadIdx.x == 0) c->epoch += 1u;
 }
 
-__global__ void __launch_bounds__(kBlock) k_init_tables(Scene s)
+__global__ void __launch_bounds__(kBlock) k_init_tables(Scene s, size_t table)
 {
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < s.T) s.cell_count[i] = 0u;
-    if (i == 0) s.cells[s.T] = make_uint2((uint32_t)s.n, 0xffffffffu);
+    const size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x;
+    if (i < table) s.cells[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (i < (size_t)s.n_radix_tiles * kRadixBins) s.radix_state[i] = 0ull;
+    if (i < (size_t)(kMaxRadixPasses * kRadixBins)) s.hist[i] = 0u;
+    if (i < (size_t)kMaxRadixPasses) s.tile_ctr[i] = 0u;
+    if (i == 0) s.counters->epoch = 0u;
 }
 
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream)
 {
-    if (s.pscene)           // multi-scene mode: one variant for every mix
-        hipLaunchKernelGGL(k_iterate<true>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src,
-                           it);
-    else if (s.dense_iterate)
-        hipLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c, src,
-                           it);
-    else
-        hipLaunchKernelGGL(k_iterate<false>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s, c,
-                           src, it);
+    const dim3 grid(s.n_iter_blocks), block(64 * s.waves_per_block);
+    if (s.pscene) {         // multi-scene mode: a body's arithmetic does not depend on the mix
+        if (s.wide_bodies)
+            hipLaunchKernelGGL((k_iterate<true, true>), grid, block, 0, stream, s, c, src, it);
+        else
+            hipLaunchKernelGGL((k_iterate<true, false>), grid, block, 0, stream, s, c, src, it);
+    } else if (s.dense_iterate) {
+        hipLaunchKernelGGL(k_iterate_dense, grid, block, 0, stream, s, c, src, it);
+    } else if (s.wide_bodies) {
+        hipLaunchKernelGGL((k_iterate<false, true>), grid, block, 0, stream, s, c, src, it);
+    } else {
+        hipLaunchKernelGGL((k_iterate<false, false>), grid, block, 0, stream, s, c, src, it);
+    }
 }
 
 // The same launch with a pair of events bound to the dispatch itself: their
@@ -1173,15 +1337,24 @@ void launch_iterate(const Scene& s, const StepConsts& c, int src, int it, hipStr
 void launch_iterate_timed(const Scene& s, const StepConsts& c, int src, int it, hipStream_t stream, hipEvent_t t0,
                           hipEvent_t t1)
 {
+    const dim3 grid(s.n_iter_blocks), block(64 * s.waves_per_block);
     if (s.dense_iterate)
-        hipExtLaunchKernelGGL(k_iterate_dense, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1,
-                              0, s, c, src, it);
+        hipExtLaunchKernelGGL(k_iterate_dense, grid, block, 0, stream, t0, t1, 0, s, c, src, it);
+    else if (s.wide_bodies)
+        hipExtLaunchKernelGGL((k_iterate<false, true>), grid, block, 0, stream, t0, t1, 0, s, c, src, it);
     else
-        hipExtLaunchKernelGGL(k_iterate<false>, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, t0, t1, 0,
-                              s, c, src, it);
+        hipExtLaunchKernelGGL((k_iterate<false, false>), grid, block, 0, stream, t0, t1, 0, s, c, src, it);
 }
 
 }  // namespace
+
+hipError_t enqueue_zero(void* p, size_t bytes, hipStream_t stream)
+{
+    const size_t words = bytes / 4;
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words)), dim3(kBlock), 0, stream, (uint32_t*)p, words);
+    return hipGetLastError();
+}
 
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
 {
@@ -1191,16 +1364,12 @@ hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t enqueue_init_tables(const Scene& s, hipStream_t stream)
+hipError_t enqueue_init_tables(const Scene& s, size_t table, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_init_tables, dim3(blocks_for((size_t)s.T)), dim3(kBlock), 0, stream, s);
-    return hipGetLastError();
-}
-
-hipError_t enqueue_canonical_order(const Scene& s, hipStream_t stream)
-{
-    if (s.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_canonical, dim3(blocks_for((size_t)s.n)), dim3(kBlock), 0, stream, s);
+    size_t items = table;
+    items = items > (size_t)s.n_radix_tiles * kRadixBins ? items : (size_t)s.n_radix_tiles * kRadixBins;
+    items = items > (size_t)(kMaxRadixPasses * kRadixBins) ? items : (size_t)(kMaxRadixPasses * kRadixBins);
+    hipLaunchKernelGGL(k_init_tables, dim3(blocks_for(items)), dim3(kBlock), 0, stream, s, table);
     return hipGetLastError();
 }
 
@@ -1273,20 +1442,30 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
     const size_t extent = multi ? (size_t)s.n_extent : (size_t)s.n;
     const unsigned nb = blocks_for(extent);
     const unsigned nb_nbr = multi ? blocks_for((size_t)s.n_active) : nb;
-    const unsigned nb_pred = blocks_for(extent > (size_t)s.n_scan_tiles ? extent : (size_t)s.n_scan_tiles);
+    const size_t pred_items = (size_t)(kMaxRadixPasses * kRadixBins);
+    const unsigned nb_pred = blocks_for(extent > pred_items ? extent : pred_items);
+    const unsigned nb_hist = (unsigned)(((size_t)s.n_sort + kHistChunk - 1) / kHistChunk);
     const size_t nbr_lds = (size_t)c.nbr_cap * kBlock * sizeof(uint32_t);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
     for (int sub = 0; sub < count; ++sub) {
-        if (multi) {
+        if (multi)
             hipLaunchKernelGGL(k_predict_keys<true>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c, sub == 0 ? -1 : last);
-            hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_scatter<true>, dim3(nb), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb_nbr), dim3(kBlock), nbr_lds, stream, s, c);
-        } else {
+        else
             hipLaunchKernelGGL(k_predict_keys<false>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c,
                                sub == 0 ? -1 : last);
-            hipLaunchKernelGGL(k_scan, dim3(s.n_scan_tiles), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_scatter<false>, dim3(nb), dim3(kBlock), 0, stream, s);
+        // (key, id) sorted by key, stable: digit counts, then one pass per digit
+        hipLaunchKernelGGL(k_radix_hist, dim3(nb_hist), dim3(1024), 0, stream, s);
+        for (int p = 0; p < s.radix_passes; ++p) {
+            const uint32_t* kin = p == 0 ? s.key : s.kbuf[(p - 1) & 1];
+            const uint32_t* iin = p == 0 ? nullptr : s.ibuf[(p - 1) & 1];
+            hipLaunchKernelGGL(k_radix_pass, dim3(s.n_radix_tiles), dim3(kBlock), 0, stream, s, p, kin, iin,
+                               s.kbuf[p & 1], s.ibuf[p & 1]);
+        }
+        if (multi) {
+            hipLaunchKernelGGL(k_cells<true>, dim3(nb_nbr), dim3(kBlock), 0, stream, s);
+            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb_nbr), dim3(kBlock), nbr_lds, stream, s, c);
+        } else {
+            hipLaunchKernelGGL(k_cells<false>, dim3(nb), dim3(kBlock), 0, stream, s);
             hipLaunchKernelGGL(k_neighbours<false>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
         }
         if (!multi && s.resident_iterate) {

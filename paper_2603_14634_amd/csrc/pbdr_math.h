@@ -117,6 +117,54 @@ __device__ inline void wave_sums_by_row(float* v)
     }
 }
 
+// FP64 form of wave_sums_by_row: the same lane swaps and DPP steps applied to
+// both 32-bit halves of each value, with FP64 adds.  On return, every lane of
+// row j of v[p] holds the sum of value j K/4 + p, for p < K/4.
+template <int CTRL>
+__device__ inline double dpp_add64(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xf, 0xf, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xf, 0xf, false);
+    return v + __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+template <int K>
+__device__ inline void wave_sums_by_row64(double* v)
+{
+    static_assert(K % 4 == 0, "K must be a multiple of 4");
+    constexpr int H = K / 2, Q = K / 4;
+#pragma unroll
+    for (int p = 0; p < H; ++p) {
+        const unsigned long long a = __builtin_bit_cast(unsigned long long, v[p]);
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v[p + H]);
+        const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)a, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+        const unsigned l0 = lo[0], l1 = lo[1], h0 = hi[0], h1 = hi[1];
+        v[p] = __builtin_bit_cast(double, ((unsigned long long)h0 << 32) | l0) +
+               __builtin_bit_cast(double, ((unsigned long long)h1 << 32) | l1);
+    }
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        const unsigned long long a = __builtin_bit_cast(unsigned long long, v[p]);
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v[p + Q]);
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+        const unsigned l0 = lo[0], l1 = lo[1], h0 = hi[0], h1 = hi[1];
+        v[p] = __builtin_bit_cast(double, ((unsigned long long)h0 << 32) | l0) +
+               __builtin_bit_cast(double, ((unsigned long long)h1 << 32) | l1);
+    }
+#pragma unroll
+    for (int p = 0; p < Q; ++p) {
+        double t = v[p];
+        t = dpp_add64<0xb1>(t);    // quad_perm [1,0,3,2]
+        t = dpp_add64<0x4e>(t);    // quad_perm [2,3,0,1]
+        t = dpp_add64<0x141>(t);   // row_half_mirror
+        t = dpp_add64<0x140>(t);   // row_mirror: the row sum in all 16 lanes
+        v[p] = t;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // small 3x3 algebra (FP32)
 // ---------------------------------------------------------------------------

@@ -69,7 +69,7 @@ PoolLayout pool_layout(int32_t S, int32_t P, int32_t Bc, int cap)
     L.scenes = take(sizeof(pbdr::PoolScene) * s);
     L.stats = take(sizeof(pbdr::PoolStat) * s);
     L.save_stats = take(sizeof(pbdr::PoolStat) * s);
-    L.order = take(8 * s * kLanes);
+    L.order = take(8 * s * (kLanes + 1));    // one launch list per lane, and the captured graph's
     L.part = take(4 * 24 * slot_arena(S, P, Bc));
     L.sid = take(4 * p);
     L.rank = take(4 * p);
@@ -147,12 +147,32 @@ struct pbdr_pool {
     hipEvent_t uploaded[kLanes][2] = {};
     hipEvent_t done[kLanes] = {};        // recorded after each lane's latest launch
     int plan_buf[kLanes] = {};
+    // pbdr_pool_step replays a captured graph of lane 0's class launches (its
+    // fork and join included) while the resident scenes, the tuning and the
+    // frame count stay the same; a change of any of them captures it again
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t generation = 1;             // bumped by every change of the resident set or tuning
+    uint64_t graph_generation = 0;
+    int32_t graph_frames = 0;
 };
 
 namespace {
 
+void drop_graph(pbdr_pool* p)
+{
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->gexec = nullptr;
+    p->graph = nullptr;
+    p->graph_generation = 0;
+}
+
 void release_host(pbdr_pool* p)
 {
+    drop_graph(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     for (SlotInfo& si : p->slots)
         if (si.uploaded) (void)hipEventDestroy(si.uploaded);
     for (int l = 0; l < kLanes; ++l) {
@@ -182,22 +202,20 @@ pbdr_status check_slot(const pbdr_pool* p, int32_t slot)
 // work: slot j advances units[j] units (0 = stays).  The launch list is
 // uploaded from the lane's pinned buffers, so launches on different lanes may
 // be in flight together.
-pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector<int32_t>& units, int subs_per_unit,
-                   int only_class = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
+// The launch list: slots with work grouped by class (largest scenes first),
+// written to ho; first/count/nmax per class.  Returns the list length.
+int build_list(const pbdr_pool* p, const std::vector<int32_t>& units, int only_class, int2* ho,
+               int* first, int* count, int32_t* nmax)
 {
-    const int b = p->plan_buf[lane];
-    p->plan_buf[lane] ^= 1;
-    HIP_TRY(hipEventSynchronize(p->uploaded[lane][b]));       // the buffer's previous upload is done
-    int2* ho = p->h_order[lane][b];
     std::vector<int32_t> by_class[kLaunchClasses];
-    int32_t nmax[kLaunchClasses] = {0};   // largest slot count per class
+    for (int c = 0; c < kLaunchClasses; ++c) nmax[c] = 0;      // largest slot count per class
     for (int32_t j = 0; j < p->S; ++j) {
         const SlotInfo& si = p->slots[(size_t)j];
         if (!si.used || units[(size_t)j] <= 0 || (only_class >= 0 && si.cls != only_class)) continue;
         by_class[si.cls].push_back(j);
         nmax[si.cls] = std::max(nmax[si.cls], si.lanes_slots);
     }
-    int first[kLaunchClasses], count[kLaunchClasses], at = 0;
+    int at = 0;
     for (int c = 0; c < kLaunchClasses; ++c) {
         auto& v = by_class[c];
         // largest scenes first: they finish last, so they start first
@@ -207,14 +225,17 @@ pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector
         count[c] = (int)v.size();
         for (int32_t j : v) ho[at++] = make_int2(j, units[(size_t)j]);
     }
-    if (at == 0) return PBDR_OK;
-    HIP_TRY(hipStreamWaitEvent(stream, p->added, 0));          // scenes added on the pool's stream are in place
-    char* dev_order = p->ws + p->lay.order + 8 * (size_t)p->S * lane;
-    HIP_TRY(hipMemcpyAsync(dev_order, ho, 8 * (size_t)at, hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipEventRecord(p->uploaded[lane][b], stream));
+    return at;
+}
+
+// Enqueues the class launches of a list already on the device (dev_order),
+// on `stream`, or side by side on the lane's aux streams (fork and join by
+// events, which a stream capture records as graph dependencies).
+pbdr_status enqueue_classes(pbdr_pool* p, int lane, hipStream_t stream, const char* dev_order, const int* first,
+                            const int* count, const int32_t* nmax, int subs_per_unit)
+{
     pbdr::PoolDev d = p->dev;
     d.order = (const int2*)dev_order;
-    if (t0) HIP_TRY(hipEventRecord(t0, stream));
     int active = 0;
     for (int c = 0; c < kLaunchClasses; ++c) active += count[c] > 0;
     // Lane 0 runs several classes side by side on its aux streams; the other
@@ -238,8 +259,67 @@ pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector
     if (active > 1)
         for (int c = 0; c < kLaunchClasses; ++c)
             if (count[c]) HIP_TRY(hipStreamWaitEvent(stream, p->join[lane][c], 0));
+    return PBDR_OK;
+}
+
+pbdr_status launch(pbdr_pool* p, int lane, hipStream_t stream, const std::vector<int32_t>& units, int subs_per_unit,
+                   int only_class = -1, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
+{
+    const int b = p->plan_buf[lane];
+    p->plan_buf[lane] ^= 1;
+    HIP_TRY(hipEventSynchronize(p->uploaded[lane][b]));       // the buffer's previous upload is done
+    int2* ho = p->h_order[lane][b];
+    int first[kLaunchClasses], count[kLaunchClasses];
+    int32_t nmax[kLaunchClasses];
+    const int at = build_list(p, units, only_class, ho, first, count, nmax);
+    if (at == 0) return PBDR_OK;
+    HIP_TRY(hipStreamWaitEvent(stream, p->added, 0));          // scenes added on the pool's stream are in place
+    char* dev_order = p->ws + p->lay.order + 8 * (size_t)p->S * lane;
+    HIP_TRY(hipMemcpyAsync(dev_order, ho, 8 * (size_t)at, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventRecord(p->uploaded[lane][b], stream));
+    if (t0) HIP_TRY(hipEventRecord(t0, stream));
+    pbdr_status st = enqueue_classes(p, lane, stream, dev_order, first, count, nmax, subs_per_unit);
+    if (st != PBDR_OK) return st;
     if (t1) HIP_TRY(hipEventRecord(t1, stream));
     HIP_TRY(hipEventRecord(p->done[lane], stream));
+    return PBDR_OK;
+}
+
+// pbdr_pool_step: every resident scene advances n_frames frames, by replaying
+// the captured graph of lane 0's class launches (captured again when the
+// resident set, the tuning or n_frames changed since).
+pbdr_status launch_graph(pbdr_pool* p, int32_t n_frames)
+{
+    if (!p->gexec || p->graph_generation != p->generation || p->graph_frames != n_frames) {
+        drop_graph(p);
+        std::vector<int32_t> units((size_t)p->S, n_frames);
+        std::vector<int2> ho((size_t)p->S);
+        int first[kLaunchClasses], count[kLaunchClasses];
+        int32_t nmax[kLaunchClasses];
+        const int at = build_list(p, units, -1, ho.data(), first, count, nmax);
+        if (at == 0) return PBDR_OK;
+        // the graph's own launch list, read by every replay
+        char* dev_order = p->ws + p->lay.order + 8 * (size_t)p->S * kLanes;
+        HIP_TRY(hipStreamWaitEvent(p->stream, p->added, 0));
+        HIP_TRY(hipMemcpyAsync(dev_order, ho.data(), 8 * (size_t)at, hipMemcpyHostToDevice, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+        pbdr_status st = enqueue_classes(p, 0, p->cap_stream, dev_order, first, count, nmax, p->res.p.substeps);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+        if (st != PBDR_OK || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return st != PBDR_OK ? st : fail(PBDR_ERR_DEVICE, "pool graph capture failed: %s", hipGetErrorString(e));
+        }
+        p->graph = g;
+        HIP_TRY(hipGraphInstantiate(&p->gexec, p->graph, nullptr, nullptr, 0));
+        p->graph_generation = p->generation;
+        p->graph_frames = n_frames;
+    }
+    HIP_TRY(hipStreamWaitEvent(p->stream, p->added, 0));
+    HIP_TRY(hipGraphLaunch(p->gexec, p->stream));
+    HIP_TRY(hipEventRecord(p->done[0], p->stream));
     return PBDR_OK;
 }
 
@@ -349,7 +429,10 @@ pbdr_status pbdr_pool_create(const pbdr_params* params, int32_t max_scenes, int3
     for (int j = 0; j < r.p.n_planes; ++j) {
         for (int k = 0; k < 3; ++k) c.plane_n[j][k] = (float)r.p.planes[j][k];
         c.plane_d[j] = (float)r.p.planes[j][3];
+        c.plane_d_d[j] = r.p.planes[j][3];
     }
+    c.radius_d = r.p.radius;
+    c.two_r_d = 2.0 * r.p.radius;
     c.iterations = r.p.iterations;
 
     char* w = p->ws;
@@ -457,6 +540,7 @@ pbdr_status pbdr_pool_add(pbdr_pool* p, const pbdr_pool_scene_desc* desc, int32_
     p->free_slots.pop_back();
     SlotInfo& si = p->slots[(size_t)slot];
     si.used = true;
+    p->generation += 1;
     si.p0 = p0;
     si.n = n;
     si.b0 = b0;
@@ -561,6 +645,7 @@ pbdr_status pbdr_pool_remove(pbdr_pool* p, int32_t slot)
     p->used_bodies -= si.nb;
     p->used_scenes -= 1;
     si.used = false;
+    p->generation += 1;
     if (si.uploaded) HIP_TRY(hipEventSynchronize(si.uploaded));   // the upload has read the staging copy
     si.staging.clear();
     si.staging.shrink_to_fit();
@@ -574,8 +659,11 @@ pbdr_status pbdr_pool_step(pbdr_pool* p, int32_t n_frames)
     if (n_frames < 0) return fail(PBDR_ERR_INVALID_ARG, "n_frames must be >= 0");
     if ((long long)n_frames * p->res.p.substeps > INT_MAX) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
     if (n_frames == 0) return PBDR_OK;
-    std::vector<int32_t> units((size_t)p->S, n_frames);
-    return launch(p, 0, p->stream, units, p->res.p.substeps);
+    if (p->res.p.flags & PBDR_FLAG_NO_GRAPH) {
+        std::vector<int32_t> units((size_t)p->S, n_frames);
+        return launch(p, 0, p->stream, units, p->res.p.substeps);
+    }
+    return launch_graph(p, n_frames);
 }
 
 pbdr_status pbdr_pool_step_slots(pbdr_pool* p, int32_t count, const int32_t* slots, const int32_t* frames)
@@ -713,6 +801,7 @@ pbdr_status pbdr_pool_set_tuning(pbdr_pool* p, const int32_t* waves)
     for (int c = 0; c < kClasses; ++c)
         if (!valid_waves(waves[c])) return fail(PBDR_ERR_INVALID_ARG, "waves[%d] = %d is not 1, 2, 4, 8 or 16", c, waves[c]);
     for (int c = 0; c < kClasses; ++c) p->waves[c] = waves[c];
+    p->generation += 1;
     return PBDR_OK;
 }
 
@@ -769,6 +858,7 @@ pbdr_status pbdr_pool_autotune(pbdr_pool* p, int32_t n_frames, int32_t repeats, 
         p->waves[c] = best_w;
         if (ms_out) ms_out[c] = best;
     }
+    p->generation += 1;
     pbdr_status st2 = restore();
     hipError_t e = hipStreamSynchronize(p->stream);
     (void)hipEventDestroy(t0);

@@ -81,6 +81,8 @@ struct PoolConsts {
     float plane_n[kMaxPlanes][3];
     float plane_d[kMaxPlanes];
     int32_t iterations;
+    double radius_d, two_r_d;            // contact geometry in FP64
+    double plane_d_d[kMaxPlanes];
 };
 
 // Dynamic LDS bytes of the pool kernel for a size class (or kPoolBigClass).

@@ -259,9 +259,11 @@ __device__ inline void contacts(const Ctx& x, int i, const float* x0, const floa
     for (int pl = 0; pl < c.n_planes; ++pl) {
         const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
         const float un = nx * del[0] + ny * del[1] + nz * del[2];
-        const float e = ((nx * x0[0] + ny * x0[1] + nz * x0[2]) - c.plane_d[pl]) + un;
-        if (!(e < c.radius)) continue;
-        const float pen = c.radius - e;
+        // signed distance and penetration in FP64, rounded only as a correction
+        double e = -c.plane_d_d[pl];
+        for (int k = 0; k < 3; ++k) e += (double)c.plane_n[pl][k] * ((double)x0[k] + (double)del[k]);
+        if (!(e < c.radius_d)) continue;
+        const float pen = (float)(c.radius_d - e);
         const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
         const float ut2 = ux * ux + uy * uy + uz * uz;
         const float f = ut2 > 0.0f ? fminf(1.0f, x.mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
@@ -273,18 +275,20 @@ __device__ inline void contacts(const Ctx& x, int i, const float* x0, const floa
     for (uint32_t sl = 0; sl < stored; ++sl) {
         const uint32_t jq = x.lists[(size_t)sl * x.n + i];
         const size_t gq = (size_t)x.p0 + jq;
-        float dd[3], u[3];
+        // separation, distance, penetration and normal in FP64
+        double dd[3];
+        float u[3];
         for (int k = 0; k < 3; ++k) {
             const float dj = d.dl[k * P + gq];
-            dd[k] = (x0[k] - d.x0[k * P + gq]) + (del[k] - dj);
+            dd[k] = ((double)x0[k] - (double)d.x0[k * P + gq]) + ((double)del[k] - (double)dj);
             u[k] = del[k] - dj;
         }
-        const float l2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
-        const float l = __builtin_amdgcn_sqrtf(l2);
-        if (!(l > 0.0f) || !(l < c.two_r)) continue;
-        const float il = frcp(l);
-        const float nx = dd[0] * il, ny = dd[1] * il, nz = dd[2] * il;
-        const float pen = c.two_r - l;
+        const double l2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+        if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) continue;
+        const double l = sqrt(l2);
+        const double il = 1.0 / l;
+        const float nx = (float)(dd[0] * il), ny = (float)(dd[1] * il), nz = (float)(dd[2] * il);
+        const float pen = (float)(c.two_r_d - l);
         const float mq = d.mass[gq];
         const float alpha = mq * frcp(m + mq);           // w_p / (w_p + w_q)
         const float un = u[0] * nx + u[1] * ny + u[2] * nz;
@@ -317,13 +321,21 @@ __device__ inline void sm_terms(bool act, const float* br, const float* x0, cons
 }
 
 // Offsets of a particle in the frame centred on the body's current centre:
-// r = (X_i - anchor) - c and the shape-matching goal offset D = R q - r.
+// r = (X_i - anchor) - c and the shape-matching goal offset D = R q - r.  D's
+// terms are body-sized while D is of the order of the contact corrections, so
+// it is formed in FP64 (products of FP32 values and the anchor difference are
+// exact there; only the result is rounded): in FP32 each particle's goal
+// would carry a rounding of ~ulp(0.1 m) that no rigid motion absorbs.
 __device__ inline void goal_offsets(bool act, const float* br, const float* x0, const float* del, const float* q,
                                     float* rr, float* Dd)
 {
     for (int k = 0; k < 3; ++k) rr[k] = ((x0[k] - br[kBAnchor + k]) + del[k]) - br[kBC + k];
-    for (int a = 0; a < 3; ++a)
-        Dd[a] = act ? (br[kBR + 3 * a] * q[0] + br[kBR + 3 * a + 1] * q[1] + br[kBR + 3 * a + 2] * q[2]) - rr[a] : 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const double rq = (double)br[kBR + 3 * a] * (double)q[0] + (double)br[kBR + 3 * a + 1] * (double)q[1] +
+                          (double)br[kBR + 3 * a + 2] * (double)q[2];
+        const double ya = ((double)x0[a] - (double)br[kBAnchor + a]) + (double)del[a];
+        Dd[a] = act ? (float)(rq - (ya - (double)br[kBC + a])) : 0.0f;
+    }
 }
 
 // Momentum terms of one particle (Eqs. (4)-(5) in the frame centred on c_i):

@@ -207,7 +207,7 @@ def cuboid_rain(seed: int = 0, n_bodies: int = 1000, radius: float = 0.01,
 
 def dense_pile(seed: int = 0, n_bodies: int = 20000, radius: float = 0.01,
                half_width: float = 2.0, sigma: float = 0.5, mean_count: float = 100.0,
-               gap_frac: float = 0.05, speed: float = 0.5) -> Scene:
+               gap_frac: float = 0.05, speed: float = 0.5, packed: bool = False) -> Scene:
     """20k mixed bodies packed tightly into a walled 4 x 4 m bin.
 
     Particle counts are log-normal (sigma 0.5, mean 100), clipped to [8, 1024];
@@ -216,6 +216,11 @@ def dense_pile(seed: int = 0, n_bodies: int = 20000, radius: float = 0.01,
     spheres, with random orientations and N(0, speed^2) velocities, so contacts
     start within the first substeps.  Solver settings: 8 substeps x 20
     iterations, walls at x, y = +-2 m.
+
+    ``packed``: the same bodies without rotation, shelf-packed by their
+    bounding boxes (gap ``gap_frac * r`` between the boxes of the particle
+    spheres) from the ground up: a pile that is dense from the start, with
+    faces of neighbouring bodies in contact when gap_frac < 0.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     mu_ln = math.log(mean_count) - 0.5 * sigma * sigma
@@ -229,8 +234,11 @@ def dense_pile(seed: int = 0, n_bodies: int = 20000, radius: float = 0.01,
             o = lattice_box(a, b, cz, 2 * radius)
         else:
             o = lattice_ball(int(c), 2 * radius)
-        offs.append(random_rotation(rng) @ o)
+        rot = random_rotation(rng)
+        offs.append(o if packed else rot @ o)
         masses.append(rng.uniform(500.0, 2000.0) * (2 * radius) ** 3)
+    if packed:
+        return _box_packed_pile(rng, offs, masses, radius, half_width, gap_frac, speed)
     radii = np.array([_bounding_radius(o, radius) for o in offs])
     gap = gap_frac * radius
     # shelf packing: rows along x, rows stacked along y, layers along z
@@ -255,6 +263,38 @@ def dense_pile(seed: int = 0, n_bodies: int = 20000, radius: float = 0.01,
         layer_h = max(layer_h, d)
     parts = [o + c.reshape(3, 1) for o, c in zip(offs, centres)]
     vels = [rng.normal(0.0, speed, size=3) for _ in range(n_bodies)]
+    x, v, m, bs = _assemble(parts, vels, masses)
+    walls = ((1.0, 0.0, 0.0, -half_width), (-1.0, 0.0, 0.0, -half_width),
+             (0.0, 1.0, 0.0, -half_width), (0.0, -1.0, 0.0, -half_width))
+    return Scene(x, v, m, bs, radius=radius, substeps=8, iterations=20,
+                 planes=(GROUND,) + walls, name="dense_pile_20k")
+
+
+def _box_packed_pile(rng, offs, masses, radius, half_width, gap_frac, speed) -> Scene:
+    """Bodies shelf-packed by bounding boxes (rows along x, rows along y,
+    layers along z, from z = 0 up) in the walled bin of ``dense_pile``."""
+    gap = gap_frac * radius
+    lo_b = -half_width + radius * 0.5
+    hi_b = half_width - radius * 0.5
+    x0, y0, z0 = lo_b, lo_b, 0.0
+    row_h, layer_h = 0.0, 0.0
+    parts = []
+    for o in offs:
+        omin, omax = o.min(axis=1) - radius, o.max(axis=1) + radius
+        ext = omax - omin + gap
+        if x0 + ext[0] > hi_b:
+            x0 = lo_b
+            y0 += row_h
+            row_h = 0.0
+        if y0 + ext[1] > hi_b:
+            y0 = lo_b
+            z0 += layer_h
+            layer_h = 0.0
+        parts.append(o + (np.array([x0, y0, z0]) - omin).reshape(3, 1))
+        x0 += ext[0]
+        row_h = max(row_h, ext[1])
+        layer_h = max(layer_h, ext[2])
+    vels = [rng.normal(0.0, speed, size=3) for _ in offs]
     x, v, m, bs = _assemble(parts, vels, masses)
     walls = ((1.0, 0.0, 0.0, -half_width), (-1.0, 0.0, 0.0, -half_width),
              (0.0, 1.0, 0.0, -half_width), (0.0, -1.0, 0.0, -half_width))

@@ -94,13 +94,11 @@ def test_batch_substep_matches_reference(orc):
     batch.close()
 
 
-@pytest.mark.parametrize("flags", [B.FLAG_STD_VELOCITY, B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN])
+@pytest.mark.parametrize("flags", [B.FLAG_STD_VELOCITY, B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN,
+                                   B.PP_AVG_NONE])
 def test_batch_flags_match_reference(orc, flags):
-    # bodies of up to 513 particles: with a momentum correction switched off,
-    # bodies of 700-900 particles differ from the FP64 reference by up to
-    # 1.4e-5 r per substep (FP32 shape matching, no longer corrected), above
-    # the 1e-5 r gate; the ablations are for Table III, not the method
-    scs = _scenes()[2:3]
+    # bodies of 1 to 1000 particles (the larger ones take FP64 shape-matching sums)
+    scs = _scenes()[2:4] + _scenes()[:1]
     batch = B.Batch(B.params_for(scs[0], flags=flags), len(scs), sum(s.n for s in scs),
                     sum(s.n_bodies for s in scs))
     slots = [batch.add(sc) for sc in scs]

@@ -12,9 +12,10 @@ Ablation (Table III): the same sliding box with the modified velocity update
 replaced by the standard one, or with either momentum correction dropped.  The
 errors are printed; the full method must meet the closed form, and each
 ablation must show the direction of Table III: dropping the linear correction
-lets linear momentum drift, and the standard velocity update or dropping the
-angular correction lets the box turn (FP32 rounding drives both).  The paper's
-magnitudes come from its own engine and are not a pin here (parity unpinned).
+lets linear momentum drift, the standard velocity update loses velocity
+(momentum) accuracy, and dropping the angular correction lets the box turn
+(FP32 rounding drives it).  The paper's magnitudes come from its own engine and
+are not a pin here (parity unpinned).
 """
 import json
 import math
@@ -187,4 +188,5 @@ def test_ablation_of_velocity_update_and_momentum_constraint(orc):
     full_p, full_rot = errs["PBD-R"][1], max(errs["PBD-R"][2], 1e-7)
     assert errs["no linear momentum"][1] > 3.0 * full_p
     assert errs["no angular momentum"][2] > 20.0 * full_rot
-    assert errs["standard velocity"][2] > 20.0 * full_rot
+    # Table III puts the standard velocity update's damage in the velocity
+    assert errs["standard velocity"][1] > 3.0 * full_p

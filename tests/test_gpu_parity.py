@@ -56,10 +56,11 @@ def _ulp32(a):
     return (np.spacing(a)).astype(np.float64)
 
 
-def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=None, label="", quiet=False):
+def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=None, label="", quiet=False,
+                  already_stepped=False):
     """One substep from the FP32 state (x, v) on both sides; asserts parity.
     The largest error/tolerance ratios of displacement and velocity are left in
-    `check_substep.ratios`."""
+    `check_substep.ratios`.  already_stepped: `solver` has run that substep."""
     import torch
 
     x = np.ascontiguousarray(x, dtype=np.float32)
@@ -67,12 +68,13 @@ def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=
     if not quiet:
         print("[parity] %s n=%d bodies=%d flags=%#x" % (label or sc.name, sc.n, sc.n_bodies, flags), flush=True)
     s = solver or _gpu_solver(sc, flags=flags, cap=cap, bits=bits)
-    s.set_state(x, v)
-    acc_t = None
-    if accel is not None:
-        acc_t = torch.tensor(np.ascontiguousarray(accel, dtype=np.float32), device="cuda")
-        s.set_accel(acc_t)
-    s.substep(1)
+    if not already_stepped:
+        s.set_state(x, v)
+        acc_t = None
+        if accel is not None:
+            acc_t = torch.tensor(np.ascontiguousarray(accel, dtype=np.float32), device="cuda")
+            s.set_accel(acc_t)
+        s.substep(1)
     xg, vg = s.read_state()
     dg = s.read_debug(B.DEBUG_DELTA).astype(np.float64)
     p = _orc_params(orc, sc, flags=flags, cap=cap, bits=bits)
@@ -105,9 +107,9 @@ def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=
     check_substep.ratios = (float((d_err / tol_d).max()) if sc.n else 0.0,
                             float((v_err / tol_v).max()) if sc.n else 0.0)
     if not quiet:
-        print("[parity]   max |d err| %.3g (tol %.3g)  max |v err| %.3g  contacts max %d"
-              % (d_err.max() if sc.n else 0, tol_d, v_err.max() if sc.n else 0, int(cnt.max()) if sc.n else 0),
-              flush=True)
+        print("[parity]   max |d err| %.3g (tol %.3g)  max |v err| %.3g  contacts max %d, mean %.4f"
+              % (d_err.max() if sc.n else 0, tol_d, v_err.max() if sc.n else 0, int(cnt.max()) if sc.n else 0,
+                 float(cnt.mean()) if sc.n else 0.0), flush=True)
     assert np.all(d_err <= tol_d), "displacement error %.3g > %.3g" % (d_err.max(), tol_d)
     assert np.all(x_err <= tol_x)
     assert np.all(v_err <= tol_v), "velocity error %.3g" % v_err.max()
@@ -229,6 +231,19 @@ def test_cuboid_rain_16_substeps_of_the_first_40_frames(orc):
     assert max(_sampled_gate(orc, sc, picks, s, "cuboid_rain")) >= 1
 
 
+def test_cuboid_rain_8_substeps_of_frames_120_to_200(orc):
+    """The rain once it has landed (frames 120-200, where bodies rest on the
+    ground and on each other and partners wait on each other inside the
+    one-launch iteration kernel), at 8 evenly spaced substeps, each from the
+    reference state rounded to FP32."""
+    sc = scenes.cuboid_rain(0)
+    s = _gpu_solver(sc)
+    assert s.info().iteration_kernel == 2
+    picks = [int(round(k)) for k in np.linspace(120 * sc.substeps, 200 * sc.substeps - 1, 8)]
+    contacts = _sampled_gate(orc, sc, picks, s, "cuboid_rain (landed)")
+    assert min(contacts) >= 1
+
+
 def test_dense_pile_16_substeps_of_the_first_4_frames(orc):
     """The 20k-body pile (2.0M particles, overlapping start) at 16 evenly
     spaced substeps of its first 4 frames (the reference takes seconds per
@@ -241,6 +256,21 @@ def test_dense_pile_16_substeps_of_the_first_4_frames(orc):
     assert int(np.diff(sc.body_start).max()) > 256
     picks = [int(round(k)) for k in np.linspace(0, 4 * sc.substeps - 1, 16)]
     assert min(_sampled_gate(orc, sc, picks, s, "dense_pile")) >= 1
+
+
+def test_dense_pile_packed_8_substeps_of_the_first_2_frames(orc):
+    """The 20k-body pile packed by bounding boxes with overlapping faces, a
+    state as dense in contacts as the settled pile the benchmark times (mean
+    list length at least that of the settled pile, 0.14 after 240 frames), at
+    8 evenly spaced substeps of its first 2 frames."""
+    sc = scenes.dense_pile(0, gap_frac=-0.1, packed=True)
+    s = _gpu_solver(sc)
+    assert s.info().iteration_kernel == 1
+    picks = [int(round(k)) for k in np.linspace(0, 2 * sc.substeps - 1, 8)]
+    _sampled_gate(orc, sc, picks, s, "dense_pile (packed)")
+    kbar = s.neighbour_stats()[1]
+    print("[gate] dense_pile (packed): mean neighbour count %.4f in the last gated substep" % kbar, flush=True)
+    assert kbar >= 0.14
 
 
 # ---------------------------------------------------------------------------
@@ -313,10 +343,23 @@ def test_read_bodies_matches_reference(orc):
         np.testing.assert_allclose(got[1][b], R0, atol=2e-5)
 
 
-@pytest.mark.parametrize("flags", [B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN, B.PP_AVG_NONE])
-def test_flags_match_reference(orc, flags):
-    sc = _touching_bodies([27, 64, 8, 125], seed=3)
-    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, flags=flags, label="flags %#x" % flags)
+@pytest.mark.parametrize("launches", [0, B.FLAG_ITERATION_LAUNCHES])
+@pytest.mark.parametrize("flags", [B.FLAG_STD_VELOCITY, B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN,
+                                   B.PP_AVG_NONE])
+def test_flags_match_reference(orc, flags, launches):
+    """Table III's ablations and the pair-weight modes, on bodies of 8 to 1024
+    particles, through the one-launch iteration kernel and through one launch
+    per iteration.  The plain sum of pair corrections is gated on the smaller
+    bodies: where particles of large bodies touch several others it
+    over-corrects, and the FP64 reference itself then amplifies perturbations
+    of 1e-12 m several hundred times (test_oracle_pins:
+    test_plain_pair_sum_is_ill_conditioned_on_face_contacts), which no FP32
+    evaluation can follow to 1e-5 r."""
+    sizes = [27, 64, 8, 125] if flags == B.PP_AVG_NONE else [27, 1024, 8, 700, 125, 900, 513]
+    sc = _touching_bodies(sizes, seed=3)
+    s = _gpu_solver(sc, flags=flags | launches)
+    assert s.info().iteration_kernel == (0 if launches else 2)
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, flags=flags, solver=s, label="flags %#x" % (flags | launches))
     assert c >= 1
 
 
@@ -327,6 +370,15 @@ def test_walls_friction_and_external_acceleration(orc):
     check_substep(orc, sc, sc.x, sc.v, accel=acc, label="walls + accel")
     sc.mu = 0.0
     check_substep(orc, sc, sc.x, sc.v, label="walls, mu = 0")
+
+
+@pytest.mark.parametrize("bits", [6, 8, 9, 17, 25])
+def test_key_sort_passes(orc, bits):
+    """Keys of 6 to 25 bits: one to four 8-bit radix passes, all giving the
+    (key, id) order and the tables of the reference."""
+    sc = _touching_bodies([64, 125, 27, 300, 8], seed=4)
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, bits=bits, label="k = %d" % bits)
+    assert c >= 1
 
 
 def test_heavy_hash_aliasing(orc):
@@ -509,6 +561,54 @@ def test_one_launch_iterations_equal_iteration_launches(scene):
     np.testing.assert_array_equal(out[0][1], out[2][1])
     np.testing.assert_array_equal(out[0][0], out[1][0])
     np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
+def test_two_scenes_on_two_streams(orc):
+    """Two 171k-particle scenes stepped at the same time on two streams.  Each
+    alone would run its iterations as one launch, whose workgroups wait for
+    each other; the two grids do not fit on the GPU together, so while both
+    exist they take one launch per iteration.  Nothing waits or gives up,
+    every substep matches the reference, and the states equal the scenes
+    stepped alone."""
+    import torch
+
+    sc = scenes.cuboid_rain(0)
+    states = _oracle_substep_states(orc, sc, [0, 300])
+    p = B.params_for(sc, hash_bits=_hash_bits(sc.n), flags=B.FLAG_NO_GRAPH)
+    solo = B.Solver(p, sc.x, sc.v, sc.mass, sc.body_start)
+    assert solo.info().iteration_kernel == 2
+    solo.set_state(*states[300])
+    solo.step(6)
+    xs, vs = solo.read_state()
+    solo.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    pair = [B.Solver(p, sc.x, sc.v, sc.mass, sc.body_start, stream=st) for st in streams]
+    for k in (0, 300):                               # one substep of both at once, from the reference state
+        for s in pair:
+            s.set_state(*states[k])
+        for s in pair:
+            s.substep(1)
+        for j, s in enumerate(pair):
+            assert s.info().iteration_kernel == 0
+            check_substep(orc, sc, *states[k], solver=s, label="stream %d, substep %d" % (j, k),
+                          already_stepped=True)
+    for s in pair:
+        s.set_state(*states[300])
+    for _ in range(6):                               # frames interleaved on the two streams
+        for s in pair:
+            s.step(1)
+    torch.cuda.synchronize()
+    for s in pair:
+        assert s.status() == B.OK, B.last_error()
+        x, v = s.read_state()
+        np.testing.assert_array_equal(x, xs)
+        np.testing.assert_array_equal(v, vs)
+    for s in pair:
+        s.close()
+    alone = B.Solver(p, sc.x, sc.v, sc.mass, sc.body_start, stream=streams[0])
+    alone.step(1)
+    assert alone.info().iteration_kernel == 2        # the other scene is gone: one launch again
+    alone.close()
 
 
 def test_checkpoint_resume_is_bit_identical():

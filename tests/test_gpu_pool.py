@@ -137,6 +137,67 @@ def test_pool_sampled_scenes_of_the_full_batch(orc):
     pool.close()
 
 
+def test_pool_sampled_batch_scenes_in_contact(orc):
+    """16 scenes of the 4096-scene batch (spread over its sizes) after 250
+    reference frames, when every body has landed: one substep of each, from
+    the reference state rounded to FP32 (rest pose: that state, on both
+    sides).  Every scene rests on the ground, and some bodies on each other."""
+    batch = scenes.batch_scenes(0)
+    order = np.argsort([sc.n for sc in batch])
+    pick = [int(order[j]) for j in np.linspace(0, len(batch) - 1, 16).astype(int)]
+    moved = []
+    for j in pick:
+        sc = batch[j]
+        p = orc.params_for(sc, threads=THREADS)
+        rest = orc.Body(sc.x, sc.mass, sc.body_start)
+        x, v, _ = orc.substep(p, rest, sc.x, sc.v, n_substeps=250 * sc.substeps)
+        sc2 = sc.copy()
+        sc2.x, sc2.v = x.astype(np.float32), v.astype(np.float32)
+        moved.append(sc2)
+    pool = _new_pool(moved)
+    slots = [pool.add(sc) for sc in moved]
+    pool.substep(1)
+    contacts = [_check_scene(orc, pool, sl, sc, sc.x, sc.v, label="batch scene %d after 250 frames" % j)
+                for sl, sc, j in zip(slots, moved, pick)]
+    print("[pool] pair contacts per sampled scene: %s" % contacts, flush=True)
+    assert all(float(sc.x[2].min()) < 1.001 * sc.radius for sc in moved)   # on the ground
+    assert max(contacts) >= 1                                          # and bodies on bodies
+    pool.close()
+
+
+def test_pool_step_graph_replays_equal_direct_launches():
+    """pbdr_pool_step replays a captured graph of the class launches (fork and
+    join included); pbdr_pool_step_slots launches them directly.  Replayed
+    several times, with other work and synchronisations between the replays,
+    and captured again after the resident set changes, the states stay
+    bitwise equal to the direct launches'."""
+    import torch
+
+    scs = scenes.batch_scenes(3, n_scenes=48)
+    graphed, direct = _new_pool(scs), _new_pool(scs)
+    sg = [graphed.add(sc) for sc in scs]
+    sd = [direct.add(sc) for sc in scs]
+    scratch = torch.zeros(1 << 20, device="cuda")
+    for rep in range(6):
+        if rep == 3:                       # a new resident set: the graph is captured again
+            graphed.remove(sg[5])
+            direct.remove(sd[5])
+            sg[5] = sd[5] = None
+        graphed.step(2)
+        direct.step_slots([s for s in sd if s is not None], [2] * sum(s is not None for s in sd))
+        scratch.add_(1.0)                  # eager work between the replays
+        torch.cuda.synchronize()
+        for a, b in zip(sg, sd):
+            if a is None:
+                continue
+            xa, va = graphed.read_state(a)
+            xb, vb = direct.read_state(b)
+            np.testing.assert_array_equal(xa, xb)
+            np.testing.assert_array_equal(va, vb)
+    graphed.close()
+    direct.close()
+
+
 def test_scene_result_is_the_same_alone_in_a_mix_and_for_every_launch_shape():
     scs = _mixed_scenes()
     target = scs[-2]                            # 2912 particles: several register sets per lane

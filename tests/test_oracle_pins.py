@@ -289,6 +289,44 @@ def test_symmetric_averaging_conserves_total_momentum(orc):
         np.testing.assert_allclose(P1, P0, rtol=0, atol=1e-12 * np.abs(P0).max())
 
 
+def _amplification(orc, sc, flags, seeds=3, eps=1e-9):
+    """Largest change of the reference's substep per unit of a random velocity
+    perturbation of eps (a position perturbation of h eps), applied only where
+    it leaves the FP32 velocity unchanged, so the FP32 predicted positions and
+    the neighbour lists stay the same."""
+    p = orc.params_for(sc, flags=flags)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
+    x1, _, _ = orc.substep(p, rest, x, v)
+    h = sc.dt_frame / sc.substeps
+    xt = orc.predict32(p, sc.x, sc.v)
+    out = 0.0
+    for seed in range(seeds):
+        vp = v + np.random.default_rng(seed).normal(0.0, eps, size=v.shape)
+        keep = vp.astype(np.float32) != v.astype(np.float32)
+        vp[keep] = v[keep]
+        assert np.array_equal(orc.predict32(p, sc.x, vp.astype(np.float32)), xt)
+        x2, _, _ = orc.substep(p, rest, x, vp)
+        out = max(out, float(np.abs(x2 - x1).max()) / (h * eps))
+    return out
+
+
+def test_plain_pair_sum_is_ill_conditioned_on_face_contacts(orc):
+    """Pair weights (averaging reading): with 1/max(n_p, n_q) the Jacobi
+    iteration contracts perturbations, while the plain sum over-corrects
+    where particles of large bodies touch several others and amplifies a
+    perturbation of 1e-12 m hundreds of times.  On smaller bodies the plain
+    sum contracts too.  (This is why the GPU gate of the plain-sum mode uses
+    the smaller bodies.)"""
+    from scene_helpers import touching_bodies
+
+    big = touching_bodies([27, 1024, 8, 700, 125, 900, 513], seed=3)
+    small = touching_bodies([27, 64, 8, 125], seed=3)
+    assert _amplification(orc, big, 0) < 3.0
+    assert _amplification(orc, big, 2 << 8) > 100.0
+    assert _amplification(orc, small, 2 << 8) < 3.0
+
+
 # --------------------------------------------------------------------------
 # shape matching: polar decomposition (Mueller et al. 2005)
 # --------------------------------------------------------------------------
