@@ -148,6 +148,11 @@ typedef struct {
                                      oversubscribes the GPU; 2: all K iterations of a
                                      substep in one launch (the grid is resident at
                                      once, K < 64) */
+    int32_t first_launch_particles; /* particles and bodies of the first iteration launch:
+                                       all of them, unless the bodies of more than 4 waves
+                                       have a second launch (iteration_kernel 1), which
+                                       follows it */
+    int32_t first_launch_bodies;
     size_t workspace_bytes;
 } pbdr_scene_info;
 
@@ -160,7 +165,9 @@ int32_t pbdr_abi_version(void);
  * them is discarded (see Conventions). */
 #define PBDR_COND_CAPACITY 0x1u      /* a neighbour list exceeded nbr_cap            */
 #define PBDR_COND_NONFINITE 0x2u     /* a position or velocity became NaN/Inf        */
-#define PBDR_COND_SORT_WAIT 0x4u     /* the key sort's look-back gave up             */
+#define PBDR_COND_INTERNAL 0x4u      /* an internal consistency check failed (a key
+                                        sort position out of range, a pool scene
+                                        that did not fit its launch shape)          */
 #define PBDR_COND_PARTNER_WAIT 0x8u  /* a one-launch iteration's wait for a contact
                                         partner gave up (its workgroups were not all
                                         resident together)                           */

@@ -25,7 +25,7 @@ DEBUG_XT, DEBUG_KEYS, DEBUG_SORTED, DEBUG_CELL_START, DEBUG_CELL_COUNT = 1, 2, 3
 DEBUG_NBR_COUNT, DEBUG_NBR, DEBUG_DELTA = 6, 7, 8
 MAX_PLANES = 8
 MAX_TIMED_LAUNCHES = 4096
-COND_CAPACITY, COND_NONFINITE, COND_SORT_WAIT, COND_PARTNER_WAIT = 0x1, 0x2, 0x4, 0x8
+COND_CAPACITY, COND_NONFINITE, COND_INTERNAL, COND_PARTNER_WAIT = 0x1, 0x2, 0x4, 0x8
 
 EXPORTED = [
     "pbdr_abi_version", "pbdr_last_error", "pbdr_condition_status", "pbdr_scene_bytes", "pbdr_scene_create",
@@ -89,6 +89,8 @@ class SceneInfo(ctypes.Structure):
         ("iteration_blocks", ctypes.c_int32),
         ("max_body_particles", ctypes.c_int32),
         ("iteration_kernel", ctypes.c_int32),
+        ("first_launch_particles", ctypes.c_int32),
+        ("first_launch_bodies", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 
@@ -291,19 +293,19 @@ class Solver:
         self._bs = np.ascontiguousarray(body_start, dtype=np.int32)
         self._q = None if rest_q is None else _host_f32(rest_q, (3, n))
         self.n, self.n_bodies = n, int(self._bs.shape[0] - 1)
-        nbytes = self._lib.pbdr_scene_bytes(ctypes.byref(params), n, self.n_bodies)
-        if nbytes == 0:
-            raise PbdrError(ERR_INVALID_ARG, last_error())
-        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         desc = SceneDesc(n, self.n_bodies, self._x.ctypes.data, self._v.ctypes.data, self._m.ctypes.data,
                          self._bs.ctypes.data, None if self._q is None else self._q.ctypes.data)
         handle = ctypes.c_void_p()
+        self._accel = None
+        nbytes = self._lib.pbdr_scene_bytes(ctypes.byref(params), n, self.n_bodies)
+        if nbytes == 0:
+            raise PbdrError(ERR_INVALID_ARG, last_error())
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         _check(self._lib.pbdr_scene_create(ctypes.byref(params), ctypes.byref(desc),
                                            self.workspace.data_ptr(), int(nbytes),
                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(handle)))
         self._h = handle
-        self._accel = None
         self.workspace.record_stream(self.stream)   # the allocator waits for this stream's work on free
 
     @classmethod

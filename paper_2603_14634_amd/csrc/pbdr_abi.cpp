@@ -37,7 +37,7 @@ void clear_error() { g_err[0] = 0; }
 bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
 static_assert(pbdr::kErrCapacity == PBDR_COND_CAPACITY && pbdr::kErrNonFinite == PBDR_COND_NONFINITE &&
-                  pbdr::kErrInternal == PBDR_COND_SORT_WAIT && pbdr::kErrWait == PBDR_COND_PARTNER_WAIT,
+                  pbdr::kErrInternal == PBDR_COND_INTERNAL && pbdr::kErrWait == PBDR_COND_PARTNER_WAIT,
               "latched condition bits");
 
 pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap)
@@ -59,7 +59,7 @@ pbdr_status latched_status(uint32_t err, uint32_t max_nbr, int cap)
                     "a one-launch iteration gave up waiting for a contact partner (workgroups not resident together; "
                     "PBDR_FLAG_ITERATION_LAUNCHES avoids the form); the frame was discarded");
     if (err & pbdr::kErrInternal)
-        return fail(PBDR_ERR_DEVICE, "the key sort gave up waiting for a preceding tile; the frame was discarded");
+        return fail(PBDR_ERR_DEVICE, "an internal consistency check failed on the device; the frame was discarded");
     return PBDR_OK;
 }
 
@@ -118,15 +118,13 @@ using pbdr::host::resolve;
 using pbdr::host::g_err;
 
 struct Layout {
-    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1,
-        ibuf0, ibuf1, nbr_n, nbr, hist, tile_ctr, radix_state, cells, body_rot, counters, nbr_stats, wave_body,
+    size_t x, v, x0, mass, body, q, body_start, body_mass, body_mass64, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1,
+        ibuf0, ibuf1, nbr_n, nbr, hist, tile_off, cells, body_rot, counters, nbr_stats, wave_body,
         body_wave0, block_body, tagged, body_mq, body_out, total;
 };
 
 // Passes of the key sort (8-bit digits) for keys of `bits` bits.
 int radix_passes(int bits) { return std::max(1, (bits + pbdr::kRadixBits - 1) / pbdr::kRadixBits); }
-
-size_t radix_tiles(size_t n) { return (n + pbdr::kRadixTile - 1) / pbdr::kRadixTile; }
 
 // Upper bound on the padded wave count of the iteration kernel's body packing
 // (both launches together): each body needs ceil(n_b / 64) <= n_b / 64 + 1
@@ -159,6 +157,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.q = take(12 * N);
     L.body_start = take(4 * (B + 1));
     L.body_mass = take(4 * B);
+    L.body_mass64 = take(8 * B);
     L.dl0 = take(12 * N);
     L.dl1 = take(12 * N);
     L.vel0 = take(12 * N);
@@ -173,8 +172,7 @@ Layout make_layout(int32_t n, int32_t nb, int k, int cap)
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
     L.hist = take(4 * pbdr::kMaxRadixPasses * pbdr::kRadixBins);
-    L.tile_ctr = take(4 * pbdr::kMaxRadixPasses);
-    L.radix_state = take(8 * pbdr::kRadixBins * radix_tiles(N));
+    L.tile_off = take(4 * pbdr::kRadixBins * pbdr::radix_tiles_capacity(N));
     L.cells = take(16 * T);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
@@ -200,6 +198,7 @@ struct pbdr_scene {
     pbdr::StepConsts consts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    int32_t first_particles = 0, first_bodies = 0;   // of the first iteration launch
     hipGraph_t graph = nullptr;          // one frame
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph_n = nullptr;        // kGraphFrames frames
@@ -360,7 +359,8 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.T = (uint32_t)(1ull << s->res.k);
     d.n_sort = n;
     d.radix_passes = radix_passes(s->res.k);
-    d.n_radix_tiles = (uint32_t)radix_tiles((size_t)n);
+    d.radix_items = pbdr::radix_items_for((size_t)n);
+    d.n_radix_tiles = (uint32_t)pbdr::radix_tiles_for((size_t)n);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
     d.x0 = (float*)(w + L.x0);
@@ -369,6 +369,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.q = (const float*)(w + L.q);
     d.body_start = (const int32_t*)(w + L.body_start);
     d.body_mass = (const float*)(w + L.body_mass);
+    d.body_mass64 = (const double*)(w + L.body_mass64);
     d.dl[0] = (float*)(w + L.dl0);
     d.dl[1] = (float*)(w + L.dl1);
     d.vel[0] = (float*)(w + L.vel0);
@@ -385,8 +386,7 @@ void fill_device(pbdr_scene* s, int32_t n, int32_t nb)
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
     d.hist = (uint32_t*)(w + L.hist);
-    d.tile_ctr = (uint32_t*)(w + L.tile_ctr);
-    d.radix_state = (unsigned long long*)(w + L.radix_state);
+    d.tile_off = (uint32_t*)(w + L.tile_off);
     d.cells = (uint4*)(w + L.cells);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
@@ -621,10 +621,24 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
         wave_body.insert(wave_body.end(), wave_body2.begin(), wave_body2.end());
         block_body.insert(block_body.end(), block_body2.begin(), block_body2.end());
     }
+    s->first_particles = n;
+    s->first_bodies = nb;
+    if (s->split) {
+        s->first_particles = 0;
+        s->first_bodies = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t nbp = desc->body_start[b + 1] - desc->body_start[b];
+            if ((nbp + 63) / 64 <= pbdr::kWideBodyWaves) {
+                s->first_particles += nbp;
+                s->first_bodies += 1;
+            }
+        }
+    }
 
     // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
     std::vector<int32_t> body((size_t)n);
     std::vector<float> bmass((size_t)nb), q(3 * (size_t)n), bmq(3 * (size_t)nb);
+    std::vector<double> bmass64((size_t)nb);
     for (int32_t b = 0; b < nb; ++b) {
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i) {
@@ -634,6 +648,7 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
             for (int k = 0; k < 3; ++k) cm[k] += m * (double)desc->x[(size_t)k * n + i];
         }
         bmass[(size_t)b] = (float)M;
+        bmass64[(size_t)b] = M;
         for (int k = 0; k < 3; ++k) cm[k] /= M;
         double mq[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[b]; i < desc->body_start[b + 1]; ++i)
@@ -657,6 +672,7 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
         if (e == hipSuccess) e = h2d(lay.q, q.data(), 12 * (size_t)n);
         if (e == hipSuccess) e = h2d(lay.body_start, desc->body_start, 4 * ((size_t)nb + 1));
         if (e == hipSuccess) e = h2d(lay.body_mass, bmass.data(), 4 * (size_t)nb);
+        if (e == hipSuccess) e = h2d(lay.body_mass64, bmass64.data(), 8 * (size_t)nb);
         if (e == hipSuccess) e = h2d(lay.wave_body, wave_body.data(), 4 * wave_body.size());
         if (e == hipSuccess) e = h2d(lay.body_wave0, body_wave0.data(), 4 * (size_t)nb);
         if (e == hipSuccess) e = h2d(lay.block_body, block_body.data(), 4 * block_body.size());
@@ -953,6 +969,8 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->iteration_blocks = s->dev.n_iter_blocks + (s->split ? s->dev2.n_iter_blocks : 0);
     out->max_body_particles = s->max_body;
     out->iteration_kernel = s->dev.resident_iterate ? 2 : s->dev.dense_iterate;
+    out->first_launch_particles = s->first_particles;
+    out->first_launch_bodies = s->first_bodies;
     out->workspace_bytes = s->lay.total;
     return PBDR_OK;
 }

@@ -42,8 +42,8 @@ int table_bits(int32_t n)
 }
 
 struct BLayout {
-    size_t x, v, x0, mass, body, q, body_start, body_mass, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1, ibuf0,
-        ibuf1, nbr_n, nbr, hist, tile_ctr, radix_state, cells, body_rot, counters, nbr_stats, body_mq, pscene, plan,
+    size_t x, v, x0, mass, body, q, body_start, body_mass, body_mass64, dl0, dl1, vel0, vel1, xt, sxt4, key, kbuf0, kbuf1, ibuf0,
+        ibuf1, nbr_n, nbr, hist, tile_off, cells, body_rot, counters, nbr_stats, body_mq, pscene, plan,
         total;
     size_t plan_bytes, mscene_off, wave_off, block_off, wave0_off;   // within the plan region
     size_t max_waves, max_blocks;
@@ -61,7 +61,6 @@ size_t batch_max_waves(int32_t P, int32_t B, int32_t S)
 BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
 {
     const size_t N = (size_t)P, B = (size_t)BC;
-    const size_t tiles = (N + pbdr::kRadixTile - 1) / pbdr::kRadixTile;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -77,6 +76,7 @@ BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
     L.q = take(12 * N);
     L.body_start = take(4 * (B + 1));
     L.body_mass = take(4 * B);
+    L.body_mass64 = take(8 * B);
     L.dl0 = take(12 * N);
     L.dl1 = take(12 * N);
     L.vel0 = take(12 * N);
@@ -91,8 +91,7 @@ BLayout make_blayout(int32_t P, int32_t BC, int32_t S, size_t K, int cap)
     L.nbr_n = take(4 * N);
     L.nbr = take(4 * N * (size_t)cap);
     L.hist = take(4 * pbdr::kMaxRadixPasses * pbdr::kRadixBins);
-    L.tile_ctr = take(4 * pbdr::kMaxRadixPasses);
-    L.radix_state = take(8 * pbdr::kRadixBins * tiles);
+    L.tile_off = take(4 * pbdr::kRadixBins * pbdr::radix_tiles_capacity(N));
     L.cells = take(16 * K);
     L.body_rot = take(36 * B);
     L.counters = take(sizeof(pbdr::Counters));
@@ -272,7 +271,8 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
     d.n_iter_blocks = (int32_t)nblk;
     d.n_extent = b->parts.high_water(b->P);
     d.n_sort = d.n_extent;
-    d.n_radix_tiles = (uint32_t)(((size_t)d.n_sort + pbdr::kRadixTile - 1) / pbdr::kRadixTile);
+    d.radix_items = pbdr::radix_items_for((size_t)d.n_sort);
+    d.n_radix_tiles = (uint32_t)pbdr::radix_tiles_for((size_t)d.n_sort);
     d.n_active = 0;
     for (int32_t s = 0; s < b->S; ++s)
         if (b->slots[(size_t)s].used && active[(size_t)s]) d.n_active += b->slots[(size_t)s].n;
@@ -346,7 +346,8 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.T = (uint32_t)K;
     d.n_sort = max_particles;
     d.radix_passes = 1;
-    d.n_radix_tiles = (uint32_t)(((size_t)max_particles + pbdr::kRadixTile - 1) / pbdr::kRadixTile);
+    d.radix_items = pbdr::radix_items_for((size_t)max_particles);
+    d.n_radix_tiles = (uint32_t)pbdr::radix_tiles_for((size_t)max_particles);
     d.x = (float*)(w + L.x);
     d.v = (float*)(w + L.v);
     d.x0 = (float*)(w + L.x0);
@@ -355,6 +356,7 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.q = (const float*)(w + L.q);
     d.body_start = (const int32_t*)(w + L.body_start);
     d.body_mass = (const float*)(w + L.body_mass);
+    d.body_mass64 = (const double*)(w + L.body_mass64);
     d.wave_body = (const int32_t*)(w + L.plan + L.wave_off);
     d.body_wave0 = (const int32_t*)(w + L.plan + L.wave0_off);
     d.block_body = (const int32_t*)(w + L.plan + L.block_off);
@@ -375,8 +377,7 @@ pbdr_status pbdr_batch_create(const pbdr_params* params, int32_t max_scenes, int
     d.nbr_n = (uint32_t*)(w + L.nbr_n);
     d.nbr = (uint32_t*)(w + L.nbr);
     d.hist = (uint32_t*)(w + L.hist);
-    d.tile_ctr = (uint32_t*)(w + L.tile_ctr);
-    d.radix_state = (unsigned long long*)(w + L.radix_state);
+    d.tile_off = (uint32_t*)(w + L.tile_off);
     d.cells = (uint4*)(w + L.cells);
     d.body_rot = (float*)(w + L.body_rot);
     d.counters = (pbdr::Counters*)(w + L.counters);
@@ -454,6 +455,7 @@ pbdr_status pbdr_batch_add(pbdr_batch* b, const pbdr_pool_scene_desc* desc, int3
     // rest pose (FP64): body mass, centre, q = x - c (Sec. III-C, shape matching)
     std::vector<int32_t> body((size_t)n), pscene((size_t)n, slot), bstart((size_t)nb + 1);
     std::vector<float> bmass((size_t)nb + 1, 0.0f), q(3 * (size_t)n), bmq(3 * ((size_t)nb + 1), 0.0f);
+    std::vector<double> bmass64((size_t)nb + 1, 0.0);
     for (int32_t bb = 0; bb < nb; ++bb) {
         double M = 0.0, cm[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[bb]; i < desc->body_start[bb + 1]; ++i) {
@@ -462,6 +464,7 @@ pbdr_status pbdr_batch_add(pbdr_batch* b, const pbdr_pool_scene_desc* desc, int3
             for (int k = 0; k < 3; ++k) cm[k] += (double)desc->mass[i] * (double)desc->x[(size_t)k * n + i];
         }
         bmass[(size_t)bb] = (float)M;
+        bmass64[(size_t)bb] = M;
         for (int k = 0; k < 3; ++k) cm[k] /= M;
         double mq[3] = {0.0, 0.0, 0.0};
         for (int32_t i = desc->body_start[bb]; i < desc->body_start[bb + 1]; ++i)
@@ -490,6 +493,7 @@ pbdr_status pbdr_batch_add(pbdr_batch* b, const pbdr_pool_scene_desc* desc, int3
     if (e == hipSuccess) e = h2d(L.pscene + 4 * (size_t)p0, pscene.data(), 4 * (size_t)n);
     if (e == hipSuccess) e = h2d(L.body_start + 4 * (size_t)b0, bstart.data(), 4 * ((size_t)nb + 1));
     if (e == hipSuccess) e = h2d(L.body_mass + 4 * (size_t)b0, bmass.data(), 4 * ((size_t)nb + 1));
+    if (e == hipSuccess) e = h2d(L.body_mass64 + 8 * (size_t)b0, bmass64.data(), 8 * ((size_t)nb + 1));
     if (e == hipSuccess) e = h2d(L.body_mq + 12 * (size_t)b0, bmq.data(), 12 * ((size_t)nb + 1));
     if (e == hipSuccess) e = hipStreamSynchronize(b->upload);      // host arrays are freed on return
     if (e == hipSuccess) e = hipEventRecord(b->uploaded, b->upload);

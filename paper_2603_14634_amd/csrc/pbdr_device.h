@@ -16,13 +16,27 @@ constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
 constexpr int kWideBodyWaves = 4;
 constexpr int kRadixBits = 8;                   // key sort: digit width
 constexpr int kRadixBins = 1 << kRadixBits;
-constexpr int kRadixItems = 16;                  // keys per thread of a sort pass
-constexpr int kRadixTile = kBlock * kRadixItems; // keys per workgroup of a sort pass
 constexpr int kMaxRadixPasses = 4;               // keys of up to 32 bits
 constexpr int kHistChunk = 16384;                // keys per workgroup of the digit histogram
-constexpr int kHistMaxBlocks = 128;
+// A sort tile is kBlock threads of `items` keys each: 16 from kRadixLargeFrom
+// keys on (longer runs of one digit per tile, so longer runs of writes), 4
+// below (more tiles to fill the GPU).
+constexpr size_t kRadixLargeFrom = size_t(1) << 20;
+inline uint32_t radix_items_for(size_t n) { return n >= kRadixLargeFrom ? 16u : 4u; }
+inline size_t radix_tiles_for(size_t n)
+{
+    const size_t t = (size_t)kBlock * radix_items_for(n);
+    return (n + t - 1) / t;
+}
+// the most tiles of any key count up to n
+inline size_t radix_tiles_capacity(size_t n)
+{
+    const size_t a = radix_tiles_for(n), b = radix_tiles_for(n < kRadixLargeFrom ? n : kRadixLargeFrom - 1);
+    return a > b ? a : b;
+}
 
-// kErrInternal: the key sort's look-back (or a pool launch shape) gave up;
+// kErrInternal: an internal consistency check failed (a sort position out of
+// range, a pool scene that does not fit its launch shape);
 // kErrWait: a one-launch iteration's wait for a contact partner gave up.
 enum : uint32_t { kErrCapacity = 1u, kErrNonFinite = 2u, kErrInternal = 4u, kErrWait = 8u };
 // Any of these discards the frame in which it is raised: the committed state
@@ -90,7 +104,8 @@ struct Scene {
                               //     (multi-scene mode; T is also the key of particles not stepped)
     int32_t n_sort;           // particles taking part in the key sort (0 .. n_sort - 1)
     int32_t radix_passes;     // ceil(key bits / 8)
-    uint32_t n_radix_tiles;   // ceil(n_sort / kRadixTile)
+    uint32_t radix_items;     // keys per thread of a sort tile: radix_items_for(n_sort)
+    uint32_t n_radix_tiles;   // radix_tiles_for(n_sort)
     float* x;                 // [3][N] committed positions: the state after the last clean frame
     float* v;                 // [3][N] committed velocities
     float* x0;                // [3][N] X_init of the current substep (the working state)
@@ -99,6 +114,7 @@ struct Scene {
     const float* q;           // [3][N] rest offsets
     const int32_t* body_start;// [B+1]
     const float* body_mass;   // [B]
+    const double* body_mass64;// [B] the same in FP64 (sum of the FP32 particle masses)
     const int32_t* wave_body; // [n_iter_blocks * waves_per_block] body of each wave, -1 = idle
     const int32_t* body_wave0;// [B] first (global) wave of each body
     const int32_t* block_body;// [2 * n_iter_blocks] first body and body count of each workgroup
@@ -119,8 +135,8 @@ struct Scene {
     uint32_t* nbr_n;          // [N] neighbour-list length
     uint32_t* nbr;            // [cap][N] neighbour ids, slot-major, ascending
     uint32_t* hist;           // [kMaxRadixPasses][kRadixBins] digit counts of the substep's keys
-    uint32_t* tile_ctr;       // [kMaxRadixPasses] sort passes: next tile to take
-    unsigned long long* radix_state;   // [n_radix_tiles][kRadixBins] look-back: tag | status | count
+    uint32_t* tile_off;       // [kRadixBins][n_radix_tiles] sort pass: a tile's count of each
+                              //     digit, then the digit's first output position in the tile
     uint4* cells;             // [T] per key, written for occupied keys only: first sorted slot,
                               //     end slot, body signature (the one body of all its particles,
                               //     or -2 mixed), and the substep (epoch) that wrote it; an entry
@@ -162,8 +178,8 @@ int resident_iterate_capacity(int waves_per_block);
 hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                               hipStream_t stream);
 
-// As enqueue_iterations, launch `k` bound to the events t0[k] (begin of its
-// first kernel) and t1[k] (end of its last).
+// As enqueue_iterations, launch `k` with its first kernel bound to the events
+// t0[k] (begin) and t1[k] (end); a second launch (s2) follows it untimed.
 hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1);
 
@@ -174,9 +190,8 @@ hipError_t enqueue_zero(void* p, size_t bytes, hipStream_t stream);
 // Clears the latched counters.
 hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream);
 
-// Clears the key table, the digit counts, the sort passes' tile counters and
-// look-back words, and the substep epoch (once, at creation; `cells` holds
-// `table` entries).
+// Clears the key table, the digit counts and the substep epoch (once, at
+// creation; `cells` holds `table` entries).
 hipError_t enqueue_init_tables(const Scene& s, size_t table, hipStream_t stream);
 
 }  // namespace pbdr

@@ -9,12 +9,14 @@
 //                  first folds the previous substep's result into the state
 //                  (x += dX, v = V)
 //   radix_hist     counts of every 8-bit digit of the keys
-//   radix_pass x P stable LSD radix sort of (key, id), one sweep per digit
-//                  (local ranking by ballots, decoupled look-back over tiles)
+//   radix x P      stable LSD radix sort of (key, id), one digit per pass:
+//                  tile counts, a scan per digit over the tiles, then each
+//                  tile ranks its keys by ballots and writes them in place;
+//                  the last pass also writes sorted copies of the FP32
+//                  predicted positions and body ids
 //   cells          per-key table from the sorted keys, written for occupied
 //                  keys only and tagged with the substep: first and end slot,
-//                  body signature (the key's single body, or "mixed"); sorted
-//                  copies of the FP32 predicted positions and body ids
+//                  body signature (the key's single body, or "mixed")
 //   neighbours     walks particles in key order: 27-cell stencil (skipping
 //                  keys that hold only the particle's own body), FP32
 //                  predicate, ascending lists
@@ -75,11 +77,10 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 {
 #pragma clang fp contract(off)
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    // the key sort of this substep starts from zero digit counts and tile counters
+    // the key sort of this substep starts from zero digit counts
     if (i < kMaxRadixPasses * kRadixBins) s.hist[i] = 0u;
-    if (i < kMaxRadixPasses) s.tile_ctr[i] = 0u;
-    // a new substep: fresh tags for the sort's look-back, the key table and
-    // one-launch iterations (no other thread of this launch reads the epoch)
+    // a new substep: fresh tags for the key table and one-launch iterations
+    // (no other thread of this launch reads the epoch)
     if (i == 0) s.counters->epoch += 1u;
     if (i >= s.n_sort) return;
     const size_t n = (size_t)s.n;
@@ -124,10 +125,11 @@ __global__ void __launch_bounds__(kBlock) k_predict_keys(Scene s, StepConsts c, 
 }
 
 // ---------------------------------------------------------------------------
-// stable LSD radix sort of (key, id), 8-bit digits, one launch per digit
-// (each pass is a single sweep: tiles rank their keys locally and find the
-// counts of the same digit in all earlier tiles by decoupled look-back; the
-// global digit offsets come from one histogram of all digits, taken first)
+// stable LSD radix sort of (key, id), 8-bit digits.  One histogram of all
+// digits of all passes first; then per pass three launches: each tile counts
+// its digits, one scan per digit over the tiles turns the counts into output
+// positions, and each tile ranks its keys and writes them there.  No
+// workgroup waits for another.
 // ---------------------------------------------------------------------------
 
 // Inclusive prefix sum over the lanes of a wave: shifts by 1, 2, 4, 8 within
@@ -159,7 +161,6 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp)
     return before + incl - v;
 }
 
-constexpr uint32_t kSpinLimit = 1u << 22;   // bounded wait: flag an error, never hang
 
 // Digit counts of every pass over all keys: each workgroup counts a chunk of
 // kHistChunk keys in LDS (16 consecutive keys per thread, equal digits of a
@@ -204,54 +205,114 @@ __global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
         if (h[t]) atomicAdd(&s.hist[t], h[t]);
 }
 
-// look-back word: tag (30 bits) | status (2 bits) | count (32 bits); the tag
-// names the substep and the pass, so words of earlier passes read as "not yet
-// published"
-constexpr uint32_t kStAggregate = 1u, kStInclusive = 2u;
-__device__ inline unsigned long long radix_word(uint32_t tag, uint32_t status, uint32_t v)
+// Pass p, step 1: the digit counts of one tile (kBlock threads of ITEMS
+// keys; thread t counts keys ITEMS t .. ITEMS t + ITEMS - 1 of the tile, equal
+// digits of a run once) to tile_off[d][tile].
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_radix_count(Scene s, int p, const uint32_t* kin)
 {
-    return ((unsigned long long)tag << 34) | ((unsigned long long)status << 32) | v;
+    static_assert(kBlock == kRadixBins, "one thread per digit");
+    __shared__ uint32_t h[kRadixBins];
+    const int tid = threadIdx.x;
+    h[tid] = 0u;
+    __syncthreads();
+    const size_t n = (size_t)s.n_sort;
+    const uint32_t tile = blockIdx.x;
+    const size_t i0 = (size_t)tile * (kBlock * ITEMS) + (size_t)tid * ITEMS;
+    uint32_t k[ITEMS];
+    if (i0 + ITEMS <= n) {
+        const uint4* src = reinterpret_cast<const uint4*>(kin + i0);
+#pragma unroll
+        for (int u = 0; u < ITEMS / 4; ++u) {
+            const uint4 q = src[u];
+            k[4 * u] = q.x; k[4 * u + 1] = q.y; k[4 * u + 2] = q.z; k[4 * u + 3] = q.w;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < ITEMS; ++u) k[u] = i0 + u < n ? kin[i0 + u] : 0u;
+    }
+    const int cnt = i0 >= n ? 0 : (int)min((size_t)ITEMS, n - i0);
+    const uint32_t sh = kRadixBits * p;
+    uint32_t run_d = 0, run_n = 0;
+#pragma unroll
+    for (int u = 0; u < ITEMS; ++u) {
+        if (u >= cnt) break;
+        const uint32_t d = (k[u] >> sh) & (kRadixBins - 1);
+        if (run_n && d != run_d) {
+            atomicAdd(&h[run_d], run_n);
+            run_n = 0;
+        }
+        run_d = d;
+        ++run_n;
+    }
+    if (run_n) atomicAdd(&h[run_d], run_n);
+    __syncthreads();
+    s.tile_off[(size_t)tid * s.n_radix_tiles + tile] = h[tid];
 }
 
-// One pass over digit p (bits 8p .. 8p + 7): keys kin (ids iin, or the key's
-// index when iin is null) -> kout, iout, stable.  A workgroup takes the next
-// tile of kRadixTile keys (tiles are taken in order, so every tile it waits
-// on belongs to a workgroup that is already running).  Item t of lane l of
-// wave w is key w * 64 * kRadixItems + 64 t + l of the tile: each wave ranks
-// its items in that order by matching equal digits across lanes with ballots,
-// so ranks follow key order within the tile.
-// The last pass also writes each particle's predicted position and body to
-// its sorted slot (sxt4).
-__global__ void __launch_bounds__(kBlock) k_radix_pass(Scene s, int p, const uint32_t* kin, const uint32_t* iin,
-                                                       uint32_t* kout, uint32_t* iout)
+// Pass p, step 2: workgroup d turns digit d's tile counts into the first
+// output position of the digit in each tile: the count of smaller digits over
+// all keys plus the counts of d in earlier tiles.
+__global__ void __launch_bounds__(kBlock) k_radix_scan(Scene s, int p)
 {
-    __shared__ uint32_t s_key[kRadixTile], s_id[kRadixTile];
+    __shared__ uint32_t tmp[kWaves];
+    __shared__ uint32_t s_base, s_total;
+    const int tid = threadIdx.x;
+    const uint32_t d = blockIdx.x;
+    const uint32_t below = block_exclusive_scan(s.hist[p * kRadixBins + tid], tmp);
+    if ((uint32_t)tid == d) s_base = below;
+    __syncthreads();
+    uint32_t carry = s_base;
+    const uint32_t T = s.n_radix_tiles;
+    uint32_t* row = s.tile_off + (size_t)d * T;
+    for (uint32_t t0 = 0; t0 < T; t0 += kBlock) {
+        const uint32_t t = t0 + (uint32_t)tid;
+        const uint32_t c = t < T ? row[t] : 0u;
+        const uint32_t ex = block_exclusive_scan(c, tmp);
+        if (t < T) row[t] = carry + ex;
+        if (tid == kBlock - 1) s_total = ex + c;
+        __syncthreads();
+        carry += s_total;
+        __syncthreads();
+    }
+}
+
+// Pass p, step 3: keys kin (ids iin, or the key's index when iin is null) ->
+// kout, iout, stable.  Item t of lane l of wave w is key w * 64 ITEMS + 64 t
+// + l of the tile: each wave ranks its items in that order by matching equal
+// digits across lanes with ballots, so ranks follow key order within the
+// tile.  The tile's keys go through LDS in (digit, key order), so the slots
+// of one digit are written to consecutive positions.  The last pass also
+// writes each particle's predicted position and body to its sorted slot (sxt4).
+template <int ITEMS>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(Scene s, int p, const uint32_t* kin, const uint32_t* iin,
+                                                          uint32_t* kout, uint32_t* iout)
+{
+    constexpr int TILE = kBlock * ITEMS;
+    __shared__ uint32_t s_key[TILE], s_id[TILE];
     __shared__ uint32_t wcnt[kWaves][kRadixBins];   // per-wave digit counters, then wave offsets
     __shared__ uint32_t lstart[kRadixBins];         // first LDS slot of each digit in the tile
     __shared__ int32_t gshift[kRadixBins];          // output position - LDS slot, per digit
     __shared__ uint32_t tmp[kWaves];
-    __shared__ uint32_t s_tile;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_tile = atomicAdd(&s.tile_ctr[p], 1u);
     for (int t = tid; t < kWaves * kRadixBins; t += kBlock) (&wcnt[0][0])[t] = 0u;
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint32_t n = (uint32_t)s.n_sort;
     const uint32_t sh = kRadixBits * p;
-    const uint32_t tag = ((s.counters->epoch << 2) | (uint32_t)p) & 0x3fffffffu;
-    const uint32_t first = tile * kRadixTile + (uint32_t)wave * 64u * kRadixItems + (uint32_t)lane;
+    const uint32_t first = tile * TILE + (uint32_t)wave * 64u * ITEMS + (uint32_t)lane;
 
-    uint32_t k[kRadixItems], id[kRadixItems], r[kRadixItems];
+    uint32_t k[ITEMS], id[ITEMS], r[ITEMS];
 #pragma unroll
-    for (int t = 0; t < kRadixItems; ++t) {
+    for (int t = 0; t < ITEMS; ++t) {
         const uint32_t e = first + 64u * t;
         k[t] = e < n ? kin[e] : 0u;
         id[t] = e < n ? (iin ? iin[e] : e) : 0u;
     }
     // rank within the wave, item by item (each lane's items in key order)
 #pragma unroll
-    for (int t = 0; t < kRadixItems; ++t) {
+    for (int t = 0; t < ITEMS; ++t) {
         const bool valid = first + 64u * t < n;
         const uint32_t d = (k[t] >> sh) & (kRadixBins - 1);
         unsigned long long peers = __ballot(valid);
@@ -277,61 +338,12 @@ __global__ void __launch_bounds__(kBlock) k_radix_pass(Scene s, int p, const uin
         wcnt[w][d] = total;
         total += c;
     }
-    unsigned long long* st = s.radix_state + (size_t)tile * kRadixBins;
-    if (tile > 0)
-        __hip_atomic_store(&st[d], radix_word(tag, kStAggregate, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    else
-        __hip_atomic_store(&st[d], radix_word(tag, kStInclusive, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t local = block_exclusive_scan(total, tmp);          // first slot of digit d in the tile
-    const uint32_t global = block_exclusive_scan(s.hist[p * kRadixBins + d], tmp);   // first position of digit d
-    // count of digit d in all earlier tiles (decoupled look-back): the words
-    // of kLookBack predecessors are loaded together; aggregates are summed
-    // until an inclusive count, and a word not yet published is polled again
-    uint32_t before = 0;
-    if (tile > 0) {
-        constexpr int kLookBack = 8;
-        int t = (int)tile - 1;             // newest predecessor not yet summed
-        uint32_t spins = 0;
-        bool done = false;
-        while (!done) {
-            unsigned long long w[kLookBack];
-#pragma unroll
-            for (int j = 0; j < kLookBack; ++j)
-                w[j] = t - j >= 0 ? __hip_atomic_load(&s.radix_state[(size_t)(t - j) * kRadixBins + d],
-                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                  : 0ull;
-            bool stalled = false;
-#pragma unroll
-            for (int j = 0; j < kLookBack; ++j) {
-                if (done || stalled || t < 0) continue;
-                const uint32_t status = (uint32_t)(w[j] >> 32) & 3u;
-                if ((uint32_t)(w[j] >> 34) != tag || status == 0u) {   // not published yet
-                    stalled = true;
-                    continue;
-                }
-                before += (uint32_t)w[j];
-                done = status == kStInclusive;
-                --t;
-            }
-            if (done || t < 0) break;         // (tile 0 is always inclusive: t < 0 only after an error)
-            if (stalled) {
-                if (++spins > kSpinLimit) {
-                    atomicOr(&s.counters->err, kErrInternal);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-        }
-        __hip_atomic_store(&st[d], radix_word(tag, kStInclusive, before + total), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-    }
     lstart[d] = local;
-    gshift[d] = (int32_t)(global + before) - (int32_t)local;
+    gshift[d] = (int32_t)s.tile_off[(size_t)d * s.n_radix_tiles + tile] - (int32_t)local;
     __syncthreads();
-    // keys to LDS in (digit, key order), then out: the slots of one digit go
-    // to consecutive positions
 #pragma unroll
-    for (int t = 0; t < kRadixItems; ++t) {
+    for (int t = 0; t < ITEMS; ++t) {
         if (first + 64u * t >= n) continue;
         const uint32_t dd = (k[t] >> sh) & (kRadixBins - 1);
         const uint32_t slot = lstart[dd] + wcnt[wave][dd] + r[t];
@@ -339,13 +351,16 @@ __global__ void __launch_bounds__(kBlock) k_radix_pass(Scene s, int p, const uin
         s_id[slot] = id[t];
     }
     __syncthreads();
-    const uint32_t in_tile = min((uint32_t)kRadixTile, n - tile * kRadixTile);
+    const uint32_t in_tile = min((uint32_t)TILE, n - tile * TILE);
     const bool last = p == s.radix_passes - 1;
     const size_t ns = (size_t)s.n;
     for (uint32_t j = (uint32_t)tid; j < in_tile; j += kBlock) {
         const uint32_t kk = s_key[j], ii = s_id[j];
         const uint32_t pos = (uint32_t)((int32_t)j + gshift[(kk >> sh) & (kRadixBins - 1)]);
-        if (pos >= n) continue;        // (a look-back that gave up leaves the positions unusable)
+        if (pos >= n) {                // (counts and keys disagree: cannot happen)
+            atomicOr(&s.counters->err, kErrInternal);
+            continue;
+        }
         kout[pos] = kk;
         iout[pos] = ii;
         if (last && kk < s.T)          // stepped particles (in multi-scene mode the others take key T)
@@ -379,23 +394,43 @@ __global__ void __launch_bounds__(kBlock) k_cells(Scene s)
 // neighbour lists, one thread per particle in key order
 // ---------------------------------------------------------------------------
 
-// At most 128 VGPRs (4 waves per SIMD, no spill): the 27 key ranges and 9
-// candidates in flight otherwise take ~156 and leave 3 waves per SIMD.
-template <bool MULTI>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4, 4)))
-k_neighbours(Scene s, StepConsts c)
+// One candidate of particle i (list `lst`, slot k at lst[k * stride]): same
+// body (which also excludes i) and the FP32 predicate, then an insertion that
+// keeps the `cap` smallest ids in ascending order.  Lists are short (most
+// particles have none), so they are kept in place in the output array.
+__device__ __forceinline__ void nbr_consider(uint32_t* lst, size_t stride, int cap, uint32_t& count, int32_t pb,
+                                             float px, float py, float pz, float r2, const float4 o, uint32_t id)
 {
-    extern __shared__ uint32_t lst[];          // [cap][kBlock], slot-major
+    if (__float_as_int(o.w) == pb) return;
+    if (!within(px, py, pz, o.x, o.y, o.z, r2)) return;
+    const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
+    ++count;
+    if (m == cap && id > lst[(size_t)(cap - 1) * stride]) return;
+    int pos = (m == cap) ? cap - 1 : m;
+    while (pos > 0 && lst[(size_t)(pos - 1) * stride] > id) {
+        lst[(size_t)pos * stride] = lst[(size_t)(pos - 1) * stride];
+        --pos;
+    }
+    lst[(size_t)pos * stride] = id;
+}
+
+// One thread per particle in key order.  The 27 keys are walked one z-layer
+// of 9 at a time: the layer's table entries are loaded together, then the
+// first candidate of each of its keys, so the loads of a layer are in flight
+// together; further candidates of a key (rare with >= 8 keys per particle)
+// follow.
+template <bool MULTI>
+__global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
+{
     const int blk = xcd_block();
     const int j = blk * kBlock + threadIdx.x;  // position in key order
     // multi-scene mode: the stepped particles come first in key order
     bool live = j < (MULTI ? s.n_active : s.n);
     const size_t n = (size_t)s.n;
     const int cap = c.nbr_cap;
-    const int tid = threadIdx.x;
     const uint32_t epoch = s.counters->epoch;
     uint32_t count = 0;
-    uint32_t i = live ? s.sorted[j] : 0u;
+    const uint32_t i = live ? s.sorted[j] : 0u;
     uint32_t key_base = 0u, key_mask = c.key_mask;
     if (MULTI && live) {                // multi-scene mode: the particle's own scene table
         const int32_t sc = s.pscene[i];
@@ -412,55 +447,33 @@ k_neighbours(Scene s, StepConsts c)
         const uint32_t cx = cell_axis(px, c.origin[0], c.inv_cell);
         const uint32_t cy = cell_axis(py, c.origin[1], c.inv_cell);
         const uint32_t cz = cell_axis(pz, c.origin[2], c.inv_cell);
-        uint32_t lo[27], hi[27];
-#pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const uint32_t k = key_base + morton(cx + (uint32_t)(t % 3 - 1), cy + (uint32_t)((t / 3) % 3 - 1),
-                                                 cz + (uint32_t)(t / 9 - 1), key_mask);
-            const uint4 e = s.cells[k];
-            lo[t] = e.x;
-            // an entry of an earlier substep is an empty key, and a key
-            // holding only this particle's body has no candidates
-            hi[t] = (e.w != epoch || (int32_t)e.z == pb) ? e.x : e.y;
-        }
-        auto consider = [&](uint32_t q, const float4 o) {
-            if (__float_as_int(o.w) == pb) return;            // same body (also excludes i)
-            if (!within(px, py, pz, o.x, o.y, o.z, c.search_r2)) return;
-            const uint32_t id = s.sorted[q];
-            // insert keeping the `cap` smallest ids in ascending order
-            const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
-            ++count;
-            if (m == cap && id > lst[(cap - 1) * kBlock + tid]) return;
-            int pos = (m == cap) ? cap - 1 : m;
-            while (pos > 0 && lst[(pos - 1) * kBlock + tid] > id) {
-                lst[pos * kBlock + tid] = lst[(pos - 1) * kBlock + tid];
-                --pos;
-            }
-            lst[pos * kBlock + tid] = id;
-        };
-        // one z-layer of 9 keys at a time: the first candidate of every key is
-        // loaded before any is examined, so the loads are in flight together;
-        // further candidates of a key (rare with >= 8 keys per particle) follow
+        uint32_t* lst = s.nbr + i;
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
+            uint32_t lo[9], hi[9];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) {
+                const uint32_t k = key_base + morton(cx + (uint32_t)(u % 3 - 1), cy + (uint32_t)(u / 3 - 1),
+                                                     cz + (uint32_t)(dz - 1), key_mask);
+                const uint4 e = s.cells[k];
+                lo[u] = e.x;
+                // an entry of an earlier substep is an empty key, and a key
+                // holding only this particle's body has no candidates
+                hi[u] = (e.w != epoch || (int32_t)e.z == pb) ? e.x : e.y;
+            }
             float4 o[9];
 #pragma unroll
-            for (int u = 0; u < 9; ++u) {
-                const int t = 9 * dz + u;
-                o[u] = hi[t] > lo[t] ? s.sxt4[lo[t]] : me;
-            }
+            for (int u = 0; u < 9; ++u) o[u] = hi[u] > lo[u] ? s.sxt4[lo[u]] : me;
 #pragma unroll
             for (int u = 0; u < 9; ++u) {
-                const int t = 9 * dz + u;
-                if (hi[t] > lo[t]) {
-                    consider(lo[t], o[u]);
-                    for (uint32_t q = lo[t] + 1; q < hi[t]; ++q) consider(q, s.sxt4[q]);
+                if (hi[u] > lo[u]) {
+                    nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, o[u], s.sorted[lo[u]]);
+                    for (uint32_t q = lo[u] + 1; q < hi[u]; ++q)
+                        nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, s.sxt4[q], s.sorted[q]);
                 }
             }
         }
         s.nbr_n[i] = count;
-        const uint32_t stored = count < (uint32_t)cap ? count : (uint32_t)cap;
-        for (uint32_t k = 0; k < stored; ++k) s.nbr[k * n + i] = lst[k * kBlock + tid];
     }
     // statistics: this workgroup's own slot (no contention); the capacity
     // error is latched only when it happens
@@ -576,6 +589,32 @@ __device__ inline void sum_wave_partials(const float4* red, int w0, int nw, floa
     }
 }
 
+// The rotation of shape matching (FP32, orthogonal to about 1e-7) made
+// orthogonal to FP64 precision by one Newton step X <- (X + X^-T) / 2 (the
+// iteration that converges to the orthogonal polar factor, quadratically);
+// applied in FP64, so that it moves a body's goal rigidly: a rotation that is
+// orthogonal only to 1e-7 would stretch a decimetre-sized body's goal shape
+// by 1e-8 m.
+// Each cofactor is formed where it is used (few FP64 values live at once).
+__device__ __forceinline__ double cofactor64(const float* X, int a, int b, int c, int d)
+{
+    return (double)X[a] * (double)X[b] - (double)X[c] * (double)X[d];
+}
+
+__device__ inline void orthonormalise64(const float* X, double* Rd)
+{
+    // cofactor k of X (row-major): the (1, 1) minor pattern of cof3
+    constexpr int kIdx[9][4] = {{4, 8, 5, 7}, {5, 6, 3, 8}, {3, 7, 4, 6}, {2, 7, 1, 8}, {0, 8, 2, 6},
+                                {1, 6, 0, 7}, {1, 5, 2, 4}, {2, 3, 0, 5}, {0, 4, 1, 3}};
+    double det = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) det += (double)X[k] * cofactor64(X, kIdx[k][0], kIdx[k][1], kIdx[k][2], kIdx[k][3]);
+    const double id = 1.0 / det;
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        Rd[k] = 0.5 * ((double)X[k] + cofactor64(X, kIdx[k][0], kIdx[k][1], kIdx[k][2], kIdx[k][3]) * id);
+}
+
 // Shape matching's goal offset D = R q - (y - c) of one particle, y its
 // position relative to the body's anchor (x0 - anchor + del).  The terms are
 // body-sized (up to decimetres) while D is of the order of the contact
@@ -584,39 +623,45 @@ __device__ inline void sum_wave_partials(const float4* red, int w0, int nw, floa
 // rounded.  In FP32 every particle's goal would carry a rounding of ~ulp(0.1 m)
 // = 7e-9 m that no rigid motion absorbs, and resting contacts amplify such
 // particle-level differences over the iterations.
-__device__ __forceinline__ void goal_offset(const float* R, const float* q, const float* x0, const float* anchor,
-                                            const float* del, const float* c, float* D)
+// Rc: the body's R (row-major) and centre relative to the anchor, in FP64.
+__device__ __forceinline__ void goal_offset(const double* Rc, const float* q, const float* x0, const float* anchor,
+                                            const float* del, float* D)
 {
     for (int a = 0; a < 3; ++a) {
-        const double rq = (double)R[3 * a] * (double)q[0] + (double)R[3 * a + 1] * (double)q[1] +
-                          (double)R[3 * a + 2] * (double)q[2];
+        const double rq = Rc[3 * a] * (double)q[0] + Rc[3 * a + 1] * (double)q[1] + Rc[3 * a + 2] * (double)q[2];
         const double ya = ((double)x0[a] - (double)anchor[a]) + (double)del[a];
-        D[a] = (float)(rq - (ya - (double)c[a]));
+        D[a] = (float)(rq - (ya - Rc[9 + a]));
     }
 }
 
 // This wave's partial sums of shape matching, sum m y and sum m y q^T (12
 // values), to LDS: in FP32 (red32), or in FP64 (red64) when `wide`.
+// y: the particle's position relative to the body's anchor, (x0 - anchor) +
+// del, in FP32; a wide body's sums take it in FP64 (exact there).
 template <bool WIDE_OK>
-__device__ __forceinline__ void sm_wave_partials(bool wide, float m, const float* y, const float* q, int wave,
-                                                 int lane, float4* red32, double* red64)
+__device__ __forceinline__ void sm_wave_partials(bool wide, float m, const float* x0, const float* anchor,
+                                                 const float* del, const float* q, int wave, int lane, float4* red32,
+                                                 double* red64)
 {
     if (WIDE_OK && wide) {
         // three groups of four sums (fewer FP64 values live at once); after
         // the reduction row j of group g holds sum 4 g + j
         const double md = m;
+        auto y = [&](int j) { return ((double)x0[j] - (double)anchor[j]) + (double)del[j]; };
 #pragma unroll
         for (int g = 0; g < 3; ++g) {
             double S[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int k = 4 * g + u;          // 0-2: m y, 3-11: m y_a q_b
-                S[u] = k < 3 ? md * (double)y[k] : md * (double)y[(k - 3) / 3] * (double)q[(k - 3) % 3];
+                S[u] = k < 3 ? md * y(k) : md * y((k - 3) / 3) * (double)q[(k - 3) % 3];
             }
             wave_sums_by_row64<4>(S);
             if ((lane & 15) == 15) red64[wave * 12 + 4 * g + (lane >> 4)] = S[0];
         }
     } else {
+        float y[3];
+        for (int j = 0; j < 3; ++j) y[j] = (x0[j] - anchor[j]) + del[j];
         float S[12];
         for (int j = 0; j < 3; ++j) S[j] = m * y[j];
         for (int a = 0; a < 3; ++a)
@@ -631,29 +676,38 @@ __device__ __forceinline__ void sm_wave_partials(bool wide, float m, const float
 
 // Centre (relative to the body's anchor) and covariance A = sum m (y - c) q^T
 // of a body from its waves' partials, on the body's lane:
-// A = sum m y q^T - c (sum m q)^T.
+// A = sum m y q^T - c (sum m q)^T.  M: the body mass in FP32; M64 the same in
+// FP64 (a wide body's centre divides by it).
 template <bool WIDE_OK, int UNROLL>
-__device__ __forceinline__ void sm_body_sums(int w0, int nw, float M, const float* mq3, const float4* red32,
-                                             const double* red64, float* cc, float* A)
+__device__ __forceinline__ void sm_body_sums(int w0, int nw, float M, double M64, const float* mq3,
+                                             const float4* red32, const double* red64, float* cc, double* cd,
+                                             float* A)
 {
     if (WIDE_OK && nw > kWideBodyWaves) {
-        double T[12];
-        for (int j = 0; j < 12; ++j) T[j] = 0.0;
+        // centre, then the covariance row by row (few FP64 values live at once)
+        const double im = 1.0 / M64;
+        double c[3] = {0.0, 0.0, 0.0};
         for (int w = 0; w < nw; ++w)
-            for (int j = 0; j < 12; ++j) T[j] += red64[(w0 + w) * 12 + j];
-        const double im = 1.0 / (double)M;
-        double c[3];
+            for (int j = 0; j < 3; ++j) c[j] += red64[(w0 + w) * 12 + j];
         for (int j = 0; j < 3; ++j) {
-            c[j] = T[j] * im;
+            c[j] *= im;
             cc[j] = (float)c[j];
+            cd[j] = c[j];
         }
-        for (int a = 0; a < 3; ++a)
-            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = (float)(T[3 + 3 * a + k2] - c[a] * (double)mq3[k2]);
+        for (int a = 0; a < 3; ++a) {
+            double t[3] = {0.0, 0.0, 0.0};
+            for (int w = 0; w < nw; ++w)
+                for (int k2 = 0; k2 < 3; ++k2) t[k2] += red64[(w0 + w) * 12 + 3 + 3 * a + k2];
+            for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = (float)(t[k2] - c[a] * (double)mq3[k2]);
+        }
     } else {
         float T[12];
         sum_wave_partials<3, UNROLL>(red32, w0, nw, T);
         const float im = frcp(M);
-        for (int j = 0; j < 3; ++j) cc[j] = T[j] * im;
+        for (int j = 0; j < 3; ++j) {
+            cc[j] = T[j] * im;
+            cd[j] = (double)cc[j];
+        }
         for (int a = 0; a < 3; ++a)
             for (int k2 = 0; k2 < 3; ++k2) A[3 * a + k2] = T[3 + 3 * a + k2] - cc[a] * mq3[k2];
     }
@@ -675,6 +729,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
     __shared__ float body_sm[kMaxWaves * 12];    // per body of the workgroup: R (9), centre (3)
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
+    __shared__ double body_rd[kMaxWaves * 12];   // R and centre in FP64 (goal offsets)
 
     // the wave index as a wave-uniform (scalar) value: the per-wave table and
     // body entries below then come through scalar loads
@@ -707,10 +762,12 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     const int bb = blk_b0 + (body_lane ? lane : 0);
     int bl_w0 = 0, bl_nw = 0;
     float bl_M = 1.0f, Rprev[9], mq3[3];
+    double bl_M64 = 1.0;
     if (body_lane) {
         bl_w0 = s.body_wave0[bb] - blk * s.waves_per_block;
         bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
         bl_M = s.body_mass[bb];
+        if (WIDE_OK) bl_M64 = s.body_mass64[bb];
         for (int j = 0; j < 3; ++j) mq3[j] = s.body_mq[3 * (size_t)bb + j];
         if (it > 0)
             for (int j = 0; j < 9; ++j) Rprev[j] = s.body_rot[9 * (size_t)bb + j];
@@ -760,31 +817,28 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 
     // shape matching on X_i: centre and covariance in one reduction,
     // A = sum m (x - c) q^T = sum m y q^T - c (sum m q)^T, y = x - anchor
-    float y[3];
-    y[0] = (x0[0] - ax) + del[0];
-    y[1] = (x0[1] - ay) + del[1];
-    y[2] = (x0[2] - az) + del[2];
-    sm_wave_partials<WIDE_OK>(wide, m, y, q, wave, lane, red_sm, red_sm64);
+    sm_wave_partials<WIDE_OK>(wide, m, x0, anc, del, q, wave, lane, red_sm, red_sm64);
     __syncthreads();
     if (body_lane) {            // one lane per body: centre, covariance, rotation
         float cc[3], A[9], Rb[9];
-        sm_body_sums<WIDE_OK, SM_UNROLL>(bl_w0, bl_nw, bl_M, mq3, red_sm, red_sm64, cc, A);
+        sm_body_sums<WIDE_OK, SM_UNROLL>(bl_w0, bl_nw, bl_M, bl_M64, mq3, red_sm, red_sm64, cc,
+                                         &body_rd[lane * 12 + 9], A);
         if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
         for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
         for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+        orthonormalise64(Rb, &body_rd[lane * 12]);
         if (s.body_rot)
             for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rb[j];
     }
     __syncthreads();
-    float R[9], cyv[3];
-    for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+    float cyv[3];
     for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
 
     // goal offsets D = R q - (x - c) and the momentum sums, in the frame
     // centred on c_i: z_b = r + C (before shape matching), z_a = z_b + D
     float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
-    for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
-    if (act) goal_offset(R, q, x0, anc, del, cyv, Dd);
+    for (int j = 0; j < 3; ++j) r[j] = ((x0[j] - anc[j]) + del[j]) - cyv[j];
+    if (act) goal_offset(&body_rd[lb * 12], q, x0, anc, del, Dd);
     {
         float S[NMOM];
         float zb[3], za[3], vb[3], t[3];
@@ -946,6 +1000,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
     __shared__ float body_sm[kMaxWaves * 12];
     __shared__ float body_mom[kMaxWaves * 9];
+    __shared__ double body_rd[kMaxWaves * 12];
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int blk = xcd_block();
@@ -971,31 +1026,49 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
     // per-body constants in LDS rather than in registers of every lane; the
     // previous iteration's rotation is read from the body's LDS slot
     __shared__ float body_mq_s[kMaxWaves * 3];
+    __shared__ int body_waves_s[kMaxWaves * 2];   // first wave in the workgroup, wave count
+    __shared__ float body_M_s[kMaxWaves];
+    __shared__ double body_M64_s[kMaxWaves];
     const bool body_lane = wave == 0 && lane < blk_nb;
-    const int bb = blk_b0 + (body_lane ? lane : 0);
-    int bl_w0 = 0, bl_nw = 0;
-    float bl_M = 1.0f;
     if (body_lane) {
-        bl_w0 = s.body_wave0[bb] - blk * W;
-        bl_nw = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
-        bl_M = s.body_mass[bb];
+        const int bb = blk_b0 + lane;
+        body_waves_s[2 * lane] = s.body_wave0[bb] - blk * W;
+        body_waves_s[2 * lane + 1] = (s.body_start[bb + 1] - s.body_start[bb] + 63) >> 6;
+        body_M_s[lane] = s.body_mass[bb];
+        body_M64_s[lane] = s.body_mass64[bb];
         for (int j = 0; j < 3; ++j) body_mq_s[lane * 3 + j] = s.body_mq[3 * (size_t)bb + j];
     }
 
-    // X_0 - X_init and V_0 from the integration step; the rest is constant
-    float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
-    float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f;
+    // X_0 - X_init and V_0 from the integration step stay in registers; the
+    // constants X_init, q and m of the lane's particle wait in LDS and are
+    // read in each phase that uses them, so that they do not hold registers
+    // through the per-body algebra
+    __shared__ float p_const[7][64 * kMaxWaves];
+    const int tid = threadIdx.x;
+    float del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
     uint32_t ni = 0u;
-    if (act) {
-        for (int j = 0; j < 3; ++j) {
-            x0[j] = s.x0[j * n + i];
-            del[j] = s.dl[0][j * n + i];
-            V[j] = s.vel[0][j * n + i];
-            q[j] = s.q[j * n + i];
+    {
+        float cv[7] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (act) {
+            for (int j = 0; j < 3; ++j) {
+                cv[j] = s.x0[j * n + i];
+                del[j] = s.dl[0][j * n + i];
+                V[j] = s.vel[0][j * n + i];
+                cv[3 + j] = s.q[j * n + i];
+            }
+            cv[6] = s.mass[i];
+            ni = s.nbr_n[i];
         }
-        m = s.mass[i];
-        ni = s.nbr_n[i];
+        for (int j = 0; j < 7; ++j) p_const[j][tid] = cv[j];
     }
+    float x0[3], q[3], m;
+    auto load_consts = [&]() {
+        for (int j = 0; j < 3; ++j) {
+            x0[j] = p_const[j][tid];
+            q[j] = p_const[3 + j][tid];
+        }
+        m = p_const[6][tid];
+    };
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
     const float mu = c.mu;
     const uint32_t epoch = s.counters->epoch;
@@ -1007,9 +1080,11 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
 
     for (int it = 0; it < K; ++it) {
         const unsigned long long* tg = s.tagged + (size_t)(it & 1) * 3 * n;   // partners' X_it, tagged
-        // the first PE partners' words are loaded before the shape-matching
-        // phase, which does not need them, and checked after it
-        constexpr int PE = 3;
+        load_consts();
+        sm_wave_partials<true>(wide, m, x0, anc, del, q, wave, lane, red_sm, red_sm64);
+        // the first PE partners' words are loaded during the per-body phase,
+        // which does not need them, and checked after it
+        constexpr int PE = 1;
         const uint32_t want = iter_tag(epoch, it);
         uint32_t je[PE];
         unsigned long long we[PE][3];
@@ -1024,33 +1099,29 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                     for (int j = 0; j < 3; ++j)
                         we[g][j] = __hip_atomic_load(&tg[j * n + je[g]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-
-        float y[3];
-        y[0] = (x0[0] - ax) + del[0];
-        y[1] = (x0[1] - ay) + del[1];
-        y[2] = (x0[2] - az) + del[2];
-        sm_wave_partials<true>(wide, m, y, q, wave, lane, red_sm, red_sm64);
         __syncthreads();
         if (body_lane) {
             float cc[3], A[9], Rb[9];
             float mq3[3], Rprev[9];
             for (int j = 0; j < 3; ++j) mq3[j] = body_mq_s[lane * 3 + j];
-            sm_body_sums<true, 4>(bl_w0, bl_nw, bl_M, mq3, red_sm, red_sm64, cc, A);
+            sm_body_sums<true, 4>(body_waves_s[2 * lane], body_waves_s[2 * lane + 1], body_M_s[lane],
+                                  body_M64_s[lane], mq3, red_sm, red_sm64, cc, &body_rd[lane * 12 + 9], A);
             for (int j = 0; j < 9; ++j) Rprev[j] = body_sm[lane * 12 + j];   // (it > 0) the last iteration's
             if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
             for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
             for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+            orthonormalise64(Rb, &body_rd[lane * 12]);
         }
         __syncthreads();
         // goal offsets (shape matching), formed before the contacts so that
-        // the rotation need not stay in registers through them
+        // the body's rotation and centre need not stay in registers through them
+        load_consts();
         float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
         {
-            float R[9], cyv[3];
-            for (int j = 0; j < 9; ++j) R[j] = body_sm[lb * 12 + j];
+            float cyv[3];
             for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
-            for (int j = 0; j < 3; ++j) r[j] = y[j] - cyv[j];
-            if (act) goal_offset(R, q, x0, anc, del, cyv, Dd);
+            for (int j = 0; j < 3; ++j) r[j] = ((x0[j] - anc[j]) + del[j]) - cyv[j];
+            if (act) goal_offset(&body_rd[lb * 12], q, x0, anc, del, Dd);
         }
 
         // contacts from X_i (planes, then partners in list order)
@@ -1135,12 +1206,15 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         }
 
 
+        // r + C + D and C + D: all the velocity update needs of this phase
+        float za[3], step[3];
         {
             float S[NMOM];
-            float zb[3], za[3], vb[3], t[3];
+            float zb[3], vb[3], t[3];
             for (int j = 0; j < 3; ++j) {
                 zb[j] = r[j] + Cd[j];
                 za[j] = zb[j] + Dd[j];
+                step[j] = Cd[j] + Dd[j];
                 vb[j] = V[j] + Cd[j] * c.inv_h;
                 S[j] = m * Cd[j];
                 S[3 + j] = m * Dd[j];
@@ -1166,8 +1240,8 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         __syncthreads();
         if (body_lane) {
             float T[NMOM];
-            sum_wave_partials<NMOM / 4, 4>(red_mom, bl_w0, bl_nw, T);
-            const float Mb = bl_M, im = frcp(Mb);
+            sum_wave_partials<NMOM / 4, 4>(red_mom, body_waves_s[2 * lane], body_waves_s[2 * lane + 1], T);
+            const float Mb = body_M_s[lane], im = frcp(Mb);
             float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
             for (int j = 0; j < 3; ++j) {
                 cb[j] = T[j] * im;
@@ -1204,17 +1278,17 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
                 w[j] = body_mom[lb * 9 + 3 + j];
                 ca[j] = body_mom[lb * 9 + 6 + j];
             }
-            for (int j = 0; j < 3; ++j) ra[j] = r[j] + Cd[j] + Dd[j] - ca[j];
+            for (int j = 0; j < 3; ++j) ra[j] = za[j] - ca[j];
             cross(w, ra, wr);
             for (int j = 0; j < 3; ++j) {
-                const float step = Cd[j] + Dd[j];
                 const float dvi = dv[j] - wr[j];
-                const float dnew = (del[j] + step) + c.h * dvi;
+                const float dnew = (del[j] + step[j]) + c.h * dvi;
                 if (c.flags & kFlagStdVelocity) {
-                    const float xw = x0[j] + dnew;
-                    V[j] = (xw - x0[j]) * c.inv_h;
+                    const float x0j = p_const[j][tid];
+                    const float xw = x0j + dnew;
+                    V[j] = (xw - x0j) * c.inv_h;
                 } else {
-                    V[j] = (V[j] + step * c.inv_h) + dvi;
+                    V[j] = (V[j] + step[j] * c.inv_h) + dvi;
                 }
                 del[j] = dnew;
             }
@@ -1237,7 +1311,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         }
     }
     if (body_lane && s.body_rot)
-        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = body_sm[lane * 12 + j];
+        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)(blk_b0 + lane) + j] = body_sm[lane * 12 + j];
 }
 
 // End of a frame, in two launches so that a frame is committed whole or not
@@ -1307,9 +1381,7 @@ __global__ void __launch_bounds__(kBlock) k_init_tables(Scene s, size_t table)
 {
     const size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x;
     if (i < table) s.cells[i] = make_uint4(0u, 0u, 0u, 0u);
-    if (i < (size_t)s.n_radix_tiles * kRadixBins) s.radix_state[i] = 0ull;
     if (i < (size_t)(kMaxRadixPasses * kRadixBins)) s.hist[i] = 0u;
-    if (i < (size_t)kMaxRadixPasses) s.tile_ctr[i] = 0u;
     if (i == 0) s.counters->epoch = 0u;
 }
 
@@ -1346,6 +1418,20 @@ void launch_iterate_timed(const Scene& s, const StepConsts& c, int src, int it, 
         hipExtLaunchKernelGGL((k_iterate<false, false>), grid, block, 0, stream, t0, t1, 0, s, c, src, it);
 }
 
+// One Jacobi iteration: s's launch, then s2's (if any).  t0 / t1 (or null):
+// events bound to the begin and end of s's launch.  (Run side by side on two
+// streams, the two launches took longer: the second one's 16-wave
+// workgroups wait for CUs that the first one's fill.)
+void launch_pair(const Scene& s, const Scene* s2, const StepConsts& c, int src, int it, hipStream_t stream,
+                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
+{
+    if (t0 || t1)
+        launch_iterate_timed(s, c, src, it, stream, t0, t1);
+    else
+        launch_iterate(s, c, src, it, stream);
+    if (s2) launch_iterate(*s2, c, src, it, stream);
+}
+
 }  // namespace
 
 hipError_t enqueue_zero(void* p, size_t bytes, hipStream_t stream)
@@ -1367,7 +1453,6 @@ hipError_t enqueue_clear_counters(const Scene& s, hipStream_t stream)
 hipError_t enqueue_init_tables(const Scene& s, size_t table, hipStream_t stream)
 {
     size_t items = table;
-    items = items > (size_t)s.n_radix_tiles * kRadixBins ? items : (size_t)s.n_radix_tiles * kRadixBins;
     items = items > (size_t)(kMaxRadixPasses * kRadixBins) ? items : (size_t)(kMaxRadixPasses * kRadixBins);
     hipLaunchKernelGGL(k_init_tables, dim3(blocks_for(items)), dim3(kBlock), 0, stream, s, table);
     return hipGetLastError();
@@ -1387,8 +1472,7 @@ hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts&
     }
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        launch_iterate(s, c, src, it, stream);
-        if (s2) launch_iterate(*s2, c, src, it, stream);
+        launch_pair(s, s2, c, src, it, stream);
         src ^= 1;
     }
     return hipGetLastError();
@@ -1408,12 +1492,7 @@ hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepC
     }
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        if (s2) {       // one iteration = both launches: begin of the first, end of the second
-            launch_iterate_timed(s, c, src, it, stream, t0[it], nullptr);
-            launch_iterate_timed(*s2, c, src, it, stream, nullptr, t1[it]);
-        } else {
-            launch_iterate_timed(s, c, src, it, stream, t0[it], t1[it]);
-        }
+        launch_pair(s, s2, c, src, it, stream, t0[it], t1[it]);
         src ^= 1;
     }
     return hipGetLastError();
@@ -1445,7 +1524,6 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
     const size_t pred_items = (size_t)(kMaxRadixPasses * kRadixBins);
     const unsigned nb_pred = blocks_for(extent > pred_items ? extent : pred_items);
     const unsigned nb_hist = (unsigned)(((size_t)s.n_sort + kHistChunk - 1) / kHistChunk);
-    const size_t nbr_lds = (size_t)c.nbr_cap * kBlock * sizeof(uint32_t);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
     for (int sub = 0; sub < count; ++sub) {
         if (multi)
@@ -1458,15 +1536,25 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
         for (int p = 0; p < s.radix_passes; ++p) {
             const uint32_t* kin = p == 0 ? s.key : s.kbuf[(p - 1) & 1];
             const uint32_t* iin = p == 0 ? nullptr : s.ibuf[(p - 1) & 1];
-            hipLaunchKernelGGL(k_radix_pass, dim3(s.n_radix_tiles), dim3(kBlock), 0, stream, s, p, kin, iin,
-                               s.kbuf[p & 1], s.ibuf[p & 1]);
+            const dim3 tiles(s.n_radix_tiles);
+            if (s.radix_items == 16) {
+                hipLaunchKernelGGL(k_radix_count<16>, tiles, dim3(kBlock), 0, stream, s, p, kin);
+                hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins), dim3(kBlock), 0, stream, s, p);
+                hipLaunchKernelGGL(k_radix_scatter<16>, tiles, dim3(kBlock), 0, stream, s, p, kin, iin,
+                                   s.kbuf[p & 1], s.ibuf[p & 1]);
+            } else {
+                hipLaunchKernelGGL(k_radix_count<4>, tiles, dim3(kBlock), 0, stream, s, p, kin);
+                hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins), dim3(kBlock), 0, stream, s, p);
+                hipLaunchKernelGGL(k_radix_scatter<4>, tiles, dim3(kBlock), 0, stream, s, p, kin, iin,
+                                   s.kbuf[p & 1], s.ibuf[p & 1]);
+            }
         }
         if (multi) {
             hipLaunchKernelGGL(k_cells<true>, dim3(nb_nbr), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb_nbr), dim3(kBlock), nbr_lds, stream, s, c);
+            hipLaunchKernelGGL(k_neighbours<true>, dim3(nb_nbr), dim3(kBlock), 0, stream, s, c);
         } else {
             hipLaunchKernelGGL(k_cells<false>, dim3(nb), dim3(kBlock), 0, stream, s);
-            hipLaunchKernelGGL(k_neighbours<false>, dim3(nb), dim3(kBlock), nbr_lds, stream, s, c);
+            hipLaunchKernelGGL(k_neighbours<false>, dim3(nb), dim3(kBlock), 0, stream, s, c);
         }
         if (!multi && s.resident_iterate) {
             hipLaunchKernelGGL(k_iterate_resident, dim3(s.n_iter_blocks), dim3(64 * s.waves_per_block), 0, stream, s,
@@ -1475,8 +1563,7 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
         }
         int src = 0;
         for (int it = 0; it < iterations; ++it) {
-            launch_iterate(s, c, src, it, stream);
-            if (s2) launch_iterate(*s2, c, src, it, stream);
+            launch_pair(s, s2, c, src, it, stream);
             src ^= 1;
         }
     }

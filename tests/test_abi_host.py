@@ -65,12 +65,12 @@ def test_latched_conditions_map_to_statuses():
     assert B.condition_status(0) == B.OK
     assert B.condition_status(B.COND_CAPACITY) == B.ERR_CAPACITY
     assert B.condition_status(B.COND_NONFINITE) == B.ERR_NONFINITE
-    assert B.condition_status(B.COND_SORT_WAIT) == B.ERR_DEVICE
-    assert "sort" in B.last_error()
+    assert B.condition_status(B.COND_INTERNAL) == B.ERR_DEVICE
+    assert "internal" in B.last_error()
     assert B.condition_status(B.COND_PARTNER_WAIT) == B.ERR_DEVICE
     assert "partner" in B.last_error()
     assert B.condition_status(B.COND_CAPACITY | B.COND_PARTNER_WAIT) == B.ERR_CAPACITY
-    assert B.condition_status(B.COND_NONFINITE | B.COND_PARTNER_WAIT | B.COND_SORT_WAIT) == B.ERR_NONFINITE
+    assert B.condition_status(B.COND_NONFINITE | B.COND_PARTNER_WAIT | B.COND_INTERNAL) == B.ERR_NONFINITE
     assert B.condition_status(0xF) == B.ERR_CAPACITY
     assert "last frame" in B.last_error()
 

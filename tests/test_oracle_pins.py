@@ -289,13 +289,15 @@ def test_symmetric_averaging_conserves_total_momentum(orc):
         np.testing.assert_allclose(P1, P0, rtol=0, atol=1e-12 * np.abs(P0).max())
 
 
-def _amplification(orc, sc, flags, seeds=3, eps=1e-9):
+def _amplification(orc, sc, flags, seeds=3, eps=1e-9, rest=None, threads=1):
     """Largest change of the reference's substep per unit of a random velocity
     perturbation of eps (a position perturbation of h eps), applied only where
     it leaves the FP32 velocity unchanged, so the FP32 predicted positions and
-    the neighbour lists stay the same."""
-    p = orc.params_for(sc, flags=flags)
-    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    the neighbour lists stay the same.  rest: the rest pose (default: the
+    scene's positions)."""
+    p = orc.params_for(sc, flags=flags, threads=threads)
+    if rest is None:
+        rest = orc.Body(sc.x, sc.mass, sc.body_start)
     x, v = sc.x.astype(np.float64), sc.v.astype(np.float64)
     x1, _, _ = orc.substep(p, rest, x, v)
     h = sc.dt_frame / sc.substeps
@@ -325,6 +327,29 @@ def test_plain_pair_sum_is_ill_conditioned_on_face_contacts(orc):
     assert _amplification(orc, big, 0) < 3.0
     assert _amplification(orc, big, 2 << 8) > 100.0
     assert _amplification(orc, small, 2 << 8) < 3.0
+
+
+def test_packed_pile_is_ill_conditioned_until_its_overlaps_resolve(orc):
+    """A pile packed with overlapping faces (300 bodies of the dense-pile
+    recipe, 30k particles): in its first substep the Jacobi iteration
+    amplifies a perturbation of 1e-12 m about a hundred times, while the
+    overlaps are pushed apart; three frames later, resting in contact at the
+    same density, it contracts again (amplification of a few).  (This is why
+    the GPU's settled-density gate settles a pile of randomly oriented bodies
+    instead of packing one face to face.)"""
+    import os
+
+    from paper_2603_14634_amd import scenes
+
+    threads = max(1, min(8, os.cpu_count() or 1))
+    sc = scenes.dense_pile(0, n_bodies=300, gap_frac=-0.1, packed=True)
+    rest = orc.Body(sc.x, sc.mass, sc.body_start)
+    assert _amplification(orc, sc, 0, seeds=2, threads=threads) > 30.0
+    p = orc.params_for(sc, threads=threads)
+    x, v, _ = orc.substep(p, rest, sc.x.astype(np.float64), sc.v.astype(np.float64), n_substeps=3 * sc.substeps)
+    later = sc.copy()
+    later.x, later.v = x.astype(np.float32), v.astype(np.float32)
+    assert _amplification(orc, later, 0, seeds=2, rest=rest, threads=threads) < 10.0
 
 
 # --------------------------------------------------------------------------
