@@ -306,6 +306,34 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* scene, pbdr_scene_info* out);
 /* Frees the host handle (and any captured graph).  The workspace is untouched. */
 void pbdr_scene_destroy(pbdr_scene* scene);
 
+/* Size of the static device workspace of pbdr_scene_create_static. */
+#define PBDR_STATIC_WORKSPACE_BYTES (128u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): a scene as
+ * pbdr_scene_create makes it, placed in the library's own static device
+ * workspace of PBDR_STATIC_WORKSPACE_BYTES bytes instead of a caller
+ * workspace.  Every device the library runs on holds that workspace until the
+ * process ends.
+ *  - A scene whose pbdr_scene_bytes exceeds PBDR_STATIC_WORKSPACE_BYTES is
+ *    rejected with PBDR_ERR_WORKSPACE before any device work.
+ *  - Nothing is allocated: no hipMalloc or hipFree, no allocating library
+ *    routine, and the scene's host record is one of the library's own (one
+ *    per device).  The scene steps by direct kernel launches (pbdr_scene_step
+ *    never captures a graph for it, which would allocate).
+ *  - One static scene per device at a time: a later call on the same device
+ *    waits for the earlier static scene's work and then replaces it in the
+ *    same workspace and host record, so the earlier handle refers to the new
+ *    scene.  Calls that overlap on one device race.
+ *  - The inputs (desc, host memory) are as for pbdr_scene_create; every state
+ *    in the workspace that must start cleared is cleared by this call.  Every
+ *    other pbdr_scene_* call works on the returned handle as on any scene;
+ *    pbdr_scene_destroy releases it.
+ */
+pbdr_status pbdr_scene_create_static(const pbdr_params* params, const pbdr_scene_desc* desc,
+                                     void* hip_stream, pbdr_scene** out);
+
 /* ------------------------------------------------------------------------
  * Scene pools: many independent small scenes stepped together.
  *

@@ -32,7 +32,7 @@ EXPORTED = [
     "pbdr_scene_set_accel", "pbdr_scene_set_stream", "pbdr_scene_step", "pbdr_scene_substep", "pbdr_scene_set_state",
     "pbdr_scene_read_state", "pbdr_scene_read_bodies", "pbdr_scene_read_rest", "pbdr_scene_check", "pbdr_scene_neighbour_stats",
     "pbdr_scene_read_debug", "pbdr_scene_info_get", "pbdr_scene_launch_iterations",
-    "pbdr_scene_time_iterations", "pbdr_scene_destroy",
+    "pbdr_scene_time_iterations", "pbdr_scene_destroy", "pbdr_scene_create_static",
     "pbdr_pool_bytes", "pbdr_pool_create", "pbdr_pool_add", "pbdr_pool_remove", "pbdr_pool_step",
     "pbdr_pool_step_slots", "pbdr_pool_substep", "pbdr_pool_read_state", "pbdr_pool_read_debug",
     "pbdr_pool_check", "pbdr_pool_get_tuning", "pbdr_pool_set_tuning", "pbdr_pool_autotune",
@@ -278,7 +278,9 @@ class Solver:
     """One scene resident in GPU memory (a torch uint8 workspace)."""
 
     def __init__(self, params: Params, x, v, mass, body_start, rest_q=None, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, static_workspace: bool = False):
+        """static_workspace: place the scene in the library's static device
+        workspace (pbdr_scene_create_static) instead of a torch allocation."""
         import torch
 
         self._lib = load_library()
@@ -298,6 +300,17 @@ class Solver:
                          self._bs.ctypes.data, None if self._q is None else self._q.ctypes.data)
         handle = ctypes.c_void_p()
         self._accel = None
+        if static_workspace:
+            fn = self._lib.pbdr_scene_create_static
+            fn.restype = ctypes.c_int32
+            fn.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(SceneDesc), ctypes.c_void_p,
+                           ctypes.POINTER(ctypes.c_void_p)]
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(fn(ctypes.byref(params), ctypes.byref(desc), ctypes.c_void_p(self.stream.cuda_stream),
+                          ctypes.byref(handle)))
+            self._h = handle
+            return
         nbytes = self._lib.pbdr_scene_bytes(ctypes.byref(params), n, self.n_bodies)
         if nbytes == 0:
             raise PbdrError(ERR_INVALID_ARG, last_error())
@@ -324,7 +337,8 @@ class Solver:
         """Moves later work to ``stream`` (a torch stream) after the current one drains."""
         _check(self._lib.pbdr_scene_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
         self.stream = stream
-        self.workspace.record_stream(stream)
+        if self.workspace is not None:
+            self.workspace.record_stream(stream)
 
     def set_accel(self, accel):
         """accel: torch float32 device tensor [3, N] (kept alive here) or None."""

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbdr.so")
 SOURCES = ["pbdr_kernels.hip", "pbdr_pool_kernels.hip", "pbdr_state.hip", "pbdr_abi.cpp", "pbdr_pool.cpp",
-           "pbdr_batch.cpp"]
+           "pbdr_batch.cpp", "pbdr_static.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # Contraction only within one source expression keeps the rounding of the same
