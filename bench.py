@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--iteration-launches", action="store_true",
                     help="one launch per solver iteration even where the substep could run them as one")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="direct kernel launches instead of replaying a captured graph (counter runs)")
     ap.add_argument("--cpu-budget-s", type=float, default=15.0)
     ap.add_argument("--cpu-threads", type=int, default=16, help="OpenMP threads of the FP64 reference baseline")
     ap.add_argument("--iter-launches", type=int, default=200, help="launches timed for the roofline")
@@ -429,8 +431,8 @@ def main():
     sc = scenes.WORKLOADS[args.workload](args.seed)
     print("[bench] workload %s: %d particles, %d bodies" % (sc.name, sc.n, sc.n_bodies), file=sys.stderr,
           flush=True)
-    solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits,
-                                 flags=B.FLAG_ITERATION_LAUNCHES if args.iteration_launches else 0)
+    flags = (B.FLAG_ITERATION_LAUNCHES if args.iteration_launches else 0) | (B.FLAG_NO_GRAPH if args.no_graph else 0)
+    solver = B.Solver.from_scene(sc, hash_bits=args.hash_bits, flags=flags)
     stream = solver.stream
     settle = args.settle if args.settle is not None else SETTLE_FRAMES.get(args.workload, 0)
     if settle:

@@ -583,14 +583,15 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
     s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
     s->dev.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
     s->split = false;
-    if (s->dev.dense_iterate && W > 4) {
+    constexpr int kDenseWaves = 4;      // workgroup of the split packing's first launch
+    if (s->dev.dense_iterate && W > kDenseWaves) {
         wave_body.clear();
-        pack(4, 0, 4, wave_body, block_body, body_wave0);
-        pack(W, 5, W, wave_body2, block_body2, body_wave0);     // bodies of more than 4 waves
+        pack(kDenseWaves, 0, kDenseWaves, wave_body, block_body, body_wave0);
+        pack(W, kDenseWaves + 1, W, wave_body2, block_body2, body_wave0);     // the larger bodies
         s->split = !wave_body2.empty();
-        s->dev.waves_per_block = 4;
-        s->dev.n_iter_blocks = (int32_t)(wave_body.size() / 4);
-        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * 4 ? 1 : 0;
+        s->dev.waves_per_block = kDenseWaves;
+        s->dev.n_iter_blocks = (int32_t)(wave_body.size() / kDenseWaves);
+        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / kDenseWaves) ? 1 : 0;
         s->dev.wide_bodies = 0;
     }
     const size_t waves_total = wave_body.size() + wave_body2.size();
@@ -615,9 +616,10 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
         s->dev2.block_body = s->dev.block_body + block_body.size();
         s->dev2.waves_per_block = W;
         s->dev2.n_iter_blocks = (int32_t)(wave_body2.size() / (size_t)W);
-        // bodies of more than 4 waves: the kernel with FP64 shape-matching sums
+        // bodies of more than 4 waves: the register-rich kernel, with FP64
+        // shape-matching sums if some body needs them
         s->dev2.dense_iterate = 0;
-        s->dev2.wide_bodies = 1;
+        s->dev2.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
         wave_body.insert(wave_body.end(), wave_body2.begin(), wave_body2.end());
         block_body.insert(block_body.end(), block_body2.begin(), block_body2.end());
     }
@@ -628,7 +630,7 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
         s->first_bodies = 0;
         for (int32_t b = 0; b < nb; ++b) {
             const int32_t nbp = desc->body_start[b + 1] - desc->body_start[b];
-            if ((nbp + 63) / 64 <= pbdr::kWideBodyWaves) {
+            if ((nbp + 63) / 64 <= kDenseWaves) {
                 s->first_particles += nbp;
                 s->first_bodies += 1;
             }

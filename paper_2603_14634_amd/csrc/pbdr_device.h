@@ -11,9 +11,11 @@ constexpr int kMaxWaves = 16;    // iteration kernel: waves per workgroup (bodie
 constexpr int kMaxPlanes = 8;
 constexpr int kMaxCap = 64;      // largest supported neighbour-list capacity
 // Shape matching's sums over a body of many particles lose precision in FP32
-// (ten or more rounding levels over about 1000 terms of one sign): a body of
-// more than kWideBodyWaves waves (64 particles each) accumulates them in FP64.
-constexpr int kWideBodyWaves = 4;
+// (ten rounding levels over about 1000 terms of one sign): a body of more
+// than kWideBodyWaves waves (64 particles each) accumulates them in FP64.
+// Bodies of up to 512 particles keep FP32 sums, which meet the per-substep
+// tolerance in every mode.
+constexpr int kWideBodyWaves = 8;
 constexpr int kRadixBits = 8;                   // key sort: digit width
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kMaxRadixPasses = 4;               // keys of up to 32 bits
@@ -122,7 +124,7 @@ struct Scene {
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
     int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (80-VGPR kernel)
-    int32_t wide_bodies;      // 1: some body of the iteration launch spans more than 4 waves
+    int32_t wide_bodies;      // 1: some body of the iteration launch spans more than kWideBodyWaves waves
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
     float* xt;                // [3][N] FP32 predicted positions
