@@ -164,12 +164,19 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp)
 
 // Digit counts of every pass over all keys: each workgroup counts a chunk of
 // kHistChunk keys in LDS (16 consecutive keys per thread, equal digits of a
-// run counted once) and adds its non-zero counts to the global table.
+// run counted once) and adds its non-zero counts to the global table.  It
+// also writes the first pass's per-tile counts (the tiles of a chunk, in the
+// keys' input order), so that pass needs no counting launch of its own.
 __global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
 {
+    constexpr int kMaxChunkTiles = kHistChunk / (kBlock * 4);
     __shared__ uint32_t h[kMaxRadixPasses * kRadixBins];
+    __shared__ uint32_t ht[kMaxChunkTiles * kRadixBins];
     const int P = s.radix_passes;
+    const int tile_keys = kBlock * (int)s.radix_items;
+    const int chunk_tiles = kHistChunk / tile_keys;
     for (int t = threadIdx.x; t < P * kRadixBins; t += 1024) h[t] = 0u;
+    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += 1024) ht[t] = 0u;
     __syncthreads();
     const size_t n = (size_t)s.n_sort;
     const size_t i0 = (size_t)blockIdx.x * kHistChunk + 16 * (size_t)threadIdx.x;
@@ -186,6 +193,8 @@ __global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
         for (int u = 0; u < 16; ++u) k[u] = i0 + u < n ? s.key[i0 + u] : 0u;
     }
     const int cnt = i0 >= n ? 0 : (int)min((size_t)16, n - i0);
+    // the thread's 16 keys lie in one tile (16 divides the tile size)
+    uint32_t* hp0 = &ht[(16 * (int)threadIdx.x / tile_keys) * kRadixBins];
     for (int p = 0; p < P; ++p) {
         const uint32_t sh = kRadixBits * p;
         uint32_t run_d = 0, run_n = 0;
@@ -193,16 +202,26 @@ __global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
             const uint32_t d = (k[u] >> sh) & (kRadixBins - 1);
             if (run_n && d != run_d) {
                 atomicAdd(&h[p * kRadixBins + run_d], run_n);
+                if (p == 0) atomicAdd(&hp0[run_d], run_n);
                 run_n = 0;
             }
             run_d = d;
             ++run_n;
         }
-        if (run_n) atomicAdd(&h[p * kRadixBins + run_d], run_n);
+        if (run_n) {
+            atomicAdd(&h[p * kRadixBins + run_d], run_n);
+            if (p == 0) atomicAdd(&hp0[run_d], run_n);
+        }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < P * kRadixBins; t += 1024)
         if (h[t]) atomicAdd(&s.hist[t], h[t]);
+    // the chunk's tiles: [digit][tile] like k_radix_count
+    const uint32_t T = s.n_radix_tiles;
+    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += 1024) {
+        const uint32_t tile = (uint32_t)blockIdx.x * (uint32_t)chunk_tiles + (uint32_t)(t / kRadixBins);
+        if (tile < T) s.tile_off[(size_t)(t % kRadixBins) * T + tile] = ht[t];
+    }
 }
 
 // Pass p, step 1: the digit counts of one tile (kBlock threads of ITEMS
@@ -399,10 +418,12 @@ __global__ void __launch_bounds__(kBlock) k_cells(Scene s)
 // keeps the `cap` smallest ids in ascending order.  Lists are short (most
 // particles have none), so they are kept in place in the output array.
 __device__ __forceinline__ void nbr_consider(uint32_t* lst, size_t stride, int cap, uint32_t& count, int32_t pb,
-                                             float px, float py, float pz, float r2, const float4 o, uint32_t id)
+                                             float px, float py, float pz, float r2, const float4 o,
+                                             const uint32_t* sorted, uint32_t q)
 {
     if (__float_as_int(o.w) == pb) return;
     if (!within(px, py, pz, o.x, o.y, o.z, r2)) return;
+    const uint32_t id = sorted[q];        // (loaded only for a neighbour)
     const int m = (int)(count < (uint32_t)cap ? count : (uint32_t)cap);
     ++count;
     if (m == cap && id > lst[(size_t)(cap - 1) * stride]) return;
@@ -448,13 +469,20 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
         const uint32_t cy = cell_axis(py, c.origin[1], c.inv_cell);
         const uint32_t cz = cell_axis(pz, c.origin[2], c.inv_cell);
         uint32_t* lst = s.nbr + i;
+        // the spread (Morton) bits of the three cells along each axis, so
+        // that each stencil key is two ORs
+        uint32_t sx[3], sy[3], sz[3];
+        for (int d = 0; d < 3; ++d) {
+            sx[d] = spread3(cx + (uint32_t)(d - 1));
+            sy[d] = spread3(cy + (uint32_t)(d - 1)) << 1;
+            sz[d] = spread3(cz + (uint32_t)(d - 1)) << 2;
+        }
 #pragma unroll
         for (int dz = 0; dz < 3; ++dz) {
             uint32_t lo[9], hi[9];
 #pragma unroll
             for (int u = 0; u < 9; ++u) {
-                const uint32_t k = key_base + morton(cx + (uint32_t)(u % 3 - 1), cy + (uint32_t)(u / 3 - 1),
-                                                     cz + (uint32_t)(dz - 1), key_mask);
+                const uint32_t k = key_base + ((sx[u % 3] | sy[u / 3] | sz[dz]) & key_mask);
                 const uint4 e = s.cells[k];
                 lo[u] = e.x;
                 // an entry of an earlier substep is an empty key, and a key
@@ -467,9 +495,9 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 #pragma unroll
             for (int u = 0; u < 9; ++u) {
                 if (hi[u] > lo[u]) {
-                    nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, o[u], s.sorted[lo[u]]);
+                    nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, o[u], s.sorted, lo[u]);
                     for (uint32_t q = lo[u] + 1; q < hi[u]; ++q)
-                        nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, s.sxt4[q], s.sorted[q]);
+                        nbr_consider(lst, n, cap, count, pb, px, py, pz, c.search_r2, s.sxt4[q], s.sorted, q);
                 }
             }
         }
@@ -512,6 +540,18 @@ __global__ void __launch_bounds__(kBlock) k_neighbours(Scene s, StepConsts c)
 
 // Signed distance n . X_i - d of a particle from plane pl, in FP64 (the
 // penetration r - e is formed from it before any rounding).
+// Whether X_i = x0 + del lies clearly outside plane pl's contact range: the
+// signed distance evaluated in FP32 exceeds r by more than 2^-20 of the
+// magnitudes involved (several times the bound of that evaluation's
+// rounding), so the FP64 distance below exceeds r as well and its test can
+// be skipped without changing any result.  mag: |x0|_1 + |del|_1.
+__device__ __forceinline__ bool plane_far(const StepConsts& c, int pl, const float* x0, const float* del, float mag)
+{
+    const float e = c.plane_n[pl][0] * (x0[0] + del[0]) + c.plane_n[pl][1] * (x0[1] + del[1]) +
+                    c.plane_n[pl][2] * (x0[2] + del[2]) - c.plane_d[pl];
+    return e > c.radius + 0x1p-20f * (mag + fabsf(c.plane_d[pl]));
+}
+
 __device__ __forceinline__ double plane_gap(const StepConsts& c, int pl, const float* x0, const float* del)
 {
     double e = -c.plane_d_d[pl];
@@ -789,7 +829,9 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     // other bodies (constraint (2)); friction from the displacement since X_init
     if (act) {
         const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
+        const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
         for (int pl = 0; pl < c.n_planes; ++pl) {
+            if (plane_far(c, pl, x0, del, mag)) continue;
             const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
             const float un = nx * del[0] + ny * del[1] + nz * del[2];
             const double e = plane_gap(c, pl, x0, del);
@@ -1127,7 +1169,10 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
         // contacts from X_i (planes, then partners in list order)
         float Cd[3] = {0.0f, 0.0f, 0.0f};
         if (act) {
+            const float mag =
+                fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
             for (int pl = 0; pl < c.n_planes; ++pl) {
+                if (plane_far(c, pl, x0, del, mag)) continue;
                 const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
                 const float un = nx * del[0] + ny * del[1] + nz * del[2];
                 const double e = plane_gap(c, pl, x0, del);
@@ -1537,13 +1582,14 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
             const uint32_t* kin = p == 0 ? s.key : s.kbuf[(p - 1) & 1];
             const uint32_t* iin = p == 0 ? nullptr : s.ibuf[(p - 1) & 1];
             const dim3 tiles(s.n_radix_tiles);
+            // (the first pass's tile counts come from the histogram launch)
             if (s.radix_items == 16) {
-                hipLaunchKernelGGL(k_radix_count<16>, tiles, dim3(kBlock), 0, stream, s, p, kin);
+                if (p > 0) hipLaunchKernelGGL(k_radix_count<16>, tiles, dim3(kBlock), 0, stream, s, p, kin);
                 hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins), dim3(kBlock), 0, stream, s, p);
                 hipLaunchKernelGGL(k_radix_scatter<16>, tiles, dim3(kBlock), 0, stream, s, p, kin, iin,
                                    s.kbuf[p & 1], s.ibuf[p & 1]);
             } else {
-                hipLaunchKernelGGL(k_radix_count<4>, tiles, dim3(kBlock), 0, stream, s, p, kin);
+                if (p > 0) hipLaunchKernelGGL(k_radix_count<4>, tiles, dim3(kBlock), 0, stream, s, p, kin);
                 hipLaunchKernelGGL(k_radix_scan, dim3(kRadixBins), dim3(kBlock), 0, stream, s, p);
                 hipLaunchKernelGGL(k_radix_scatter<4>, tiles, dim3(kBlock), 0, stream, s, p, kin, iin,
                                    s.kbuf[p & 1], s.ibuf[p & 1]);

@@ -256,8 +256,13 @@ __device__ inline void contacts(const Ctx& x, int i, const float* x0, const floa
     const PoolDev& d = *x.d;
     const size_t P = x.P;
     for (int k = 0; k < 3; ++k) Cd[k] = 0.0f;
+    // planes clearly out of contact range in FP32 (by 2^-20 of the magnitudes
+    // involved, several times that evaluation's rounding bound) skip the FP64 test
+    const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
     for (int pl = 0; pl < c.n_planes; ++pl) {
         const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
+        const float e32 = nx * (x0[0] + del[0]) + ny * (x0[1] + del[1]) + nz * (x0[2] + del[2]) - c.plane_d[pl];
+        if (e32 > c.radius + 0x1p-20f * (mag + fabsf(c.plane_d[pl]))) continue;
         const float un = nx * del[0] + ny * del[1] + nz * del[2];
         // signed distance and penetration in FP64, rounded only as a correction
         double e = -c.plane_d_d[pl];
