@@ -511,6 +511,7 @@ class Pool:
             raise ValueError("slots and frames differ in length")
         _check(self._lib.pbdr_pool_step_slots_on(self._h, lane, ctypes.c_void_p(stream.cuda_stream), int(s.shape[0]),
                                                  s.ctypes.data, f.ctypes.data))
+        self.workspace.record_stream(stream)   # the allocator waits for this lane's work as well
 
     def slot_class(self, slot: int) -> int:
         c = ctypes.c_int32()
