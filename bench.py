@@ -85,10 +85,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the iteration kernel on this workload from the
-    committed rocprofv3 counter summary, or None when there is none or it was
-    taken on a different kernel source."""
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of the iteration kernel `kernel` on this workload
+    from the committed rocprofv3 counter summary, or None when there is none,
+    it covers another kernel, or it was taken on a different kernel source."""
     try:
         vals = {}
         with open(os.path.join(PROFILES, "k_iterate_%s_traffic.txt" % workload)) as f:
@@ -96,7 +96,7 @@ def measured_traffic(workload: str):
                 if ":" in line:
                     k, v = line.split(":", 1)
                     vals[k.strip()] = v.strip()
-        if vals.get("kernel_source_sha256_16") != source_digest():
+        if vals.get("kernel_source_sha256_16") != source_digest() or vals.get("kernel") != kernel:
             return None
         return float(vals["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -501,10 +501,11 @@ def main():
     bytes_launch = per_launch * (info.first_launch_particles * iterate_bytes_per_particle(kbar)
                                  + info.first_launch_bodies * iterate_bytes_per_body())
     achieved = bytes_launch / (it_ms / 1e3) / 1e9
-    traffic = measured_traffic(sc.name)
+    timed_kernel = {0: "k_iterate", 1: "k_iterate_dense", 2: "k_iterate_resident"}[info.iteration_kernel]
+    traffic = measured_traffic(sc.name, timed_kernel)
     kernel = {0: "k_iterate (one Jacobi iteration, all bodies, one launch)",
               1: ("k_iterate_dense (one Jacobi iteration over the bodies of up to 4 waves, in 4-wave "
-                  "workgroups; the larger bodies run beside it in k_iterate)" if split else
+                  "workgroups; the larger bodies follow in k_iterate)" if split else
                   "k_iterate_dense (one Jacobi iteration, all bodies, one launch)"),
               2: "k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)" % per_launch}
     sub_b = substep_bytes_per_particle(sc.iterations, kbar, info.hash_bits)
