@@ -495,18 +495,12 @@ def main():
     k1.record(stream)
     torch.cuda.synchronize()
     interval_ms = k0.elapsed_time(k1) / n_it
-    # with a second launch for the bodies of more than 4 waves (running beside
-    # the first), the events time the first launch, and the bytes are its own
-    split = info.first_launch_particles < sc.n
-    bytes_launch = per_launch * (info.first_launch_particles * iterate_bytes_per_particle(kbar)
-                                 + info.first_launch_bodies * iterate_bytes_per_body())
+    bytes_launch = per_launch * (sc.n * iterate_bytes_per_particle(kbar) + sc.n_bodies * iterate_bytes_per_body())
     achieved = bytes_launch / (it_ms / 1e3) / 1e9
     timed_kernel = {0: "k_iterate", 1: "k_iterate_dense", 2: "k_iterate_resident"}[info.iteration_kernel]
     traffic = measured_traffic(sc.name, timed_kernel)
     kernel = {0: "k_iterate (one Jacobi iteration, all bodies, one launch)",
-              1: ("k_iterate_dense (one Jacobi iteration over the bodies of up to 4 waves, in 4-wave "
-                  "workgroups; the larger bodies follow in k_iterate)" if split else
-                  "k_iterate_dense (one Jacobi iteration, all bodies, one launch)"),
+              1: "k_iterate_dense (one Jacobi iteration, all bodies, one launch of 4-wave workgroups)",
               2: "k_iterate_resident (the %d Jacobi iterations of a substep, all bodies, one launch)" % per_launch}
     sub_b = substep_bytes_per_particle(sc.iterations, kbar, info.hash_bits)
     sub_gbs = value * sub_b / 1e9
@@ -515,7 +509,7 @@ def main():
             "kernel": kernel[info.iteration_kernel],
             "iterations_per_launch": per_launch, "measured_copy_gbs": round(copy_gbs, 1),
             "avg_launch_us": round(it_ms * 1e3, 3), "launch_interval_us": round(interval_ms * 1e3, 3),
-            "bytes_per_launch": int(bytes_launch), "particles_per_launch": info.first_launch_particles,
+            "bytes_per_launch": int(bytes_launch), "particles_per_launch": sc.n,
             "mean_neighbours": round(kbar, 4),
             # HBM bytes the counters saw per launch, over the same duration
             "counter_frac": (round(traffic / (it_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if traffic else None),

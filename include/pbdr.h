@@ -148,11 +148,6 @@ typedef struct {
                                      oversubscribes the GPU; 2: all K iterations of a
                                      substep in one launch (the grid is resident at
                                      once, K < 64) */
-    int32_t first_launch_particles; /* particles and bodies of the first iteration launch:
-                                       all of them, unless the bodies of more than 4 waves
-                                       have a second launch (iteration_kernel 1), which
-                                       follows it */
-    int32_t first_launch_bodies;
     size_t workspace_bytes;
 } pbdr_scene_info;
 

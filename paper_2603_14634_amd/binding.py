@@ -89,8 +89,6 @@ class SceneInfo(ctypes.Structure):
         ("iteration_blocks", ctypes.c_int32),
         ("max_body_particles", ctypes.c_int32),
         ("iteration_kernel", ctypes.c_int32),
-        ("first_launch_particles", ctypes.c_int32),
-        ("first_launch_bodies", ctypes.c_int32),
         ("workspace_bytes", ctypes.c_size_t),
     ]
 

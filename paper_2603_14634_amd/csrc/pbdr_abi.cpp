@@ -126,14 +126,12 @@ struct Layout {
 // Passes of the key sort (8-bit digits) for keys of `bits` bits.
 int radix_passes(int bits) { return std::max(1, (bits + pbdr::kRadixBits - 1) / pbdr::kRadixBits); }
 
-// Upper bound on the padded wave count of the iteration kernel's body packing
-// (both launches together): each body needs ceil(n_b / 64) <= n_b / 64 + 1
-// waves.  Greedy packing into workgroups of W waves wastes less than half of
-// every workgroup it closes for lack of room.  When bodies of more than 4
-// waves get their own launch, each of them (>= 5 waves) may sit alone in a
-// workgroup of at most 16 waves and force one early close (<= 3 waves) in
-// the 4-wave packing: at most 19 < 4 x 5 waves.  The last workgroup of each
-// launch is padded by at most W - 1 waves.
+// Upper bound on the padded wave count of the iteration kernel's body packing:
+// each body needs ceil(n_b / 64) <= n_b / 64 + 1 waves.  Greedy packing into
+// workgroups of W waves wastes less than half of every workgroup it closes
+// for lack of room.  In the 4-wave packing of the 80-VGPR kernel a body of
+// more than 4 waves takes one workgroup of 4 waves, fewer than it needs.  The
+// last workgroup is padded by at most W - 1 waves.
 size_t max_iteration_waves(int32_t n, int32_t nb)
 {
     return 4 * ((size_t)n / 64 + (size_t)nb + 2) + 2 * pbdr::kMaxWaves;
@@ -193,12 +191,9 @@ struct pbdr_scene {
     Resolved res;
     Layout lay;
     pbdr::Scene dev;
-    pbdr::Scene dev2;                    // second iteration launch (bodies of more than 4 waves) if split
-    bool split = false;
     pbdr::StepConsts consts;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
-    int32_t first_particles = 0, first_bodies = 0;   // of the first iteration launch
     hipGraph_t graph = nullptr;          // one frame
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph_n = nullptr;        // kGraphFrames frames
@@ -262,9 +257,6 @@ void choose_iteration_form(pbdr_scene* s)
         s->dev.resident_iterate = want;
     }
 }
-
-// The second iteration launch of a split packing, or NULL.
-const pbdr::Scene* second_launch(const pbdr_scene* s) { return s->split ? &s->dev2 : nullptr; }
 
 void drop_graph(pbdr_scene* s)
 {
@@ -414,7 +406,7 @@ pbdr_status check_host_finite(const float* a, size_t count, const char* what)
 pbdr_status enqueue(pbdr_scene* s, int32_t substeps_total)
 {
     choose_iteration_form(s);
-    hipError_t e = pbdr::enqueue_substeps(s->dev, second_launch(s), s->consts, s->res.p.iterations, substeps_total,
+    hipError_t e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, substeps_total,
                                           s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     s->stepped = true;
@@ -430,7 +422,7 @@ pbdr_status capture(pbdr_scene* s, int frames, hipGraph_t* graph, hipGraphExec_t
     HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     for (int f = 0; f < frames && e == hipSuccess; ++f)
-        e = pbdr::enqueue_substeps(s->dev, second_launch(s), s->consts, s->res.p.iterations, s->res.p.substeps,
+        e = pbdr::enqueue_substeps(s->dev, s->consts, s->res.p.iterations, s->res.p.substeps,
                                    s->cap_stream);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(s->cap_stream, &g);
@@ -571,32 +563,34 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
         if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     }
     const int W = std::max(4, (max_body + 63) / 64);
-    std::vector<int32_t> wave_body, block_body, body_wave0((size_t)nb), wave_body2, block_body2;
+    std::vector<int32_t> wave_body, block_body, body_wave0((size_t)nb);
     pack(W, 0, W, wave_body, block_body, body_wave0);
     s->dev.waves_per_block = W;
     s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
     // More workgroups than the GPU holds at once with 4 waves per SIMD (16 per
-    // CU, the ~100-VGPR kernel): take the 80-VGPR kernel (6 waves per SIMD),
-    // and if the largest bodies need wider workgroups than the others, give
-    // the bodies of up to 4 waves workgroups of 4 waves (so that more of them
-    // share a CU) and the larger ones a second launch of W-wave workgroups.
+    // CU, the ~100-VGPR kernel): take the 80-VGPR kernel (6 waves per SIMD)
+    // with workgroups of 4 waves, so that more of them share a CU.  Bodies of
+    // more than 4 waves then take one such workgroup each, at the front of the
+    // launch, which goes over their particles in chunks of 4 waves.
     s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
     s->dev.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
-    s->split = false;
-    constexpr int kDenseWaves = 4;      // workgroup of the split packing's first launch
+    s->dev.n_chunked = 0;
+    constexpr int kDenseWaves = 4;      // workgroup of the 80-VGPR kernel
     if (s->dev.dense_iterate && W > kDenseWaves) {
         wave_body.clear();
-        pack(kDenseWaves, 0, kDenseWaves, wave_body, block_body, body_wave0);
-        pack(W, kDenseWaves + 1, W, wave_body2, block_body2, body_wave0);     // the larger bodies
-        s->split = !wave_body2.empty();
+        for (int32_t b = 0; b < nb; ++b) {
+            if ((desc->body_start[b + 1] - desc->body_start[b] + 63) / 64 <= kDenseWaves) continue;
+            body_wave0[(size_t)b] = (int32_t)wave_body.size();
+            wave_body.resize(wave_body.size() + kDenseWaves, b);
+            s->dev.n_chunked += 1;
+        }
+        pack(kDenseWaves, 0, kDenseWaves, wave_body, block_body, body_wave0);   // (block_body of all)
         s->dev.waves_per_block = kDenseWaves;
         s->dev.n_iter_blocks = (int32_t)(wave_body.size() / kDenseWaves);
-        s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / kDenseWaves) ? 1 : 0;
+        s->dev.dense_iterate = 1;
         s->dev.wide_bodies = 0;
     }
-    const size_t waves_total = wave_body.size() + wave_body2.size();
-    const size_t blocks_total = (block_body.size() + block_body2.size()) / 2;
-    if (waves_total > max_iteration_waves(n, nb) || blocks_total > max_iteration_waves(n, nb) / 4 + 2) {
+    if (wave_body.size() > max_iteration_waves(n, nb) || block_body.size() / 2 > max_iteration_waves(n, nb) / 4 + 2) {
         discard();
         return fail(PBDR_ERR_INVALID_ARG, "internal: body packing exceeds its bound");
     }
@@ -604,38 +598,12 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
     // single iteration launch is resident at once (and K fits the 6-bit
     // iteration field of the tags)
     (void)hipGetDevice(&s->device);
-    if (!s->split && !s->dev.dense_iterate && !(s->res.p.flags & PBDR_FLAG_ITERATION_LAUNCHES) &&
+    if (!s->dev.dense_iterate && !(s->res.p.flags & PBDR_FLAG_ITERATION_LAUNCHES) &&
         s->dev.n_iter_blocks > 0 && s->res.p.iterations < 64) {
         s->one_launch_capacity = pbdr::resident_iterate_capacity(s->dev.waves_per_block);
         s->one_launch_ok = s->dev.n_iter_blocks <= s->one_launch_capacity;
     }
     s->dev.resident_iterate = s->one_launch_ok ? 1 : 0;
-    s->dev2 = s->dev;
-    if (s->split) {
-        s->dev2.wave_body = s->dev.wave_body + wave_body.size();
-        s->dev2.block_body = s->dev.block_body + block_body.size();
-        s->dev2.waves_per_block = W;
-        s->dev2.n_iter_blocks = (int32_t)(wave_body2.size() / (size_t)W);
-        // bodies of more than 4 waves: the register-rich kernel, with FP64
-        // shape-matching sums if some body needs them
-        s->dev2.dense_iterate = 0;
-        s->dev2.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
-        wave_body.insert(wave_body.end(), wave_body2.begin(), wave_body2.end());
-        block_body.insert(block_body.end(), block_body2.begin(), block_body2.end());
-    }
-    s->first_particles = n;
-    s->first_bodies = nb;
-    if (s->split) {
-        s->first_particles = 0;
-        s->first_bodies = 0;
-        for (int32_t b = 0; b < nb; ++b) {
-            const int32_t nbp = desc->body_start[b + 1] - desc->body_start[b];
-            if ((nbp + 63) / 64 <= kDenseWaves) {
-                s->first_particles += nbp;
-                s->first_bodies += 1;
-            }
-        }
-    }
 
     // rest pose (FP64): body mass, centre, q = x - c  (Sec. III-C, shape matching)
     std::vector<int32_t> body((size_t)n);
@@ -735,7 +703,6 @@ pbdr_status pbdr_scene_set_accel(pbdr_scene* s, const float* accel_dev)
     if (!s) return fail(PBDR_ERR_INVALID_ARG, "scene is NULL");
     if (s->dev.accel != accel_dev) drop_graph(s);
     s->dev.accel = accel_dev;
-    s->dev2.accel = accel_dev;
     return PBDR_OK;
 }
 
@@ -780,7 +747,7 @@ pbdr_status pbdr_scene_launch_iterations(pbdr_scene* s, int32_t n_launches)
     if (n_launches < 0) return fail(PBDR_ERR_INVALID_ARG, "n_launches must be >= 0");
     if (!s->stepped) return fail(PBDR_ERR_STATE, "no substep has run yet");
     choose_iteration_form(s);
-    hipError_t e = pbdr::enqueue_iterations(s->dev, second_launch(s), s->consts, s->res.p.iterations, n_launches,
+    hipError_t e = pbdr::enqueue_iterations(s->dev, s->consts, s->res.p.iterations, n_launches,
                                             s->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return PBDR_OK;
@@ -806,7 +773,7 @@ pbdr_status pbdr_scene_time_iterations(pbdr_scene* s, int32_t n_launches, float*
     hipError_t e = hipSuccess;
     for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     if (e == hipSuccess)
-        e = pbdr::enqueue_iterations_timed(s->dev, second_launch(s), s->consts, s->res.p.iterations, n_launches,
+        e = pbdr::enqueue_iterations_timed(s->dev, s->consts, s->res.p.iterations, n_launches,
                                            s->stream, ev.data(), ev.data() + n_launches);
     if (e == hipSuccess) e = hipEventSynchronize(ev.back());
     for (int32_t i = 0; i < n_launches && e == hipSuccess; ++i) {
@@ -968,11 +935,9 @@ pbdr_status pbdr_scene_info_get(const pbdr_scene* s, pbdr_scene_info* out)
     out->search_radius = s->res.rs;
     out->cell_size = s->res.a;
     out->waves_per_block = s->dev.waves_per_block;
-    out->iteration_blocks = s->dev.n_iter_blocks + (s->split ? s->dev2.n_iter_blocks : 0);
+    out->iteration_blocks = s->dev.n_iter_blocks;
     out->max_body_particles = s->max_body;
     out->iteration_kernel = s->dev.resident_iterate ? 2 : s->dev.dense_iterate;
-    out->first_launch_particles = s->first_particles;
-    out->first_launch_bodies = s->first_bodies;
     out->workspace_bytes = s->lay.total;
     return PBDR_OK;
 }

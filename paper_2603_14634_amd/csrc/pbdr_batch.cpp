@@ -280,7 +280,7 @@ pbdr_status enqueue_segment(pbdr_batch* b, const std::vector<char>& active, int3
     d.wide_bodies = max_need > pbdr::kWideBodyWaves ? 1 : 0;
     const long long total = (long long)frames * b->res.p.substeps;
     if (total > 0x7fffffffll) return fail(PBDR_ERR_INVALID_ARG, "too many substeps in one call");
-    hipError_t e = pbdr::enqueue_substeps(d, nullptr, b->consts, b->res.p.iterations, (int)total, b->stream);
+    hipError_t e = pbdr::enqueue_substeps(d, b->consts, b->res.p.iterations, (int)total, b->stream);
     if (e != hipSuccess) return fail(PBDR_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
     return PBDR_OK;
 }

@@ -124,6 +124,8 @@ struct Scene {
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
     int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (80-VGPR kernel)
+    int32_t n_chunked = 0;    // 80-VGPR kernel: its first n_chunked workgroups (4 waves) take one body
+                              //     of more than 4 waves each (block_body holds (body, 1) for them)
     int32_t wide_bodies;      // 1: some body of the iteration launch spans more than kWideBodyWaves waves
     float* dl[2];             // [3][N] X_i - X_init, double buffered
     float* vel[2];            // [3][N] V_i, double buffered
@@ -162,12 +164,8 @@ struct Scene {
     int32_t resident_iterate = 0;           // 1: the K iterations run as one launch
 };
 
-// Enqueues `count` substeps of K = iterations solver iterations.  s2 (or
-// NULL) is the same scene with the wave tables of a second iteration launch
-// (bodies of more than 4 waves, when s packs the others into 4-wave
-// workgroups); both launches make one Jacobi iteration.
-hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
-                            hipStream_t stream);
+// Enqueues `count` substeps of K = iterations solver iterations.
+hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream);
 
 // Workgroups of the one-launch iteration kernel (64 waves_per_block threads)
 // that the GPU holds at once; 0 if it cannot be queried.
@@ -177,12 +175,11 @@ int resident_iterate_capacity(int waves_per_block);
 // one Jacobi iteration each (all but the first continue from the rotation of
 // the one before), or, for a scene whose substep runs its `iterations`
 // iterations as one launch, that launch.
-hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
-                              hipStream_t stream);
+hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream);
 
-// As enqueue_iterations, launch `k` with its first kernel bound to the events
-// t0[k] (begin) and t1[k] (end); a second launch (s2) follows it untimed.
-hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+// As enqueue_iterations, launch `k` bound to the events t0[k] (begin) and
+// t1[k] (end).
+hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1);
 
 // Zeroes `bytes` (a multiple of 4) at `p` with a fill kernel (no memset node

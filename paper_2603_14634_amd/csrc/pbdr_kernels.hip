@@ -66,6 +66,16 @@ __device__ inline int xcd_block()
     return (int)(x * q + (x < r ? x : r) + blockIdx.x / 8u);
 }
 
+// The same renumbering of workgroups first .. gridDim.x - 1 among themselves
+// (the XCD of their residue class is rotated by `first`, each class still on
+// one XCD).
+__device__ inline int xcd_block_from(int first)
+{
+    const uint32_t hb = blockIdx.x - (uint32_t)first, nb = gridDim.x - (uint32_t)first, q = nb / 8u, r = nb % 8u,
+                   x = hb % 8u;
+    return first + (int)(x * q + (x < r ? x : r) + hb / 8u);
+}
+
 // ---------------------------------------------------------------------------
 // integration step + keys
 // ---------------------------------------------------------------------------
@@ -753,20 +763,187 @@ __device__ __forceinline__ void sm_body_sums(int w0, int nw, float M, double M64
     }
 }
 
+constexpr int kNSm = 12, kNMom = 24;       // per-wave partial sums (float4 aligned; 21 momentum sums used)
+
+// Contact corrections of particle i from X_i (Jacobi): planes (constraint
+// (1)) and particles of other bodies (constraint (2)), friction from the
+// displacement since X_init; accumulated into Cd.
+template <bool MULTI>
+__device__ __forceinline__ void contact_correction(const Scene& s, const StepConsts& c, const float* dl, uint32_t avg,
+                                                   size_t n, int i, const float* x0, const float* del, float m,
+                                                   float* Cd)
+{
+    const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
+    const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
+    for (int pl = 0; pl < c.n_planes; ++pl) {
+        if (plane_far(c, pl, x0, del, mag)) continue;
+        const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
+        const float un = nx * del[0] + ny * del[1] + nz * del[2];
+        const double e = plane_gap(c, pl, x0, del);
+        if (!(e < c.radius_d)) continue;
+        const float pen = (float)(c.radius_d - e);
+        const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
+        const float ut2 = ux * ux + uy * uy + uz * uz;
+        const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+        Cd[0] += pen * nx - f * ux;
+        Cd[1] += pen * ny - f * uy;
+        Cd[2] += pen * nz - f * uz;
+    }
+    const uint32_t ni = s.nbr_n[i];
+    const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
+    for (uint32_t sl = 0; sl < cnt; ++sl) {
+        const uint32_t jq = s.nbr[sl * n + i];
+        float xq[3], dq[3];
+        for (int j = 0; j < 3; ++j) {
+            xq[j] = s.x0[j * n + jq];
+            dq[j] = dl[j * n + jq];
+        }
+        pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
+    }
+}
+
+// Shape matching of one body, on its lane: centre and covariance from the
+// partials of its waves w0 .. w0 + nw - 1, the rotation (from the second
+// iteration on refined from the previous iteration's, Rprev), then R and the
+// centre to `sm` (FP32, 12 values) and `rd` (FP64: R made orthonormal, and
+// the centre), and R kept for the next iteration.
+template <bool WIDE_OK, int UNROLL>
+__device__ __forceinline__ void body_shape_match(const Scene& s, int it, int bb, int w0, int nw, float M, double M64,
+                                                 const float* mq3, const float* Rprev, const float4* red32,
+                                                 const double* red64, float* sm, double* rd)
+{
+    float cc[3], A[9], Rb[9];
+    sm_body_sums<WIDE_OK, UNROLL>(w0, nw, M, M64, mq3, red32, red64, cc, &rd[9], A);
+    if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
+    for (int j = 0; j < 9; ++j) sm[j] = Rb[j];
+    for (int j = 0; j < 3; ++j) sm[9 + j] = cc[j];
+    orthonormalise64(Rb, rd);
+    if (s.body_rot)
+        for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rb[j];
+}
+
+// This wave's partial sums of the momentum constraint to LDS slot `slot`, in
+// the frame centred on c_i: z_b = r + C (before shape matching), z_a = z_b + D,
+// with r = x - c_i, C the contact correction and D the goal offset.
+__device__ __forceinline__ void mom_wave_partials(const StepConsts& c, float m, const float* r, const float* Cd,
+                                                  const float* Dd, const float* V, int slot, int lane,
+                                                  float4* red_mom)
+{
+    float S[kNMom];
+    float zb[3], za[3], vb[3], t[3];
+    for (int j = 0; j < 3; ++j) {
+        zb[j] = r[j] + Cd[j];
+        za[j] = zb[j] + Dd[j];
+        vb[j] = V[j] + Cd[j] * c.inv_h;
+        S[j] = m * Cd[j];               // S1 = sum m C
+        S[3 + j] = m * Dd[j];           // S2 = sum m D
+        S[6 + j] = m * vb[j];           // S3 = P_bsm
+    }
+    cross(zb, Dd, t);
+    for (int j = 0; j < 3; ++j) S[9 + j] = m * t[j];          // S4 = sum m z_b x D
+    cross(Dd, vb, t);
+    for (int j = 0; j < 3; ++j) S[12 + j] = m * t[j];         // S5 = sum m D x v_b
+    S[15] = m * (za[1] * za[1] + za[2] * za[2]);              // S6: inertia about c_i
+    S[16] = m * (za[0] * za[0] + za[2] * za[2]);
+    S[17] = m * (za[0] * za[0] + za[1] * za[1]);
+    S[18] = -m * za[0] * za[1];
+    S[19] = -m * za[0] * za[2];
+    S[20] = -m * za[1] * za[2];
+    S[21] = S[22] = S[23] = 0.0f;
+    wave_sums_by_row<kNMom>(S);
+    if ((lane & 15) == 15) {
+        float* dst = (float*)red_mom + slot * kNMom + (lane >> 4) * (kNMom / 4);
+        for (int j = 0; j < kNMom / 4; ++j) dst[j] = S[j];
+    }
+}
+
+// The momentum conservation constraint of one body, on its lane, from the
+// partials of its waves w0 .. w0 + nw - 1: dv (3), omega (3) and c_asm - c_i
+// (3) to `out`.
+template <int UNROLL>
+__device__ __forceinline__ void body_momentum(const StepConsts& c, int w0, int nw, float Mb, const float4* red_mom,
+                                              float* out)
+{
+    float T[kNMom];
+    sum_wave_partials<kNMom / 4, UNROLL>(red_mom, w0, nw, T);
+    const float im = frcp(Mb);
+    float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < 3; ++j) {
+        cb[j] = T[j] * im;                   // c_bsm - c_i
+        Db[j] = T[3 + j] * im;               // mean shape-matching shift
+        cab[j] = cb[j] + Db[j];              // c_asm - c_i
+    }
+    // Eq. (4): dv = (P_bsm - P_asm) / M,  P_asm - P_bsm = sum m D / dt
+    if (!(c.flags & kFlagNoLinMom))
+        for (int j = 0; j < 3; ++j) dvb[j] = -T[3 + j] * c.inv_h * im;
+    // Eq. (5): omega = I^-1 (L_asm - L_bsm); the difference is formed from
+    // the small quantities: (sum m r_b x D)/dt + sum m D x v_b - Db x P_bsm
+    if (!(c.flags & kFlagNoAngMom)) {
+        float cbxD[3], DbxP[3], dL[3], I6[6];
+        cross(cb, &T[3], cbxD);
+        cross(Db, &T[6], DbxP);
+        for (int j = 0; j < 3; ++j) dL[j] = (T[9 + j] - cbxD[j]) * c.inv_h + T[12 + j] - DbxP[j];
+        // parallel-axis shift of the inertia from c_i to c_asm
+        I6[0] = T[15] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
+        I6[1] = T[16] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
+        I6[2] = T[17] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
+        I6[3] = T[18] + Mb * cab[0] * cab[1];
+        I6[4] = T[19] + Mb * cab[0] * cab[2];
+        I6[5] = T[20] + Mb * cab[1] * cab[2];
+        const float scale = fmaxf(I6[0] + I6[1] + I6[2], Mb * c.two_r * c.two_r);
+        solve_inertia(I6, dL, scale, wb);
+    }
+    for (int j = 0; j < 3; ++j) {
+        out[j] = dvb[j];
+        out[3 + j] = wb[j];
+        out[6 + j] = cab[j];
+    }
+}
+
+// X_{i+1} - X_init and V_{i+1} of particle i (Sec. III-B velocity update with
+// the momentum terms of Sec. III-C): mom = the body's dv, omega, c_asm - c_i.
+__device__ __forceinline__ void particle_update(const StepConsts& c, const float* mom, const float* x0,
+                                                const float* del, const float* V, const float* r, const float* Cd,
+                                                const float* Dd, size_t n, int i, float* dn, float* vn)
+{
+    float dv[3], w[3], ca[3];
+    for (int j = 0; j < 3; ++j) {
+        dv[j] = mom[j];
+        w[j] = mom[3 + j];
+        ca[j] = mom[6 + j];
+    }
+    float ra[3], wr[3];
+    for (int j = 0; j < 3; ++j) ra[j] = r[j] + Cd[j] + Dd[j] - ca[j];
+    cross(w, ra, wr);
+    for (int j = 0; j < 3; ++j) {
+        const float step = Cd[j] + Dd[j];
+        const float dvi = dv[j] - wr[j];
+        const float dnew = (del[j] + step) + c.h * dvi;
+        dn[j * n + i] = dnew;
+        if (c.flags & kFlagStdVelocity) {
+            // standard PBD: V = (X_{i+1} - X_init) / dt in world FP32 coordinates
+            const float xw = x0[j] + dnew;
+            vn[j * n + i] = (xw - x0[j]) * c.inv_h;
+        } else {
+            vn[j * n + i] = (V[j] + step * c.inv_h) + dvi;
+        }
+    }
+}
+
 // Bodies are packed into workgroups of W waves; each body owns ceil(n/64)
 // consecutive waves, one particle per lane.  Per-body sums are wave sums (lane swaps, DPP)
 // combined over the body's waves; the per-body 3x3 algebra runs on lane j of
 // wave 0 for the j-th body of the workgroup.  `it` is the iteration index in
 // the substep: from the second iteration on, the rotation is refined from the
-// previous iteration's.  SM_UNROLL / MOM_UNROLL: waves whose partial sums the
-// per-body lane reads from LDS at once.
+// previous iteration's.  blk: the workgroup's index in the packing.
+// SM_UNROLL / MOM_UNROLL: waves whose partial sums the per-body lane reads
+// from LDS at once.
 template <bool MULTI, bool WIDE_OK, int SM_UNROLL, int MOM_UNROLL>
-__device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it)
+__device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it, int blk)
 {
-    constexpr int NSM = 12, NMOM = 24;          // per-wave partial sums (float4 aligned; 21 used)
-    __shared__ float4 red_sm[kMaxWaves * NSM / 4];
-    __shared__ double red_sm64[WIDE_OK ? kMaxWaves * NSM : 1];
-    __shared__ float4 red_mom[kMaxWaves * NMOM / 4];
+    __shared__ float4 red_sm[kMaxWaves * kNSm / 4];
+    __shared__ double red_sm64[WIDE_OK ? kMaxWaves * kNSm : 1];
+    __shared__ float4 red_mom[kMaxWaves * kNMom / 4];
     __shared__ float body_sm[kMaxWaves * 12];    // per body of the workgroup: R (9), centre (3)
     __shared__ float body_mom[kMaxWaves * 9];    // dv (3), omega (3), c_asm - c_i (3)
     __shared__ double body_rd[kMaxWaves * 12];   // R and centre in FP64 (goal offsets)
@@ -774,7 +951,6 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     // the wave index as a wave-uniform (scalar) value: the per-wave table and
     // body entries below then come through scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const int blk = xcd_block();
     const int g = blk * s.waves_per_block + wave;
     const int b = s.wave_body[g];                 // -1: idle wave
     const int blk_b0 = s.block_body[2 * blk], blk_nb = s.block_body[2 * blk + 1];
@@ -824,153 +1000,146 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         }
         m = s.mass[i];
     }
-
-    // contacts, from X_i (Jacobi): planes (constraint (1)) and particles of
-    // other bodies (constraint (2)); friction from the displacement since X_init
-    if (act) {
-        const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
-        const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
-        for (int pl = 0; pl < c.n_planes; ++pl) {
-            if (plane_far(c, pl, x0, del, mag)) continue;
-            const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
-            const float un = nx * del[0] + ny * del[1] + nz * del[2];
-            const double e = plane_gap(c, pl, x0, del);
-            if (!(e < c.radius_d)) continue;
-            const float pen = (float)(c.radius_d - e);
-            const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
-            const float ut2 = ux * ux + uy * uy + uz * uz;
-            const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
-            Cd[0] += pen * nx - f * ux;
-            Cd[1] += pen * ny - f * uy;
-            Cd[2] += pen * nz - f * uz;
-        }
-        const uint32_t ni = s.nbr_n[i];
-        const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
-        for (uint32_t sl = 0; sl < cnt; ++sl) {
-            const uint32_t jq = s.nbr[sl * n + i];
-            float xq[3], dq[3];
-            for (int j = 0; j < 3; ++j) {
-                xq[j] = s.x0[j * n + jq];
-                dq[j] = dl[j * n + jq];
-            }
-            pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
-        }
-    }
+    if (act) contact_correction<MULTI>(s, c, dl, avg, n, i, x0, del, m, Cd);
 
     // shape matching on X_i: centre and covariance in one reduction,
     // A = sum m (x - c) q^T = sum m y q^T - c (sum m q)^T, y = x - anchor
     sm_wave_partials<WIDE_OK>(wide, m, x0, anc, del, q, wave, lane, red_sm, red_sm64);
     __syncthreads();
-    if (body_lane) {            // one lane per body: centre, covariance, rotation
-        float cc[3], A[9], Rb[9];
-        sm_body_sums<WIDE_OK, SM_UNROLL>(bl_w0, bl_nw, bl_M, bl_M64, mq3, red_sm, red_sm64, cc,
-                                         &body_rd[lane * 12 + 9], A);
-        if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
-        for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
-        for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
-        orthonormalise64(Rb, &body_rd[lane * 12]);
-        if (s.body_rot)
-            for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rb[j];
-    }
+    if (body_lane)              // one lane per body: centre, covariance, rotation
+        body_shape_match<WIDE_OK, SM_UNROLL>(s, it, bb, bl_w0, bl_nw, bl_M, bl_M64, mq3, Rprev, red_sm, red_sm64,
+                                             &body_sm[lane * 12], &body_rd[lane * 12]);
     __syncthreads();
     float cyv[3];
     for (int j = 0; j < 3; ++j) cyv[j] = body_sm[lb * 12 + 9 + j];
 
     // goal offsets D = R q - (x - c) and the momentum sums, in the frame
-    // centred on c_i: z_b = r + C (before shape matching), z_a = z_b + D
+    // centred on c_i
     float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
     for (int j = 0; j < 3; ++j) r[j] = ((x0[j] - anc[j]) + del[j]) - cyv[j];
     if (act) goal_offset(&body_rd[lb * 12], q, x0, anc, del, Dd);
-    {
-        float S[NMOM];
-        float zb[3], za[3], vb[3], t[3];
-        for (int j = 0; j < 3; ++j) {
-            zb[j] = r[j] + Cd[j];
-            za[j] = zb[j] + Dd[j];
-            vb[j] = V[j] + Cd[j] * c.inv_h;
-            S[j] = m * Cd[j];               // S1 = sum m C
-            S[3 + j] = m * Dd[j];           // S2 = sum m D
-            S[6 + j] = m * vb[j];           // S3 = P_bsm
-        }
-        cross(zb, Dd, t);
-        for (int j = 0; j < 3; ++j) S[9 + j] = m * t[j];          // S4 = sum m z_b x D
-        cross(Dd, vb, t);
-        for (int j = 0; j < 3; ++j) S[12 + j] = m * t[j];         // S5 = sum m D x v_b
-        S[15] = m * (za[1] * za[1] + za[2] * za[2]);              // S6: inertia about c_i
-        S[16] = m * (za[0] * za[0] + za[2] * za[2]);
-        S[17] = m * (za[0] * za[0] + za[1] * za[1]);
-        S[18] = -m * za[0] * za[1];
-        S[19] = -m * za[0] * za[2];
-        S[20] = -m * za[1] * za[2];
-        S[21] = S[22] = S[23] = 0.0f;
-        wave_sums_by_row<NMOM>(S);
-        if ((lane & 15) == 15) {
-            float* dst = (float*)red_mom + wave * NMOM + (lane >> 4) * (NMOM / 4);
-            for (int j = 0; j < NMOM / 4; ++j) dst[j] = S[j];
-        }
-    }
+    mom_wave_partials(c, m, r, Cd, Dd, V, wave, lane, red_mom);
     __syncthreads();
 
     // momentum conservation constraint, one lane per body
-    if (body_lane) {
-        float T[NMOM];
-        sum_wave_partials<NMOM / 4, MOM_UNROLL>(red_mom, bl_w0, bl_nw, T);
-        const float Mb = bl_M, im = frcp(Mb);
-        float cb[3], Db[3], cab[3], dvb[3] = {0.0f, 0.0f, 0.0f}, wb[3] = {0.0f, 0.0f, 0.0f};
-        for (int j = 0; j < 3; ++j) {
-            cb[j] = T[j] * im;                   // c_bsm - c_i
-            Db[j] = T[3 + j] * im;               // mean shape-matching shift
-            cab[j] = cb[j] + Db[j];              // c_asm - c_i
-        }
-        // Eq. (4): dv = (P_bsm - P_asm) / M,  P_asm - P_bsm = sum m D / dt
-        if (!(c.flags & kFlagNoLinMom))
-            for (int j = 0; j < 3; ++j) dvb[j] = -T[3 + j] * c.inv_h * im;
-        // Eq. (5): omega = I^-1 (L_asm - L_bsm); the difference is formed from
-        // the small quantities: (sum m r_b x D)/dt + sum m D x v_b - Db x P_bsm
-        if (!(c.flags & kFlagNoAngMom)) {
-            float cbxD[3], DbxP[3], dL[3], I6[6];
-            cross(cb, &T[3], cbxD);
-            cross(Db, &T[6], DbxP);
-            for (int j = 0; j < 3; ++j) dL[j] = (T[9 + j] - cbxD[j]) * c.inv_h + T[12 + j] - DbxP[j];
-            // parallel-axis shift of the inertia from c_i to c_asm
-            I6[0] = T[15] - Mb * (cab[1] * cab[1] + cab[2] * cab[2]);
-            I6[1] = T[16] - Mb * (cab[0] * cab[0] + cab[2] * cab[2]);
-            I6[2] = T[17] - Mb * (cab[0] * cab[0] + cab[1] * cab[1]);
-            I6[3] = T[18] + Mb * cab[0] * cab[1];
-            I6[4] = T[19] + Mb * cab[0] * cab[2];
-            I6[5] = T[20] + Mb * cab[1] * cab[2];
-            const float scale = fmaxf(I6[0] + I6[1] + I6[2], Mb * c.two_r * c.two_r);
-            solve_inertia(I6, dL, scale, wb);
-        }
-        for (int j = 0; j < 3; ++j) {
-            body_mom[lane * 9 + j] = dvb[j];
-            body_mom[lane * 9 + 3 + j] = wb[j];
-            body_mom[lane * 9 + 6 + j] = cab[j];
-        }
-    }
+    if (body_lane) body_momentum<MOM_UNROLL>(c, bl_w0, bl_nw, bl_M, red_mom, &body_mom[lane * 9]);
     __syncthreads();
     if (!act) return;
-    float dv[3], w[3], ca[3];
-    for (int j = 0; j < 3; ++j) {
-        dv[j] = body_mom[lb * 9 + j];
-        w[j] = body_mom[lb * 9 + 3 + j];
-        ca[j] = body_mom[lb * 9 + 6 + j];
+    particle_update(c, &body_mom[lb * 9], x0, del, V, r, Cd, Dd, n, i, dn, vn);
+}
+
+// A body of more than 4 and at most kMaxWaves waves in a workgroup of 4
+// waves.  Such workgroups come first in the launch, so they start first and
+// their longer run overlaps the other workgroups'.  Wave w takes the body's
+// chunks of 64 particles w, w + 4, w + 8, w + 12, and for each does what one
+// wave of iterate_body does for its particles, with the chunk's partial sums
+// in the LDS slots of the wave it stands for: the body's sums and arithmetic
+// are those of a workgroup of kMaxWaves waves.  Between the phases a
+// particle's contact correction and goal offset wait in its own slots of the
+// output arrays (X_{i+1} - X_init and V_{i+1}), which its last phase
+// overwrites; its other data is read again.
+template <int SM_UNROLL, int MOM_UNROLL>
+__device__ __forceinline__ void iterate_chunked(const Scene& s, const StepConsts& c, int src, int it)
+{
+    __shared__ float4 red_sm[kMaxWaves * kNSm / 4];
+    __shared__ double red_sm64[kMaxWaves * kNSm];
+    __shared__ float4 red_mom[kMaxWaves * kNMom / 4];
+    __shared__ float body_sm[12];
+    __shared__ float body_mom[9];
+    __shared__ double body_rd[12];
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int waves = (int)(blockDim.x >> 6);
+    const int b = s.block_body[2 * blockIdx.x];
+    const int s0 = s.body_start[b], e0 = s.body_start[b + 1];
+    const int nw = (e0 - s0 + 63) >> 6;
+    const bool wide = e0 - s0 > 64 * kWideBodyWaves;
+    const size_t n = (size_t)s.n;
+    const float* dl = s.dl[src];
+    const float* vl = s.vel[src];
+    float* dn = s.dl[src ^ 1];
+    float* vn = s.vel[src ^ 1];
+    const float anc[3] = {s.x0[s0], s.x0[n + s0], s.x0[2 * n + s0]};   // body anchor
+    const uint32_t avg = (c.flags >> kAvgShift) & 3u;
+
+    const bool body_lane = threadIdx.x == 0;
+    float bl_M = 1.0f, Rprev[9], mq3[3];
+    double bl_M64 = 1.0;
+    if (body_lane) {
+        bl_M = s.body_mass[b];
+        bl_M64 = s.body_mass64[b];
+        for (int j = 0; j < 3; ++j) mq3[j] = s.body_mq[3 * (size_t)b + j];
+        if (it > 0)
+            for (int j = 0; j < 9; ++j) Rprev[j] = s.body_rot[9 * (size_t)b + j];
     }
-    float ra[3], wr[3];
-    for (int j = 0; j < 3; ++j) ra[j] = r[j] + Cd[j] + Dd[j] - ca[j];
-    cross(w, ra, wr);
-    for (int j = 0; j < 3; ++j) {
-        const float step = Cd[j] + Dd[j];
-        const float dvi = dv[j] - wr[j];
-        const float dnew = (del[j] + step) + c.h * dvi;
-        dn[j * n + i] = dnew;
-        if (c.flags & kFlagStdVelocity) {
-            // standard PBD: V = (X_{i+1} - X_init) / dt in world FP32 coordinates
-            const float xw = x0[j] + dnew;
-            vn[j * n + i] = (xw - x0[j]) * c.inv_h;
-        } else {
-            vn[j * n + i] = (V[j] + step * c.inv_h) + dvi;
+
+    // contacts, then the chunk's shape-matching partials
+    for (int k = wave; k < nw; k += waves) {
+        const int i = s0 + 64 * k + lane;
+        const bool act = i < e0;
+        float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, q[3] = {0.0f, 0.0f, 0.0f};
+        float m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
+        if (act) {
+            for (int j = 0; j < 3; ++j) {
+                x0[j] = s.x0[j * n + i];
+                del[j] = dl[j * n + i];
+                q[j] = s.q[j * n + i];
+            }
+            m = s.mass[i];
+            contact_correction<false>(s, c, dl, avg, n, i, x0, del, m, Cd);
+            for (int j = 0; j < 3; ++j) dn[j * n + i] = Cd[j];
         }
+        sm_wave_partials<true>(wide, m, x0, anc, del, q, k, lane, red_sm, red_sm64);
+    }
+    __syncthreads();
+    if (body_lane)
+        body_shape_match<true, SM_UNROLL>(s, it, b, 0, nw, bl_M, bl_M64, mq3, Rprev, red_sm, red_sm64, body_sm,
+                                          body_rd);
+    __syncthreads();
+    float cyv[3];
+    for (int j = 0; j < 3; ++j) cyv[j] = body_sm[9 + j];
+
+    // goal offsets and the chunk's momentum partials
+    for (int k = wave; k < nw; k += waves) {
+        const int i = s0 + 64 * k + lane;
+        const bool act = i < e0;
+        float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
+        float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
+        if (act) {
+            for (int j = 0; j < 3; ++j) {
+                x0[j] = s.x0[j * n + i];
+                del[j] = dl[j * n + i];
+                V[j] = vl[j * n + i];
+                q[j] = s.q[j * n + i];
+                Cd[j] = dn[j * n + i];
+            }
+            m = s.mass[i];
+        }
+        float r[3], Dd[3] = {0.0f, 0.0f, 0.0f};
+        for (int j = 0; j < 3; ++j) r[j] = ((x0[j] - anc[j]) + del[j]) - cyv[j];
+        if (act) {
+            goal_offset(body_rd, q, x0, anc, del, Dd);
+            for (int j = 0; j < 3; ++j) vn[j * n + i] = Dd[j];
+        }
+        mom_wave_partials(c, m, r, Cd, Dd, V, k, lane, red_mom);
+    }
+    __syncthreads();
+    if (body_lane) body_momentum<MOM_UNROLL>(c, 0, nw, bl_M, red_mom, body_mom);
+    __syncthreads();
+
+    for (int k = wave; k < nw; k += waves) {
+        const int i = s0 + 64 * k + lane;
+        if (i >= e0) continue;
+        float x0[3], del[3], V[3], Cd[3], Dd[3], r[3];
+        for (int j = 0; j < 3; ++j) {
+            x0[j] = s.x0[j * n + i];
+            del[j] = dl[j * n + i];
+            V[j] = vl[j * n + i];
+            Cd[j] = dn[j * n + i];
+            Dd[j] = vn[j * n + i];
+        }
+        for (int j = 0; j < 3; ++j) r[j] = ((x0[j] - anc[j]) + del[j]) - cyv[j];
+        particle_update(c, body_mom, x0, del, V, r, Cd, Dd, n, i, dn, vn);
     }
 }
 
@@ -984,14 +1153,19 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 template <bool MULTI, bool WIDE>
 __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<MULTI, WIDE, 4, 4>(s, c, src, it);
+    iterate_body<MULTI, WIDE, 4, 4>(s, c, src, it, xcd_block());
 }
 
-// (its bodies span at most 4 waves: never wide)
+// 4-wave workgroups: the first s.n_chunked take one body of more than 4
+// waves each, in chunks; the others bodies of up to 4 waves (never wide)
 __global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
-    iterate_body<false, false, 2, 2>(s, c, src, it);
+    if ((int)blockIdx.x < s.n_chunked) {
+        iterate_chunked<4, 4>(s, c, src, it);
+        return;
+    }
+    iterate_body<false, false, 2, 2>(s, c, src, it, xcd_block_from(s.n_chunked));
 }
 
 // ---------------------------------------------------------------------------
@@ -1463,20 +1637,6 @@ void launch_iterate_timed(const Scene& s, const StepConsts& c, int src, int it, 
         hipExtLaunchKernelGGL((k_iterate<false, false>), grid, block, 0, stream, t0, t1, 0, s, c, src, it);
 }
 
-// One Jacobi iteration: s's launch, then s2's (if any).  t0 / t1 (or null):
-// events bound to the begin and end of s's launch.  (Run side by side on two
-// streams, the two launches took longer: the second one's 16-wave
-// workgroups wait for CUs that the first one's fill.)
-void launch_pair(const Scene& s, const Scene* s2, const StepConsts& c, int src, int it, hipStream_t stream,
-                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
-{
-    if (t0 || t1)
-        launch_iterate_timed(s, c, src, it, stream, t0, t1);
-    else
-        launch_iterate(s, c, src, it, stream);
-    if (s2) launch_iterate(*s2, c, src, it, stream);
-}
-
 }  // namespace
 
 hipError_t enqueue_zero(void* p, size_t bytes, hipStream_t stream)
@@ -1503,8 +1663,7 @@ hipError_t enqueue_init_tables(const Scene& s, size_t table, hipStream_t stream)
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
-                              hipStream_t stream)
+hipError_t enqueue_iterations(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     if (s.resident_iterate) {       // each launch: all K iterations
@@ -1517,13 +1676,13 @@ hipError_t enqueue_iterations(const Scene& s, const Scene* s2, const StepConsts&
     }
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        launch_pair(s, s2, c, src, it, stream);
+        launch_iterate(s, c, src, it, stream);
         src ^= 1;
     }
     return hipGetLastError();
 }
 
-hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
+hipError_t enqueue_iterations_timed(const Scene& s, const StepConsts& c, int iterations, int count,
                                     hipStream_t stream, const hipEvent_t* t0, const hipEvent_t* t1)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
@@ -1537,7 +1696,7 @@ hipError_t enqueue_iterations_timed(const Scene& s, const Scene* s2, const StepC
     }
     int src = 0;
     for (int it = 0; it < count; ++it) {
-        launch_pair(s, s2, c, src, it, stream, t0[it], t1[it]);
+        launch_iterate_timed(s, c, src, it, stream, t0[it], t1[it]);
         src ^= 1;
     }
     return hipGetLastError();
@@ -1554,8 +1713,7 @@ int resident_iterate_capacity(int waves_per_block)
     return per_cu * cus;
 }
 
-hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c, int iterations, int count,
-                            hipStream_t stream)
+hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations, int count, hipStream_t stream)
 {
     if (s.n <= 0 || count <= 0) return hipSuccess;
     const bool multi = s.pscene != nullptr;
@@ -1609,7 +1767,7 @@ hipError_t enqueue_substeps(const Scene& s, const Scene* s2, const StepConsts& c
         }
         int src = 0;
         for (int it = 0; it < iterations; ++it) {
-            launch_pair(s, s2, c, src, it, stream);
+            launch_iterate(s, c, src, it, stream);
             src ^= 1;
         }
     }

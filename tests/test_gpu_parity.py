@@ -256,8 +256,8 @@ def test_dense_pile_16_substeps_of_the_first_4_frames(orc):
     s = _gpu_solver(sc)
     info = s.info()
     assert info.iteration_kernel == 1          # 20k bodies oversubscribe the GPU
-    assert info.waves_per_block == 4           # bodies of up to 4 waves in 4-wave workgroups, the rest apart
-    assert int(np.diff(sc.body_start).max()) > 256
+    assert info.waves_per_block == 4           # 4-wave workgroups; a body of more than 4 waves in chunks
+    assert int(np.diff(sc.body_start).max()) > 512            # chunked bodies with FP64 sums among them
     picks = [int(round(k)) for k in np.linspace(0, 4 * sc.substeps - 1, 16)]
     assert min(_sampled_gate(orc, sc, picks, s, "dense_pile")) >= 1
 
@@ -296,6 +296,47 @@ def test_ragged_body_sizes(orc, sizes):
     sc = _touching_bodies(sizes)
     _, _, _, c = check_substep(orc, sc, sc.x, sc.v, label="ragged %s" % sizes)
     assert c >= (1 if len(sizes) > 1 else 0)
+
+
+def _row_beside_fillers(sizes, seed=3, fillers=5000):
+    """The touching row of `sizes` beside `fillers` bodies of 8 particles (2 x
+    2 x 2 lattices pressed slightly into the ground, in a grid away from the
+    row, 4r apart): one wave each, enough of them that the iteration grid
+    oversubscribes the GPU, so the 4-wave packing of the 80-VGPR kernel is
+    taken."""
+    row = _touching_bodies(sizes, seed=seed)
+    r = row.radius
+    parts, vels, masses = [], [], []
+    for b in range(row.n_bodies):
+        s0, s1 = int(row.body_start[b]), int(row.body_start[b + 1])
+        parts.append(row.x[:, s0:s1].astype(np.float64))
+        vels.append(row.v[:, s0].astype(np.float64))
+        masses.append(float(row.mass[s0]))
+    cube = scenes.lattice_box(2, 2, 2, 2 * r)
+    cube = cube - cube.mean(axis=1, keepdims=True)
+    side = int(math.ceil(math.sqrt(fillers)))
+    rng = np.random.default_rng(seed)
+    for k in range(fillers):
+        centre = np.array([[(k % side) * 6 * r], [1.0 + (k // side) * 6 * r], [1.7 * r]])
+        parts.append(cube + centre)
+        vels.append(rng.normal(0.0, 0.05, size=3))
+        masses.append(float(rng.uniform(0.01, 0.03)))
+    return scenes.from_bodies(parts, vels, masses, radius=r)
+
+
+@pytest.mark.parametrize("flags", [0, B.FLAG_STD_VELOCITY, B.FLAG_NO_LIN_MOM, B.FLAG_NO_ANG_MOM, B.PP_AVG_OWN])
+def test_chunked_large_bodies_in_the_oversubscribed_launch(orc, flags):
+    """Bodies of 5 to 16 waves (ragged around 4, 8 and 16 waves) in contact
+    with each other, in an iteration grid that oversubscribes the GPU: each
+    is taken in chunks by one 4-wave workgroup of the 80-VGPR kernel, FP64
+    shape-matching sums for those over 8 waves; the small bodies rest on the
+    ground."""
+    sc = _row_beside_fillers([257, 300, 511, 512, 513, 640, 1000, 1024, 320, 260])
+    s = _gpu_solver(sc, flags=flags)
+    info = s.info()
+    assert info.iteration_kernel == 1 and info.waves_per_block == 4
+    _, _, _, c = check_substep(orc, sc, sc.x, sc.v, flags=flags, solver=s, label="chunked, flags %#x" % flags)
+    assert c >= 1
 
 
 def test_empty_scene():
@@ -531,9 +572,9 @@ def test_timed_iteration_launches_leave_the_state_and_next_substep_unchanged():
         s.time_iterations(B.MAX_TIMED_LAUNCHES + 1)
 
 
-def test_split_iteration_launches_graph_equals_direct_launches():
-    # 20k bodies: bodies of up to 4 waves and the larger ones in two launches
-    # per iteration, captured in the graph or enqueued directly: both agree
+def test_chunked_iteration_graph_equals_direct_launches():
+    # 20k bodies in 4-wave workgroups, the bodies of more than 4 waves taken
+    # in chunks, captured in the graph or enqueued directly: both agree
     # bitwise
     sc = scenes.dense_pile(0)
     runs = []
