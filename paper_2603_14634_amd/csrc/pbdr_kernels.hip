@@ -591,8 +591,8 @@ __device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t av
     }
     const double l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) return;
-    const double l = sqrt(l2);
-    const double il = 1.0 / l;
+    const double il = rsqrt64(l2);
+    const double l = l2 * il;
     const float nx = (float)(d[0] * il), ny = (float)(d[1] * il), nz = (float)(d[2] * il);
     const float pen = (float)(c.two_r_d - l);
     const float alpha = mq * frcp(m + mq);          // w_p / (w_p + w_q)
@@ -659,7 +659,11 @@ __device__ inline void orthonormalise64(const float* X, double* Rd)
     double det = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) det += (double)X[k] * cofactor64(X, kIdx[k][0], kIdx[k][1], kIdx[k][2], kIdx[k][3]);
-    const double id = 1.0 / det;
+    // 1 / det (about 1): the FP32 reciprocal refined by two Newton steps,
+    // each doubling its correct bits, to FP64 precision
+    double id = (double)frcp((float)det);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) id = __builtin_fma(id, __builtin_fma(-det, id, 1.0), id);
 #pragma unroll
     for (int k = 0; k < 9; ++k)
         Rd[k] = 0.5 * ((double)X[k] + cofactor64(X, kIdx[k][0], kIdx[k][1], kIdx[k][2], kIdx[k][3]) * id);

@@ -290,8 +290,8 @@ __device__ inline void contacts(const Ctx& x, int i, const float* x0, const floa
         }
         const double l2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
         if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) continue;
-        const double l = sqrt(l2);
-        const double il = 1.0 / l;
+        const double il = rsqrt64(l2);
+        const double l = l2 * il;
         const float nx = (float)(dd[0] * il), ny = (float)(dd[1] * il), nz = (float)(dd[2] * il);
         const float pen = (float)(c.two_r_d - l);
         const float mq = d.mass[gq];
