@@ -639,7 +639,7 @@ __device__ inline void sum_wave_partials(const float4* red, int w0, int nw, floa
     }
 }
 
-// The rotation of shape matching (FP32, orthogonal to about 1e-7) made
+// The rotation of shape matching (FP32, orthogonal to a few 1e-7) made
 // orthogonal to FP64 precision by one Newton step X <- (X + X^-T) / 2 (the
 // iteration that converges to the orthogonal polar factor, quadratically);
 // applied in FP64, so that it moves a body's goal rigidly: a rotation that is
@@ -779,19 +779,26 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
 {
     const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
     const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
-    for (int pl = 0; pl < c.n_planes; ++pl) {
-        if (plane_far(c, pl, x0, del, mag)) continue;
-        const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
-        const float un = nx * del[0] + ny * del[1] + nz * del[2];
-        const double e = plane_gap(c, pl, x0, del);
-        if (!(e < c.radius_d)) continue;
-        const float pen = (float)(c.radius_d - e);
-        const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
-        const float ut2 = ux * ux + uy * uy + uz * uz;
-        const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
-        Cd[0] += pen * nx - f * ux;
-        Cd[1] += pen * ny - f * uy;
-        Cd[2] += pen * nz - f * uz;
+    // the FP32 pre-filter over all planes first, so that the FP64 work below
+    // is skipped by waves with no particle near a plane
+    uint32_t near = 0u;
+    for (int pl = 0; pl < c.n_planes; ++pl)
+        if (!plane_far(c, pl, x0, del, mag)) near |= 1u << pl;
+    if (near != 0u) {
+        for (int pl = 0; pl < c.n_planes; ++pl) {
+            if (!(near & (1u << pl))) continue;
+            const float nx = c.plane_n[pl][0], ny = c.plane_n[pl][1], nz = c.plane_n[pl][2];
+            const float un = nx * del[0] + ny * del[1] + nz * del[2];
+            const double e = plane_gap(c, pl, x0, del);
+            if (!(e < c.radius_d)) continue;
+            const float pen = (float)(c.radius_d - e);
+            const float ux = del[0] - un * nx, uy = del[1] - un * ny, uz = del[2] - un * nz;
+            const float ut2 = ux * ux + uy * uy + uz * uz;
+            const float f = ut2 > 0.0f ? fminf(1.0f, mu * pen * __builtin_amdgcn_rsqf(ut2)) : 0.0f;
+            Cd[0] += pen * nx - f * ux;
+            Cd[1] += pen * ny - f * uy;
+            Cd[2] += pen * nz - f * uz;
+        }
     }
     const uint32_t ni = s.nbr_n[i];
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
@@ -808,9 +815,10 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
 
 // Shape matching of one body, on its lane: centre and covariance from the
 // partials of its waves w0 .. w0 + nw - 1, the rotation (from the second
-// iteration on refined from the previous iteration's, Rprev), then R and the
-// centre to `sm` (FP32, 12 values) and `rd` (FP64: R made orthonormal, and
-// the centre), and R kept for the next iteration.
+// iteration on refined from the previous iteration's, Rprev, by Newton steps
+// on SO(3)), made orthogonal in FP64; then R and the centre to `rd` (FP64)
+// and to `sm` (FP32, 12 values), and R's FP32 rounding kept for the next
+// iteration.
 template <bool WIDE_OK, int UNROLL>
 __device__ __forceinline__ void body_shape_match(const Scene& s, int it, int bb, int w0, int nw, float M, double M64,
                                                  const float* mq3, const float* Rprev, const float4* red32,
@@ -818,10 +826,11 @@ __device__ __forceinline__ void body_shape_match(const Scene& s, int it, int bb,
 {
     float cc[3], A[9], Rb[9];
     sm_body_sums<WIDE_OK, UNROLL>(w0, nw, M, M64, mq3, red32, red64, cc, &rd[9], A);
-    if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
+    if (!(it > 0 && polar_refine_steps(A, Rprev, Rb))) polar_rotation(A, Rb);
+    orthonormalise64(Rb, rd);
+    for (int j = 0; j < 9; ++j) Rb[j] = (float)rd[j];
     for (int j = 0; j < 9; ++j) sm[j] = Rb[j];
     for (int j = 0; j < 3; ++j) sm[9 + j] = cc[j];
-    orthonormalise64(Rb, rd);
     if (s.body_rot)
         for (int j = 0; j < 9; ++j) s.body_rot[9 * (size_t)bb + j] = Rb[j];
 }
@@ -1327,10 +1336,10 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate_resident(Scene s, St
             sm_body_sums<true, 4>(body_waves_s[2 * lane], body_waves_s[2 * lane + 1], body_M_s[lane],
                                   body_M64_s[lane], mq3, red_sm, red_sm64, cc, &body_rd[lane * 12 + 9], A);
             for (int j = 0; j < 9; ++j) Rprev[j] = body_sm[lane * 12 + j];   // (it > 0) the last iteration's
-            if (!(it > 0 && polar_refine(A, Rprev, Rb))) polar_rotation(A, Rb);
-            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = Rb[j];
-            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
+            if (!(it > 0 && polar_refine_steps(A, Rprev, Rb))) polar_rotation(A, Rb);
             orthonormalise64(Rb, &body_rd[lane * 12]);
+            for (int j = 0; j < 9; ++j) body_sm[lane * 12 + j] = (float)body_rd[lane * 12 + j];
+            for (int j = 0; j < 3; ++j) body_sm[lane * 12 + 9 + j] = cc[j];
         }
         __syncthreads();
         // goal offsets (shape matching), formed before the contacts so that

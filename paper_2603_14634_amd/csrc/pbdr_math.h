@@ -389,9 +389,10 @@ __device__ inline void polar_rotation(const float* A, float* R)
 // then restores orthogonality.  Returns false when the start is too far (the
 // step does not shrink below 3e-5 rad within two steps) or the Hessian is not
 // definite; the caller then uses polar_rotation.
-__device__ inline bool polar_refine(const float* A, const float* R0, float* R)
+// polar_refine_steps: the Newton steps alone, leaving X orthogonal to about
+// 1e-7 (for callers that make it orthogonal themselves).
+__device__ inline bool polar_refine_steps(const float* A, const float* R0, float* X)
 {
-    float X[9];
     for (int k = 0; k < 9; ++k) X[k] = R0[k];
     bool done = false;
     for (int step = 0; step < 2 && !done; ++step) {
@@ -428,7 +429,13 @@ __device__ inline bool polar_refine(const float* A, const float* R0, float* R)
             for (int b = 0; b < 3; ++b) Y[3 * a + b] = X[3 * a] * Q[b] + X[3 * a + 1] * Q[3 + b] + X[3 * a + 2] * Q[6 + b];
         for (int k = 0; k < 9; ++k) X[k] = Y[k];
     }
-    if (!done) return false;
+    return done;
+}
+
+__device__ inline bool polar_refine(const float* A, const float* R0, float* R)
+{
+    float X[9];
+    if (!polar_refine_steps(A, R0, X)) return false;
     float C[9];
     cof3(X, C);
     const float id = frcp(X[0] * C[0] + X[1] * C[1] + X[2] * C[2]);
