@@ -1157,8 +1157,8 @@ __device__ __forceinline__ void iterate_chunked(const Scene& s, const StepConsts
 }
 
 // The iteration kernel in two register budgets: the compiler's choice (about
-// 85 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
-// (6 waves per SIMD, a few values spilled) for grids that oversubscribe it,
+// 78 VGPRs, fastest when the grid fits the GPU at once), and at most 72 VGPRs
+// (7 waves per SIMD, a few values spilled) for grids that oversubscribe it,
 // where more workgroups per CU hide each other's per-body phases.
 // WIDE: some body of the launch spans more than kWideBodyWaves waves (FP64
 // sums for those bodies; the other bodies' arithmetic is the same in both
@@ -1171,7 +1171,7 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
 
 // 4-wave workgroups: the first s.n_chunked take one body of more than 4
 // waves each, in chunks; the others bodies of up to 4 waves (never wide)
-__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
+__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(7, 7)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
     if ((int)blockIdx.x < s.n_chunked) {
