@@ -144,7 +144,7 @@ typedef struct {
     int32_t iteration_blocks;     /* iteration kernel: workgroups per launch */
     int32_t max_body_particles;
     int32_t iteration_kernel;     /* 0: register-rich variant, one launch per iteration;
-                                     1: 72-VGPR variant, taken when the grid
+                                     1: 80-VGPR variant, taken when the grid
                                      oversubscribes the GPU; 2: all K iterations of a
                                      substep in one launch (the grid is resident at
                                      once, K < 64) */

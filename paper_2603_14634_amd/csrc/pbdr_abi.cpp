@@ -129,7 +129,7 @@ int radix_passes(int bits) { return std::max(1, (bits + pbdr::kRadixBits - 1) / 
 // Upper bound on the padded wave count of the iteration kernel's body packing:
 // each body needs ceil(n_b / 64) <= n_b / 64 + 1 waves.  Greedy packing into
 // workgroups of W waves wastes less than half of every workgroup it closes
-// for lack of room.  In the 4-wave packing of the 72-VGPR kernel a body of
+// for lack of room.  In the 4-wave packing of the 80-VGPR kernel a body of
 // more than 4 waves takes one workgroup of 4 waves, fewer than it needs.  The
 // last workgroup is padded by at most W - 1 waves.
 size_t max_iteration_waves(int32_t n, int32_t nb)
@@ -568,14 +568,14 @@ pbdr_status create_scene(const pbdr_params* params, const pbdr_scene_desc* desc,
     s->dev.waves_per_block = W;
     s->dev.n_iter_blocks = (int32_t)(wave_body.size() / (size_t)W);
     // More workgroups than the GPU holds at once with 4 waves per SIMD (16 per
-    // CU, the ~100-VGPR kernel): take the 72-VGPR kernel (7 waves per SIMD)
+    // CU, the ~100-VGPR kernel): take the 80-VGPR kernel (6 waves per SIMD)
     // with workgroups of 4 waves, so that more of them share a CU.  Bodies of
     // more than 4 waves then take one such workgroup each, at the front of the
     // launch, which goes over their particles in chunks of 4 waves.
     s->dev.dense_iterate = s->dev.n_iter_blocks > cus * (16 / W) ? 1 : 0;
     s->dev.wide_bodies = W > pbdr::kWideBodyWaves ? 1 : 0;
     s->dev.n_chunked = 0;
-    constexpr int kDenseWaves = 4;      // workgroup of the 72-VGPR kernel
+    constexpr int kDenseWaves = 4;      // workgroup of the 80-VGPR kernel
     if (s->dev.dense_iterate && W > kDenseWaves) {
         wave_body.clear();
         for (int32_t b = 0; b < nb; ++b) {

@@ -123,8 +123,8 @@ struct Scene {
     const float* body_mq;     // [B][3] sum of m q over the body (rest frame, ~0)
     int32_t waves_per_block;  // W: iteration workgroup = 64 W threads
     int32_t n_iter_blocks;
-    int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (72-VGPR kernel)
-    int32_t n_chunked = 0;    // 72-VGPR kernel: its first n_chunked workgroups (4 waves) take one body
+    int32_t dense_iterate;    // 1: the iteration grid oversubscribes the GPU (80-VGPR kernel)
+    int32_t n_chunked = 0;    // 80-VGPR kernel: its first n_chunked workgroups (4 waves) take one body
                               //     of more than 4 waves each (block_body holds (body, 1) for them)
     int32_t wide_bodies;      // 1: some body of the iteration launch spans more than kWideBodyWaves waves
     float* dl[2];             // [3][N] X_i - X_init, double buffered

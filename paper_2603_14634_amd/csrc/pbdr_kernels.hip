@@ -573,11 +573,12 @@ __device__ __forceinline__ double plane_gap(const StepConsts& c, int pl, const f
 // mass-weighted split of the penetration, Coulomb friction from the relative
 // displacement since X_init, and the pair weight of the averaging mode.  xq,
 // dq: the partner's X_init and X_i - X_init; mq, nq: its mass and list length.
-// Shared by both iteration kernels, with contraction limited to single
-// expressions, so that both round alike.
-__device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t avg, float mu, const float* x0,
-                                                const float* del, float m, uint32_t ni, const float* xq,
-                                                const float* dq, float mq, uint32_t nq, float* Cd)
+// The correction is sc * t (false: no contact).  Shared by all iteration
+// kernels, with contraction limited to single expressions, so that they
+// round alike.
+__device__ __forceinline__ bool pair_terms(const StepConsts& c, uint32_t avg, float mu, const float* x0,
+                                           const float* del, float m, uint32_t ni, const float* xq, const float* dq,
+                                           float mq, uint32_t nq, float& sc, float* t)
 {
 #pragma clang fp contract(on)
     // separation, distance, penetration and normal in FP64: the separation
@@ -590,7 +591,7 @@ __device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t av
         u[j] = del[j] - dq[j];
     }
     const double l2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) return;
+    if (!(l2 > 0.0) || !(l2 < c.two_r_d * c.two_r_d)) return false;
     const double il = rsqrt64(l2);
     const double l = l2 * il;
     const float nx = (float)(d[0] * il), ny = (float)(d[1] * il), nz = (float)(d[2] * il);
@@ -605,10 +606,21 @@ __device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t av
         wgt = frcp((float)(ni > nq ? ni : nq));
     else if (avg == 1u)
         wgt = frcp((float)ni);
-    const float sc = alpha * wgt;
-    Cd[0] += sc * (pen * nx - f * ux);
-    Cd[1] += sc * (pen * ny - f * uy);
-    Cd[2] += sc * (pen * nz - f * uz);
+    sc = alpha * wgt;
+    t[0] = pen * nx - f * ux;
+    t[1] = pen * ny - f * uy;
+    t[2] = pen * nz - f * uz;
+    return true;
+}
+
+__device__ __forceinline__ void pair_correction(const StepConsts& c, uint32_t avg, float mu, const float* x0,
+                                                const float* del, float m, uint32_t ni, const float* xq,
+                                                const float* dq, float mq, uint32_t nq, float* Cd)
+{
+#pragma clang fp contract(on)
+    float sc, t[3];
+    if (!pair_terms(c, avg, mu, x0, del, m, ni, xq, dq, mq, nq, sc, t)) return;
+    for (int j = 0; j < 3; ++j) Cd[j] += sc * t[j];
 }
 
 // Sum of the per-wave partials (NV float4 per wave) of a body's waves w0 ..
@@ -771,13 +783,11 @@ constexpr int kNSm = 12, kNMom = 24;       // per-wave partial sums (float4 alig
 
 // Contact corrections of particle i from X_i (Jacobi): planes (constraint
 // (1)) and particles of other bodies (constraint (2)), friction from the
-// displacement since X_init; accumulated into Cd.
-template <bool MULTI>
-__device__ __forceinline__ void contact_correction(const Scene& s, const StepConsts& c, const float* dl, uint32_t avg,
-                                                   size_t n, int i, const float* x0, const float* del, float m,
-                                                   float* Cd)
+// displacement since X_init; accumulated into Cd, the planes first, then the
+// partners in list order.
+__device__ __forceinline__ void plane_contacts(const StepConsts& c, float mu, const float* x0, const float* del,
+                                               float* Cd)
 {
-    const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
     const float mag = fabsf(x0[0]) + fabsf(x0[1]) + fabsf(x0[2]) + fabsf(del[0]) + fabsf(del[1]) + fabsf(del[2]);
     // the FP32 pre-filter over all planes first, so that the FP64 work below
     // is skipped by waves with no particle near a plane
@@ -800,6 +810,15 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
             Cd[2] += pen * nz - f * uz;
         }
     }
+}
+
+template <bool MULTI>
+__device__ __forceinline__ void contact_correction(const Scene& s, const StepConsts& c, const float* dl, uint32_t avg,
+                                                   size_t n, int i, const float* x0, const float* del, float m,
+                                                   float* Cd)
+{
+    const float mu = MULTI ? s.mscene[s.pscene[i]].mu : c.mu;   // multi-scene mode: per scene
+    plane_contacts(c, mu, x0, del, Cd);
     const uint32_t ni = s.nbr_n[i];
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
     for (uint32_t sl = 0; sl < cnt; ++sl) {
@@ -810,6 +829,65 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
             dq[j] = dl[j * n + jq];
         }
         pair_correction(c, avg, mu, x0, del, m, ni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, Cd);
+    }
+}
+
+// The partner contacts of one wave's particles (one body's, single-scene
+// mode), spread over its lanes.  A wave that loops over each particle's list
+// makes as many passes as its longest list (about two in a settled pile,
+// where most particles have none); here the wave's (particle, slot) pairs are
+// numbered in particle order, then slot order (a scan of the list lengths),
+// lane l computes pair base + l of each window of 64, and every particle then
+// adds the corrections of its own pairs in slot order, as the loop does.
+// Called by all 64 lanes (lane swaps); act: the lane holds a particle.
+__device__ __forceinline__ void pair_contacts_spread(const Scene& s, const StepConsts& c, const float* dl,
+                                                     uint32_t avg, size_t n, int i, int lane, bool act,
+                                                     const float* x0, const float* del, float m, float* Cd)
+{
+#pragma clang fp contract(on)
+    const uint32_t ni = act ? s.nbr_n[i] : 0u;
+    const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
+    const uint32_t incl = wave_inclusive_scan(cnt);
+    const uint32_t off = incl - cnt;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    for (uint32_t base = 0; base < total; base += 64u) {
+        const uint32_t p = base + (uint32_t)lane;
+        // the particle (lane) of pair p: the first lane whose inclusive count exceeds p
+        int o = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1)
+            if ((uint32_t)__shfl((int)incl, o + step - 1, 64) <= p) o += step;
+        o = o < 63 ? o : 63;
+        float ox[3], od[3];
+        for (int j = 0; j < 3; ++j) {
+            ox[j] = __shfl(x0[j], o, 64);
+            od[j] = __shfl(del[j], o, 64);
+        }
+        const float om = __shfl(m, o, 64);
+        const uint32_t oni = (uint32_t)__shfl((int)ni, o, 64), ooff = (uint32_t)__shfl((int)off, o, 64);
+        float sc = 0.0f, t[3] = {0.0f, 0.0f, 0.0f};
+        if (p < total) {
+            const int io = i - lane + o;             // the wave's particles are consecutive
+            const uint32_t jq = s.nbr[(size_t)(p - ooff) * n + io];
+            float xq[3], dq[3];
+            for (int j = 0; j < 3; ++j) {
+                xq[j] = s.x0[j * n + jq];
+                dq[j] = dl[j * n + jq];
+            }
+            if (!pair_terms(c, avg, c.mu, ox, od, om, oni, xq, dq, s.mass[jq], avg == 0u ? s.nbr_n[jq] : 0u, sc, t))
+                sc = 0.0f;                           // (a contact has sc > 0)
+        }
+        // this particle's pairs in the window: lanes lo - base .. hi - base - 1
+        const uint32_t lo = off > base ? off : base, hi = incl < base + 64u ? incl : base + 64u;
+        const uint32_t mine = hi > lo ? hi - lo : 0u;
+        for (uint32_t k = 0; __any(k < mine); ++k) {
+            const int src = (int)(lo - base + k);
+            const float a = __shfl(sc, src, 64);
+            float b[3];
+            for (int j = 0; j < 3; ++j) b[j] = __shfl(t[j], src, 64);
+            if (k < mine && a != 0.0f)
+                for (int j = 0; j < 3; ++j) Cd[j] += a * b[j];
+        }
     }
 }
 
@@ -951,7 +1029,7 @@ __device__ __forceinline__ void particle_update(const StepConsts& c, const float
 // previous iteration's.  blk: the workgroup's index in the packing.
 // SM_UNROLL / MOM_UNROLL: waves whose partial sums the per-body lane reads
 // from LDS at once.
-template <bool MULTI, bool WIDE_OK, int SM_UNROLL, int MOM_UNROLL>
+template <bool MULTI, bool WIDE_OK, int SM_UNROLL, int MOM_UNROLL, bool SPREAD = false>
 __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c, int src, int it, int blk)
 {
     __shared__ float4 red_sm[kMaxWaves * kNSm / 4];
@@ -986,7 +1064,30 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
     const float anc[3] = {ax, ay, az};
     const uint32_t avg = (c.flags >> kAvgShift) & 3u;
 
-    // per-body lane of wave 0: body slot `lane` of this workgroup
+    float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
+    float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+        for (int j = 0; j < 3; ++j) {
+            x0[j] = s.x0[j * n + i];
+            del[j] = dl[j * n + i];
+            V[j] = vl[j * n + i];
+            q[j] = s.q[j * n + i];
+        }
+        m = s.mass[i];
+    }
+    if (SPREAD) {               // single-scene mode: partner contacts spread over the wave's lanes
+        if (act) plane_contacts(c, c.mu, x0, del, Cd);
+        pair_contacts_spread(s, c, dl, avg, n, i, lane, act, x0, del, m, Cd);
+    } else if (act) {
+        contact_correction<MULTI>(s, c, dl, avg, n, i, x0, del, m, Cd);
+    }
+
+    // shape matching on X_i: centre and covariance in one reduction,
+    // A = sum m (x - c) q^T = sum m y q^T - c (sum m q)^T, y = x - anchor
+    sm_wave_partials<WIDE_OK>(wide, m, x0, anc, del, q, wave, lane, red_sm, red_sm64);
+
+    // per-body lane of wave 0: body slot `lane` of this workgroup (its data
+    // is loaded here, so that it holds no registers through the contacts)
     const bool body_lane = wave == 0 && lane < blk_nb;
     const int bb = blk_b0 + (body_lane ? lane : 0);
     int bl_w0 = 0, bl_nw = 0;
@@ -1001,23 +1102,6 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
         if (it > 0)
             for (int j = 0; j < 9; ++j) Rprev[j] = s.body_rot[9 * (size_t)bb + j];
     }
-
-    float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
-    float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
-    if (act) {
-        for (int j = 0; j < 3; ++j) {
-            x0[j] = s.x0[j * n + i];
-            del[j] = dl[j * n + i];
-            V[j] = vl[j * n + i];
-            q[j] = s.q[j * n + i];
-        }
-        m = s.mass[i];
-    }
-    if (act) contact_correction<MULTI>(s, c, dl, avg, n, i, x0, del, m, Cd);
-
-    // shape matching on X_i: centre and covariance in one reduction,
-    // A = sum m (x - c) q^T = sum m y q^T - c (sum m q)^T, y = x - anchor
-    sm_wave_partials<WIDE_OK>(wide, m, x0, anc, del, q, wave, lane, red_sm, red_sm64);
     __syncthreads();
     if (body_lane)              // one lane per body: centre, covariance, rotation
         body_shape_match<WIDE_OK, SM_UNROLL>(s, it, bb, bl_w0, bl_nw, bl_M, bl_M64, mq3, Rprev, red_sm, red_sm64,
@@ -1157,9 +1241,10 @@ __device__ __forceinline__ void iterate_chunked(const Scene& s, const StepConsts
 }
 
 // The iteration kernel in two register budgets: the compiler's choice (about
-// 78 VGPRs, fastest when the grid fits the GPU at once), and at most 72 VGPRs
-// (7 waves per SIMD, a few values spilled) for grids that oversubscribe it,
-// where more workgroups per CU hide each other's per-body phases.
+// 78 VGPRs, fastest when the grid fits the GPU at once), and at most 80 VGPRs
+// (6 waves per SIMD, a few values spilled) for grids that oversubscribe it,
+// where more workgroups per CU hide each other's per-body phases, and whose
+// partner contacts are spread over each wave's lanes.
 // WIDE: some body of the launch spans more than kWideBodyWaves waves (FP64
 // sums for those bodies; the other bodies' arithmetic is the same in both
 // instances)
@@ -1170,15 +1255,16 @@ __global__ void __launch_bounds__(64 * kMaxWaves) k_iterate(Scene s, StepConsts 
 }
 
 // 4-wave workgroups: the first s.n_chunked take one body of more than 4
-// waves each, in chunks; the others bodies of up to 4 waves (never wide)
-__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(7, 7)))
+// waves each, in chunks; the others bodies of up to 4 waves (never wide),
+// with the partner contacts spread over each wave's lanes
+__global__ void __launch_bounds__(64 * kMaxWaves) __attribute__((amdgpu_waves_per_eu(6, 6)))
 k_iterate_dense(Scene s, StepConsts c, int src, int it)
 {
     if ((int)blockIdx.x < s.n_chunked) {
         iterate_chunked<4, 4>(s, c, src, it);
         return;
     }
-    iterate_body<false, false, 2, 2>(s, c, src, it, xcd_block_from(s.n_chunked));
+    iterate_body<false, false, 2, 2, true>(s, c, src, it, xcd_block_from(s.n_chunked));
 }
 
 // ---------------------------------------------------------------------------

@@ -302,7 +302,7 @@ def _row_beside_fillers(sizes, seed=3, fillers=5000):
     """The touching row of `sizes` beside `fillers` bodies of 8 particles (2 x
     2 x 2 lattices pressed slightly into the ground, in a grid away from the
     row, 4r apart): one wave each, enough of them that the iteration grid
-    oversubscribes the GPU, so the 4-wave packing of the 72-VGPR kernel is
+    oversubscribes the GPU, so the 4-wave packing of the 80-VGPR kernel is
     taken."""
     row = _touching_bodies(sizes, seed=seed)
     r = row.radius
@@ -328,7 +328,7 @@ def _row_beside_fillers(sizes, seed=3, fillers=5000):
 def test_chunked_large_bodies_in_the_oversubscribed_launch(orc, flags):
     """Bodies of 5 to 16 waves (ragged around 4, 8 and 16 waves) in contact
     with each other, in an iteration grid that oversubscribes the GPU: each
-    is taken in chunks by one 4-wave workgroup of the 72-VGPR kernel, FP64
+    is taken in chunks by one 4-wave workgroup of the 80-VGPR kernel, FP64
     shape-matching sums for those over 8 waves; the small bodies rest on the
     ground."""
     sc = _row_beside_fillers([257, 300, 511, 512, 513, 640, 1000, 1024, 320, 260])
