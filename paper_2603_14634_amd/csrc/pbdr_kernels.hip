@@ -841,11 +841,11 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
 // adds the corrections of its own pairs in slot order, as the loop does.
 // Called by all 64 lanes (lane swaps); act: the lane holds a particle.
 __device__ __forceinline__ void pair_contacts_spread(const Scene& s, const StepConsts& c, const float* dl,
-                                                     uint32_t avg, size_t n, int i, int lane, bool act,
-                                                     const float* x0, const float* del, float m, float* Cd)
+                                                     uint32_t avg, size_t n, int i, int lane, uint32_t ni,
+                                                     uint32_t j0, const float* x0, const float* del, float m,
+                                                     float* Cd)
 {
 #pragma clang fp contract(on)
-    const uint32_t ni = act ? s.nbr_n[i] : 0u;
     const uint32_t cnt = ni < (uint32_t)c.nbr_cap ? ni : (uint32_t)c.nbr_cap;
     const uint32_t incl = wave_inclusive_scan(cnt);
     const uint32_t off = incl - cnt;
@@ -865,10 +865,11 @@ __device__ __forceinline__ void pair_contacts_spread(const Scene& s, const StepC
         }
         const float om = __shfl(m, o, 64);
         const uint32_t oni = (uint32_t)__shfl((int)ni, o, 64), ooff = (uint32_t)__shfl((int)off, o, 64);
+        const uint32_t oj0 = (uint32_t)__shfl((int)j0, o, 64);
         float sc = 0.0f, t[3] = {0.0f, 0.0f, 0.0f};
         if (p < total) {
             const int io = i - lane + o;             // the wave's particles are consecutive
-            const uint32_t jq = s.nbr[(size_t)(p - ooff) * n + io];
+            const uint32_t jq = p == ooff ? oj0 : s.nbr[(size_t)(p - ooff) * n + io];
             float xq[3], dq[3];
             for (int j = 0; j < 3; ++j) {
                 xq[j] = s.x0[j * n + jq];
@@ -1066,6 +1067,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
 
     float x0[3] = {0.0f, 0.0f, 0.0f}, del[3] = {0.0f, 0.0f, 0.0f}, V[3] = {0.0f, 0.0f, 0.0f};
     float q[3] = {0.0f, 0.0f, 0.0f}, m = 0.0f, Cd[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t ni = 0u, j0 = 0u;
     if (act) {
         for (int j = 0; j < 3; ++j) {
             x0[j] = s.x0[j * n + i];
@@ -1074,10 +1076,14 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
             q[j] = s.q[j * n + i];
         }
         m = s.mass[i];
+        if (SPREAD) {
+            ni = s.nbr_n[i];
+            j0 = s.nbr[i];
+        }
     }
     if (SPREAD) {               // single-scene mode: partner contacts spread over the wave's lanes
         if (act) plane_contacts(c, c.mu, x0, del, Cd);
-        pair_contacts_spread(s, c, dl, avg, n, i, lane, act, x0, del, m, Cd);
+        pair_contacts_spread(s, c, dl, avg, n, i, lane, ni, j0, x0, del, m, Cd);
     } else if (act) {
         contact_correction<MULTI>(s, c, dl, avg, n, i, x0, del, m, Cd);
     }
