@@ -34,3 +34,28 @@ def touching_bodies(sizes, r=0.01, seed=0, speed=0.3, pen=0.6, **kw):
         vels.append(rng.normal(0, speed, size=3))
         masses.append(rng.uniform(0.01, 0.03))
     return scenes.from_bodies(parts, vels, masses, radius=r, **kw)
+
+
+def interleaved_lattices(n_pairs, r=0.01, depth=0.2, seed=0, **kw):
+    """Pairs of 4 x 4 x 4 lattices, the second shifted by half the x spacing
+    into the first: the x spacing is (4 - 2 depth) r, so a particle between two
+    of the other body's on its x row is 2r - depth r from each (two contacts),
+    one at a row's end from one.  112 contact pairs per body; the pairs sit in
+    a grid 24r / 12r / 12r apart, above the ground."""
+    rng = np.random.default_rng(seed)
+    pitch = (4.0 - 2.0 * depth) * r
+    g = np.arange(4)
+    X, Y, Z = np.meshgrid(g * pitch, g * 2.5 * r, g * 2.5 * r, indexing="ij")
+    lattice = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    side = int(math.ceil(n_pairs ** (1.0 / 3.0)))
+    parts, vels, masses = [], [], []
+    for k in range(n_pairs):
+        o = np.array([[(k % side) * 24 * r], [((k // side) % side) * 12 * r], [0.2 + (k // (side * side)) * 12 * r]])
+        a = lattice + o
+        b = a.copy()
+        b[0] += pitch / 2.0
+        for pts in (a, b):
+            parts.append(pts)
+            vels.append(rng.normal(0.0, 0.02, size=3))
+            masses.append(float(rng.uniform(0.01, 0.03)))
+    return scenes.from_bodies(parts, vels, masses, radius=r, **kw)
