@@ -839,7 +839,9 @@ __device__ __forceinline__ void contact_correction(const Scene& s, const StepCon
 // numbered in particle order, then slot order (a scan of the list lengths),
 // lane l computes pair base + l of each window of 64, and every particle then
 // adds the corrections of its own pairs in slot order, as the loop does.
-// Called by all 64 lanes (lane swaps); act: the lane holds a particle.
+// Called by all 64 lanes (lane swaps).  ni, j0: the lane's list length and
+// first partner id, loaded with its particle's data (0 for a lane without a
+// particle), so that a pair of slot 0 takes its partner's id from that lane.
 __device__ __forceinline__ void pair_contacts_spread(const Scene& s, const StepConsts& c, const float* dl,
                                                      uint32_t avg, size_t n, int i, int lane, uint32_t ni,
                                                      uint32_t j0, const float* x0, const float* del, float m,
@@ -1076,7 +1078,7 @@ __device__ __forceinline__ void iterate_body(const Scene& s, const StepConsts& c
             q[j] = s.q[j * n + i];
         }
         m = s.mass[i];
-        if (SPREAD) {
+        if (SPREAD) {           // list length and first partner: no load waits on another
             ni = s.nbr_n[i];
             j0 = s.nbr[i];
         }
