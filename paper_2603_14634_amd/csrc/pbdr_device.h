@@ -19,12 +19,15 @@ constexpr int kWideBodyWaves = 8;
 constexpr int kRadixBits = 8;                   // key sort: digit width
 constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kMaxRadixPasses = 4;               // keys of up to 32 bits
-constexpr int kHistChunk = 16384;                // keys per workgroup of the digit histogram
 // A sort tile is kBlock threads of `items` keys each: 16 from kRadixLargeFrom
 // keys on (longer runs of one digit per tile, so longer runs of writes), 4
 // below (more tiles to fill the GPU).
 constexpr size_t kRadixLargeFrom = size_t(1) << 20;
 inline uint32_t radix_items_for(size_t n) { return n >= kRadixLargeFrom ? 16u : 4u; }
+// The digit histogram takes 16 keys per thread, in workgroups of 1024 threads
+// from kRadixLargeFrom keys on (fewer workgroups adding to the counts), 256
+// below (more workgroups for a small sort); a workgroup's keys are whole tiles.
+inline int radix_hist_threads_for(size_t n) { return n >= kRadixLargeFrom ? 1024 : 256; }
 inline size_t radix_tiles_for(size_t n)
 {
     const size_t t = (size_t)kBlock * radix_items_for(n);

@@ -172,21 +172,24 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* tmp)
 }
 
 
-// Digit counts of every pass over all keys: each workgroup counts a chunk of
-// kHistChunk keys in LDS (16 consecutive keys per thread, equal digits of a
-// run counted once) and adds its non-zero counts to the global table.  It
-// also writes the first pass's per-tile counts (the tiles of a chunk, in the
-// keys' input order), so that pass needs no counting launch of its own.
-__global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
+// Digit counts of every pass over all keys: each workgroup of THREADS threads
+// counts a chunk of 16 THREADS keys in LDS (16 consecutive keys per thread,
+// equal digits of a run counted once) and adds its non-zero counts to the
+// global table.  It also writes the first pass's per-tile counts (the tiles
+// of a chunk, in the keys' input order), so that pass needs no counting
+// launch of its own.
+template <int THREADS>
+__global__ void __launch_bounds__(THREADS) k_radix_hist(Scene s)
 {
+    constexpr int kHistChunk = 16 * THREADS;
     constexpr int kMaxChunkTiles = kHistChunk / (kBlock * 4);
     __shared__ uint32_t h[kMaxRadixPasses * kRadixBins];
     __shared__ uint32_t ht[kMaxChunkTiles * kRadixBins];
     const int P = s.radix_passes;
     const int tile_keys = kBlock * (int)s.radix_items;
     const int chunk_tiles = kHistChunk / tile_keys;
-    for (int t = threadIdx.x; t < P * kRadixBins; t += 1024) h[t] = 0u;
-    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += 1024) ht[t] = 0u;
+    for (int t = threadIdx.x; t < P * kRadixBins; t += THREADS) h[t] = 0u;
+    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += THREADS) ht[t] = 0u;
     __syncthreads();
     const size_t n = (size_t)s.n_sort;
     const size_t i0 = (size_t)blockIdx.x * kHistChunk + 16 * (size_t)threadIdx.x;
@@ -224,11 +227,11 @@ __global__ void __launch_bounds__(1024) k_radix_hist(Scene s)
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < P * kRadixBins; t += 1024)
+    for (int t = threadIdx.x; t < P * kRadixBins; t += THREADS)
         if (h[t]) atomicAdd(&s.hist[t], h[t]);
     // the chunk's tiles: [digit][tile] like k_radix_count
     const uint32_t T = s.n_radix_tiles;
-    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += 1024) {
+    for (int t = threadIdx.x; t < chunk_tiles * kRadixBins; t += THREADS) {
         const uint32_t tile = (uint32_t)blockIdx.x * (uint32_t)chunk_tiles + (uint32_t)(t / kRadixBins);
         if (tile < T) s.tile_off[(size_t)(t % kRadixBins) * T + tile] = ht[t];
     }
@@ -1833,7 +1836,9 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
     const unsigned nb_nbr = multi ? blocks_for((size_t)s.n_active) : nb;
     const size_t pred_items = (size_t)(kMaxRadixPasses * kRadixBins);
     const unsigned nb_pred = blocks_for(extent > pred_items ? extent : pred_items);
-    const unsigned nb_hist = (unsigned)(((size_t)s.n_sort + kHistChunk - 1) / kHistChunk);
+    const int hist_threads = radix_hist_threads_for((size_t)s.n_sort);
+    const size_t hist_chunk = 16 * (size_t)hist_threads;
+    const unsigned nb_hist = (unsigned)(((size_t)s.n_sort + hist_chunk - 1) / hist_chunk);
     const int last = iterations % 2;      // buffer holding X_K - X_init and V_K
     for (int sub = 0; sub < count; ++sub) {
         if (multi)
@@ -1842,7 +1847,10 @@ hipError_t enqueue_substeps(const Scene& s, const StepConsts& c, int iterations,
             hipLaunchKernelGGL(k_predict_keys<false>, dim3(nb_pred), dim3(kBlock), 0, stream, s, c,
                                sub == 0 ? -1 : last);
         // (key, id) sorted by key, stable: digit counts, then one pass per digit
-        hipLaunchKernelGGL(k_radix_hist, dim3(nb_hist), dim3(1024), 0, stream, s);
+        if (hist_threads == 1024)
+            hipLaunchKernelGGL(k_radix_hist<1024>, dim3(nb_hist), dim3(1024), 0, stream, s);
+        else
+            hipLaunchKernelGGL(k_radix_hist<256>, dim3(nb_hist), dim3(256), 0, stream, s);
         for (int p = 0; p < s.radix_passes; ++p) {
             const uint32_t* kin = p == 0 ? s.key : s.kbuf[(p - 1) & 1];
             const uint32_t* iin = p == 0 ? nullptr : s.ibuf[(p - 1) & 1];
